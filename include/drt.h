@@ -1,0 +1,158 @@
+/*
+ * drt.h -- C ABI of the MI355X (gfx950) smoothed differentiable ray tracer.
+ *
+ * Method: arXiv 2401.11882 (Eertmans, Jacques, Oestges), "Fully Differentiable
+ * Ray Tracing via Discontinuity Smoothing for Radio Network Optimization".
+ *
+ * What one call computes, for every receiver r and every path candidate
+ * sigma = (sigma_1..sigma_k), 0 <= k <= max_order, an ordered list of walls
+ * with no wall repeated back to back (Sec. IV, "exhaustive list of path
+ * candidates" from a full visibility matrix):
+ *   1. the image method in the relaxed scene of infinite wall lines
+ *      (Sec. IV and Sec. IV-B): images I_0 = tx, I_i = mirror of I_{i-1}
+ *      across the line of sigma_i; back-trace X_{k+1} = r, X_i = a + t_i e
+ *      = X_{i+1} + u_i (I_i - X_{i+1});
+ *   2. the continuous validity of Sec. IV-A, with every comparison
+ *      x0 > x1 replaced by s(x0 - x1; alpha), s = sigmoid(alpha x)
+ *      (Eq. 3, Eq. 4), AND as a product and NOT as 1 - s:
+ *        V = prod_i in(t_i) in(u_i) * prod_{legs l} prod_{walls j not at
+ *            the leg's ends} (1 - in(tau_lj) in(upsilon_lj)),
+ *        in(x) = s(x) s(1 - x);
+ *   3. the received power of Eq. 7 with the dyadic coefficient set to the
+ *      identity, summed incoherently:
+ *        P(r) = sum_sigma V / max(|r - I_k|^2, d_min^2);
+ *   4. the loss L = -F of Sec. II, and its gradients with respect to the
+ *      transmitter, every wall endpoint and (optionally) every receiver, by
+ *      a hand-written adjoint (the paper obtains them by automatic
+ *      differentiation, Sec. I and Sec. II).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_dev are DEVICE pointers, owned by the caller; the
+ *     library never allocates, frees or retains them.  Pointers to drt_*
+ *     structs are HOST pointers read during the call only.
+ *   - Layouts: walls float32 [n_walls][4] = (ax, ay, bx, by); tx float32 [2];
+ *     rx float32 [n_rx][2]; grad_walls float32 [n_walls][4] in the same
+ *     order; power / grad_power float32 [n_rx].
+ *   - stream is a hipStream_t (NULL = the default stream).  Compute calls
+ *     only enqueue kernels on it: no allocation, no host synchronisation, no
+ *     memset nodes, so they may be captured into a HIP graph.
+ *   - Return value: DRT_OK (0) or a negative drt_status.  Argument checks run
+ *     on the host before anything is enqueued, so a failed call leaves all
+ *     outputs untouched; drt_last_error() then gives a message (thread-local).
+ *     No C++ exception crosses this interface and the library never aborts.
+ *   - Results are deterministic: every reduction has a fixed order, so two
+ *     identical calls give bitwise-identical outputs.
+ */
+#ifndef DRT_H
+#define DRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DRT_ABI_VERSION 1
+#define DRT_MAX_ORDER 3      /* LOS + up to three reflections */
+#define DRT_MAX_WALLS 1024
+
+typedef enum drt_status {
+  DRT_OK = 0,
+  DRT_EINVAL = -1,      /* bad argument: sizes, alpha, order, NULL pointer */
+  DRT_EWORKSPACE = -2,  /* workspace NULL or smaller than drt_workspace_size */
+  DRT_ENOTSUP = -3,     /* option not implemented */
+  DRT_EHIP = -4         /* a HIP runtime call failed */
+} drt_status;
+
+typedef enum drt_smoothing {
+  DRT_SIGMOID = 0       /* Eq. 4: 1 / (1 + exp(-alpha x)) */
+} drt_smoothing;
+
+typedef enum drt_loss {
+  DRT_LOSS_NONE = 0,               /* no loss, no seed */
+  DRT_LOSS_SUM_POWER = 1,          /* L = sum_r P(r) */
+  DRT_LOSS_NEG_MEAN_LOG_POWER = 2  /* L = -(1/R) sum_r log(P(r) + log_eps) */
+} drt_loss;
+
+/* One scene.  All array pointers are device pointers. */
+typedef struct drt_scene {
+  const float* walls_dev;  /* [n_walls][4]; the box walls are ordinary walls */
+  int32_t n_walls;         /* 0 .. DRT_MAX_WALLS (0 = free space, LOS only) */
+  const float* tx_dev;     /* [2] transmitter */
+  const float* rx_dev;     /* [n_rx][2] receivers */
+  int32_t n_rx;            /* >= 0 */
+  int32_t rx_grid_nx;      /* 0, or the row length when rx is a row-major
+                              grid (index j*nx + i) with nx % 8 == 0 and
+                              n_rx % (8*nx) == 0: then each wavefront takes an
+                              8x8 block of neighbouring receivers.  Only the
+                              work order changes, never the result. */
+  int32_t max_order;       /* K, 0 .. DRT_MAX_ORDER */
+  float alpha;             /* smoothing sharpness, finite and > 0 (Eq. 3) */
+  int32_t smoothing;       /* drt_smoothing */
+  float d_min;             /* distance floor, finite and > 0 (e.g. 1e-3) */
+} drt_scene;
+
+/* ABI version compiled into the library (DRT_ABI_VERSION). */
+int drt_abi_version(void);
+
+/* Static text for a drt_status value. */
+const char* drt_status_string(int status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* drt_last_error(void);
+
+/* Number of candidates 1 + sum_{k=1..K} W (W-1)^(k-1) (Sec. IV); host only.
+   Returns DRT_EINVAL for out-of-range arguments. */
+int drt_num_candidates(int32_t n_walls, int32_t max_order, int64_t* count);
+
+/* Launch-shape override for the tracer kernels (a tuning knob; results do
+   not depend on it beyond float summation order).  nw = wavefronts per
+   workgroup (0 = automatic, else 2, 4, 8 or 16); cchunk = consecutive
+   candidates handed to one wavefront (0 = automatic).  Process-wide. */
+int drt_set_launch_config(int32_t nw, int32_t cchunk);
+
+/* Workspace bytes that drt_forward / drt_backward / drt_forward_backward
+   need for this scene (depends on n_walls, n_rx and the launch shape).
+   Host only; reads no device memory. */
+int drt_workspace_size(const drt_scene* scene, size_t* bytes);
+
+/* Forward pass (steps 1-3 above, and 4's loss value).
+   power_dev   out [n_rx]      P(r).
+   loss_dev    out [1] or NULL L for loss_kind (ignored for DRT_LOSS_NONE).
+   seed_dev    out [n_rx] or NULL: dL/dP(r) for loss_kind.
+   log_eps     > 0, the floor inside the log (DRT_LOSS_NEG_MEAN_LOG_POWER).
+   ws_dev      workspace of at least drt_workspace_size bytes. */
+int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps,
+                float* power_dev, float* loss_dev, float* seed_dev,
+                void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Adjoint pass: given grad_power_dev = dL/dP(r) [n_rx], writes
+   grad_tx_dev [2], grad_walls_dev [n_walls][4] and, if not NULL,
+   grad_rx_dev [n_rx][2].  Outputs are overwritten, not accumulated. */
+int drt_backward(const drt_scene* scene, const float* grad_power_dev,
+                 float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,
+                 void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Forward, loss seed and adjoint in one call (loss_kind must not be NONE).
+   Any of grad_rx_dev / loss_dev may be NULL. */
+int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_eps,
+                         float* power_dev, float* loss_dev,
+                         float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,
+                         void* ws_dev, size_t ws_bytes, void* stream);
+
+/* One Adam step on the transmitter (torch's Adam with bias correction)
+   followed by clamping every coordinate to [lo, hi].
+   tx_dev [2] in/out; grad_dev [2] in; m_dev, v_dev [2] in/out (start at 0);
+   step_dev: int32 [1] in/out, the number of steps already taken (start at
+   0; incremented on the device so a captured graph can be replayed).
+   Needs lr > 0, 0 <= b1, b2 < 1, eps > 0, lo <= hi. */
+int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                int32_t* step_dev, float lr, float b1, float b2, float eps,
+                float lo, float hi, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRT_H */

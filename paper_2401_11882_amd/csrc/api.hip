@@ -1,0 +1,288 @@
+// C ABI of the tracer library: argument checks, workspace layout, launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/drt.h"
+#include "dev.h"
+#include "trace.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(DRT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Launch shape overrides (0 = automatic).
+int g_nw_override = 0;
+int g_cchunk_override = 0;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int64_t count_candidates(int64_t W, int K) {
+  int64_t total = 1, term = 0;
+  for (int k = 1; k <= K; ++k) {
+    term = (k == 1) ? W : term * (W - 1);
+    total += term;
+  }
+  return total;
+}
+
+struct Plan {
+  int n_tiles;
+  int nw;
+  int cchunk;
+  int ncol;  // 2 + 4 W
+  size_t off_walls, off_loss, off_seed, off_grad, total;
+};
+
+int pick_nw(int n_tiles, int n_walls) {
+  int nw = g_nw_override;
+  if (nw == 0) nw = n_tiles < 512 ? 16 : (n_tiles < 2048 ? 8 : 4);
+  while (nw > 2 && drt::backward_lds_bytes(nw, n_walls) > 48 * 1024) nw >>= 1;
+  return nw;
+}
+
+int check_scene(const drt_scene* s) {
+  if (!s) return fail(DRT_EINVAL, "scene is NULL");
+  if (s->n_walls < 0 || s->n_walls > DRT_MAX_WALLS)
+    return fail(DRT_EINVAL, "n_walls=%d outside [0, %d]", s->n_walls, DRT_MAX_WALLS);
+  if (s->n_walls > 0 && !s->walls_dev) return fail(DRT_EINVAL, "walls_dev is NULL");
+  if (!s->tx_dev) return fail(DRT_EINVAL, "tx_dev is NULL");
+  if (s->n_rx < 0) return fail(DRT_EINVAL, "n_rx=%d is negative", s->n_rx);
+  if (s->n_rx > 0 && !s->rx_dev) return fail(DRT_EINVAL, "rx_dev is NULL");
+  if (s->max_order < 0 || s->max_order > DRT_MAX_ORDER)
+    return fail(DRT_EINVAL, "max_order=%d outside [0, %d]", s->max_order, DRT_MAX_ORDER);
+  if (!std::isfinite(s->alpha) || !(s->alpha > 0.0f))
+    return fail(DRT_EINVAL, "alpha must be finite and > 0");
+  if (!std::isfinite(s->d_min) || !(s->d_min > 0.0f))
+    return fail(DRT_EINVAL, "d_min must be finite and > 0");
+  if (s->smoothing != DRT_SIGMOID) return fail(DRT_ENOTSUP, "smoothing=%d not supported", s->smoothing);
+  if (s->rx_grid_nx != 0) {
+    const int nx = s->rx_grid_nx;
+    if (nx < 0 || nx % 8 != 0 || s->n_rx % (8 * nx) != 0)
+      return fail(DRT_EINVAL, "rx_grid_nx=%d needs nx %% 8 == 0 and n_rx %% (8 nx) == 0", nx);
+  }
+  if (count_candidates(s->n_walls, s->max_order) > 0x7fffffffLL)
+    return fail(DRT_EINVAL, "candidate count exceeds 2^31-1");
+  return DRT_OK;
+}
+
+Plan make_plan(const drt_scene* s) {
+  Plan p{};
+  p.n_tiles = (s->n_rx + drt::kWave - 1) / drt::kWave;
+  p.nw = pick_nw(p.n_tiles, s->n_walls);
+  p.cchunk = g_cchunk_override > 0 ? g_cchunk_override : 1;
+  p.ncol = 2 + 4 * s->n_walls;
+  size_t off = 0;
+  p.off_walls = off;
+  off = align_up(off + sizeof(drt::WallRec) * (size_t)(s->n_walls > 0 ? s->n_walls : 1));
+  p.off_loss = off;
+  off = align_up(off + sizeof(float) * (size_t)(p.n_tiles > 0 ? p.n_tiles : 1));
+  p.off_seed = off;
+  off = align_up(off + sizeof(float) * (size_t)(s->n_rx > 0 ? s->n_rx : 1));
+  p.off_grad = off;
+  off = align_up(off + sizeof(float) * (size_t)p.ncol * (size_t)(p.n_tiles > 0 ? p.n_tiles : 1));
+  p.total = off;
+  return p;
+}
+
+drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
+  drt::TraceArgs A{};
+  A.walls = reinterpret_cast<const drt::WallRec*>(static_cast<char*>(ws) + p.off_walls);
+  A.tx = s->tx_dev;
+  A.rx = s->rx_dev;
+  A.n_walls = s->n_walls;
+  A.n_rx = s->n_rx;
+  A.grid_nx = s->rx_grid_nx;
+  A.n_cand = (int)count_candidates(s->n_walls, s->max_order);
+  A.cchunk = p.cchunk;
+  A.alpha = s->alpha;
+  A.a2 = s->alpha * drt::kLog2e;
+  A.band_k = 1.0f + 2.0f * 18.0f / s->alpha;
+  A.dmin2 = s->d_min * s->d_min;
+  return A;
+}
+
+int check_ws(const Plan& p, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(DRT_EWORKSPACE, "workspace is NULL");
+  if (ws_bytes < p.total)
+    return fail(DRT_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, p.total);
+  if (reinterpret_cast<uintptr_t>(ws) % 16 != 0) return fail(DRT_EWORKSPACE, "workspace not 16-byte aligned");
+  return DRT_OK;
+}
+
+int check_loss(int32_t loss_kind, float log_eps) {
+  if (loss_kind < DRT_LOSS_NONE || loss_kind > DRT_LOSS_NEG_MEAN_LOG_POWER)
+    return fail(DRT_EINVAL, "loss_kind=%d unknown", loss_kind);
+  if (loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER && (!std::isfinite(log_eps) || !(log_eps > 0.0f)))
+    return fail(DRT_EINVAL, "log_eps must be finite and > 0");
+  return DRT_OK;
+}
+
+// Enqueue: prep walls, forward (power, seed, per-tile loss partials), loss.
+int enqueue_forward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, int32_t loss_kind,
+                    float log_eps, float* power, float* loss, float* seed, void* ws, hipStream_t st) {
+  char* w = static_cast<char*>(ws);
+  hipError_t e = drt::launch_prep_walls(s->walls_dev, s->n_walls,
+                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls), st);
+  if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
+  float* loss_part = reinterpret_cast<float*>(w + p.off_loss);
+  if (p.n_tiles > 0) {
+    e = drt::launch_forward(A, p.n_tiles, p.nw, power, seed, loss_part, loss_kind, log_eps, st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+  }
+  if (loss_kind != DRT_LOSS_NONE && loss) {
+    const double scale = loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER
+                             ? (s->n_rx > 0 ? -1.0 / (double)s->n_rx : 0.0)
+                             : 1.0;
+    e = drt::launch_reduce_scalar(loss_part, p.n_tiles, scale, loss, st);
+    if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
+  }
+  return DRT_OK;
+}
+
+int enqueue_backward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, const float* gP,
+                     float* gtx, float* gwalls, float* grx, void* ws, hipStream_t st) {
+  char* w = static_cast<char*>(ws);
+  float* part = reinterpret_cast<float*>(w + p.off_grad);
+  hipError_t e;
+  if (p.n_tiles > 0) {
+    e = drt::launch_backward(A, p.n_tiles, p.nw, gP, part, grx, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+  }
+  e = drt::launch_reduce_cols(part, p.n_tiles, p.ncol, gtx, 2, gwalls, st);
+  if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+  return DRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int drt_abi_version(void) { return DRT_ABI_VERSION; }
+
+const char* drt_status_string(int status) {
+  switch (status) {
+    case DRT_OK: return "ok";
+    case DRT_EINVAL: return "invalid argument";
+    case DRT_EWORKSPACE: return "workspace missing or too small";
+    case DRT_ENOTSUP: return "not supported";
+    case DRT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* drt_last_error(void) { return g_err.c_str(); }
+
+int drt_set_launch_config(int32_t nw, int32_t cchunk) {
+  if (!(nw == 0 || nw == 2 || nw == 4 || nw == 8 || nw == 16))
+    return fail(DRT_EINVAL, "nw=%d must be 0, 2, 4, 8 or 16", nw);
+  if (cchunk < 0) return fail(DRT_EINVAL, "cchunk=%d is negative", cchunk);
+  g_nw_override = nw;
+  g_cchunk_override = cchunk;
+  return DRT_OK;
+}
+
+int drt_num_candidates(int32_t n_walls, int32_t max_order, int64_t* count) {
+  if (!count) return fail(DRT_EINVAL, "count is NULL");
+  if (n_walls < 0 || n_walls > DRT_MAX_WALLS || max_order < 0 || max_order > DRT_MAX_ORDER)
+    return fail(DRT_EINVAL, "n_walls=%d / max_order=%d out of range", n_walls, max_order);
+  *count = count_candidates(n_walls, max_order);
+  return DRT_OK;
+}
+
+int drt_workspace_size(const drt_scene* scene, size_t* bytes) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if (!bytes) return fail(DRT_EINVAL, "bytes is NULL");
+  *bytes = make_plan(scene).total;
+  return DRT_OK;
+}
+
+int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
+                float* loss_dev, float* seed_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if ((rc = check_loss(loss_kind, log_eps))) return rc;
+  if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
+  if (seed_dev && loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "seed_dev needs a loss_kind");
+  const Plan p = make_plan(scene);
+  if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
+  const drt::TraceArgs A = make_args(scene, p, ws_dev);
+  return enqueue_forward(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed_dev, ws_dev,
+                         static_cast<hipStream_t>(stream));
+}
+
+int drt_backward(const drt_scene* scene, const float* grad_power_dev, float* grad_tx_dev,
+                 float* grad_walls_dev, float* grad_rx_dev, void* ws_dev, size_t ws_bytes,
+                 void* stream) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if (scene->n_rx > 0 && !grad_power_dev) return fail(DRT_EINVAL, "grad_power_dev is NULL");
+  if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
+  if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
+  const Plan p = make_plan(scene);
+  if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
+  const drt::TraceArgs A = make_args(scene, p, ws_dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws_dev);
+  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls,
+                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls), st);
+  if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
+  return enqueue_backward(scene, p, A, grad_power_dev, grad_tx_dev, grad_walls_dev, grad_rx_dev,
+                          ws_dev, st);
+}
+
+int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
+                         float* loss_dev, float* grad_tx_dev, float* grad_walls_dev,
+                         float* grad_rx_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if ((rc = check_loss(loss_kind, log_eps))) return rc;
+  if (loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "forward_backward needs a loss_kind");
+  if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
+  if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
+  if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
+  const Plan p = make_plan(scene);
+  if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
+  const drt::TraceArgs A = make_args(scene, p, ws_dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* seed = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + p.off_seed);
+  rc = enqueue_forward(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed, ws_dev, st);
+  if (rc) return rc;
+  return enqueue_backward(scene, p, A, seed, grad_tx_dev, grad_walls_dev, grad_rx_dev, ws_dev, st);
+}
+
+int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev, int32_t* step_dev,
+                float lr, float b1, float b2, float eps, float lo, float hi, void* stream) {
+  if (!tx_dev || !grad_dev || !m_dev || !v_dev || !step_dev)
+    return fail(DRT_EINVAL, "NULL pointer argument");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(DRT_EINVAL, "lr must be finite and > 0");
+  if (!(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f))
+    return fail(DRT_EINVAL, "betas must lie in [0, 1)");
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(DRT_EINVAL, "eps must be finite and > 0");
+  if (!(lo <= hi)) return fail(DRT_EINVAL, "lo > hi");
+  hipError_t e = drt::launch_adam_tx(tx_dev, grad_dev, m_dev, v_dev, step_dev, lr, b1, b2, eps, lo, hi,
+                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return DRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Internal interface between the C ABI (api.hip) and the tracer kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace drt {
+
+struct WallRec;
+
+struct TraceArgs {
+  const WallRec* walls;  // prepared wall records [n_walls]
+  const float* tx;       // [2]
+  const float* rx;       // [n_rx][2]
+  int n_walls;
+  int n_rx;
+  int grid_nx;           // 0 = consecutive receivers per wavefront
+  int n_cand;
+  int cchunk;            // candidates per chunk handed to one wavefront
+  float alpha;
+  float a2;              // alpha * log2(e)
+  float band_k;          // 1 + 2 * 18 / alpha: unsaturated-test band
+  float dmin2;
+};
+
+hipError_t launch_prep_walls(const float* walls, int n, WallRec* out, hipStream_t st);
+hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power, float* seed,
+                          float* loss_part, int loss_kind, float log_eps, hipStream_t st);
+hipError_t launch_backward(const TraceArgs& A, int n_tiles, int nw, const float* gP, float* part,
+                           float* grad_rx, hipStream_t st);
+size_t backward_lds_bytes(int nw, int n_walls);
+hipError_t launch_reduce_cols(const float* part, int n_rows, int ncol, float* out_head, int n_head,
+                              float* out_tail, hipStream_t st);
+hipError_t launch_reduce_scalar(const float* part, int n, double scale, float* out, hipStream_t st);
+hipError_t launch_adam_tx(float* tx, const float* grad, float* m, float* v, int32_t* step, float lr,
+                          float b1, float b2, float eps, float lo, float hi, hipStream_t st);
+
+}  // namespace drt

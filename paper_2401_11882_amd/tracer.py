@@ -1,0 +1,184 @@
+"""PyTorch-facing binding of the HIP tracer (argument marshalling only).
+
+Every number is computed by the kernels in libdrt.so; this module checks
+tensor types/devices, keeps one workspace per device and passes raw device
+pointers and the current HIP stream through the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import DrtScene, check, lib
+
+DEFAULT_DMIN = 1e-3
+DEFAULT_LOG_EPS = 1e-6
+
+
+def _dev_f32(x: torch.Tensor, name: str, shape_tail=None) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device, got {x.device}")
+    if x.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(x.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected [*, {', '.join(map(str, shape_tail))}]")
+    return x
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None else ctypes.c_void_p(0)
+
+
+def stream_handle(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Scene:
+    """Device-resident scene description (walls [W,4], tx [2], rx [R,2])."""
+
+    def __init__(self, walls, tx, rx, max_order: int, alpha: float, d_min: float = DEFAULT_DMIN,
+                 grid_nx: int = 0):
+        self.walls = _dev_f32(walls, "walls", (4,)) if walls.numel() else walls
+        self.tx = _dev_f32(tx, "tx")
+        if self.tx.numel() != 2:
+            raise ValueError("tx must hold 2 floats")
+        self.rx = _dev_f32(rx, "rx", (2,))
+        dev = self.tx.device
+        for t, nm in ((self.walls, "walls"), (self.rx, "rx")):
+            if t.numel() and t.device != dev:
+                raise ValueError(f"{nm} is on {t.device}, tx on {dev}")
+        self.max_order = int(max_order)
+        self.alpha = float(alpha)
+        self.d_min = float(d_min)
+        self.grid_nx = int(grid_nx)
+        self.device = dev
+
+    @property
+    def n_walls(self):
+        return int(self.walls.shape[0]) if self.walls.numel() else 0
+
+    @property
+    def n_rx(self):
+        return int(self.rx.shape[0])
+
+    def c_struct(self) -> DrtScene:
+        return DrtScene(
+            walls_dev=self.walls.data_ptr() if self.n_walls else None, n_walls=self.n_walls,
+            tx_dev=self.tx.data_ptr(),
+            rx_dev=self.rx.data_ptr() if self.n_rx else None, n_rx=self.n_rx, rx_grid_nx=self.grid_nx,
+            max_order=self.max_order, alpha=self.alpha, smoothing=_lib.DRT_SIGMOID, d_min=self.d_min)
+
+
+_WS: dict = {}
+
+
+def workspace(sc: DrtScene, device) -> tuple[torch.Tensor, int]:
+    n = ctypes.c_size_t(0)
+    check(lib().drt_workspace_size(ctypes.byref(sc), ctypes.byref(n)))
+    key = (str(device),)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < n.value:
+        buf = torch.empty(max(n.value, 256), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf, int(n.value)
+
+
+def num_candidates(n_walls: int, max_order: int) -> int:
+    c = ctypes.c_int64(0)
+    check(lib().drt_num_candidates(int(n_walls), int(max_order), ctypes.byref(c)))
+    return int(c.value)
+
+
+def set_launch_config(nw: int = 0, cchunk: int = 0) -> None:
+    check(lib().drt_set_launch_config(int(nw), int(cchunk)))
+
+
+def forward(scene: Scene, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS,
+            want_seed: bool = False, stream=None):
+    """P(r) [R]; plus the loss scalar (and dL/dP) when loss != 'none'."""
+    sc = scene.c_struct()
+    ws, nbytes = workspace(sc, scene.device)
+    P = torch.empty(scene.n_rx, dtype=torch.float32, device=scene.device)
+    L = torch.empty(1, dtype=torch.float32, device=scene.device) if loss != "none" else None
+    seed = torch.empty_like(P) if (want_seed and loss != "none") else None
+    check(lib().drt_forward(ctypes.byref(sc), _lib.LOSS[loss], float(log_eps), _ptr(P), _ptr(L),
+                            _ptr(seed), _ptr(ws), nbytes, stream_handle(stream)))
+    return P, L, seed
+
+
+def backward(scene: Scene, grad_power: torch.Tensor, want_rx: bool = False, stream=None):
+    """(dL/dtx [2], dL/dwalls [W,4], dL/drx [R,2] or None) for a given dL/dP."""
+    _dev_f32(grad_power, "grad_power")
+    if grad_power.numel() != scene.n_rx:
+        raise ValueError("grad_power must have one entry per receiver")
+    sc = scene.c_struct()
+    ws, nbytes = workspace(sc, scene.device)
+    gtx = torch.empty(2, dtype=torch.float32, device=scene.device)
+    gw = torch.empty(scene.n_walls, 4, dtype=torch.float32, device=scene.device)
+    grx = torch.empty(scene.n_rx, 2, dtype=torch.float32, device=scene.device) if want_rx else None
+    check(lib().drt_backward(ctypes.byref(sc), _ptr(grad_power), _ptr(gtx), _ptr(gw if scene.n_walls else None),
+                             _ptr(grx), _ptr(ws), nbytes, stream_handle(stream)))
+    return gtx, gw, grx
+
+
+def forward_backward(scene: Scene, loss: str = "neg_mean_log", log_eps: float = DEFAULT_LOG_EPS,
+                     want_rx: bool = False, out=None, stream=None):
+    """Power map, loss, and its gradients in one call.
+
+    ``out`` may hold preallocated tensors (P, L, gtx, gw, grx) to reuse, e.g.
+    inside a captured HIP graph.
+    """
+    if loss == "none":
+        raise ValueError("forward_backward needs a loss")
+    sc = scene.c_struct()
+    ws, nbytes = workspace(sc, scene.device)
+    if out is None:
+        dev = scene.device
+        out = (torch.empty(scene.n_rx, dtype=torch.float32, device=dev),
+               torch.empty(1, dtype=torch.float32, device=dev),
+               torch.empty(2, dtype=torch.float32, device=dev),
+               torch.empty(scene.n_walls, 4, dtype=torch.float32, device=dev),
+               torch.empty(scene.n_rx, 2, dtype=torch.float32, device=dev) if want_rx else None)
+    P, L, gtx, gw, grx = out
+    check(lib().drt_forward_backward(ctypes.byref(sc), _lib.LOSS[loss], float(log_eps), _ptr(P), _ptr(L),
+                                     _ptr(gtx), _ptr(gw if scene.n_walls else None), _ptr(grx),
+                                     _ptr(ws), nbytes, stream_handle(stream)))
+    return out
+
+
+def adam_tx(tx, grad, m, v, step, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8, lo=1e-3, hi=1.0 - 1e-3,
+            stream=None) -> None:
+    for t, nm in ((tx, "tx"), (grad, "grad"), (m, "m"), (v, "v")):
+        _dev_f32(t, nm)
+    if step.dtype != torch.int32 or step.device.type != "cuda":
+        raise ValueError("step must be an int32 GPU tensor")
+    check(lib().drt_adam_tx(_ptr(tx), _ptr(grad), _ptr(m), _ptr(v), _ptr(step), lr, b1, b2, eps, lo, hi,
+                            stream_handle(stream)))
+
+
+class SmoothedPower(torch.autograd.Function):
+    """P(r) as a differentiable function of (walls, tx, rx); adjoint in HIP."""
+
+    @staticmethod
+    def forward(ctx, walls, tx, rx, max_order, alpha, d_min=DEFAULT_DMIN, grid_nx=0):
+        scene = Scene(walls.detach(), tx.detach(), rx.detach(), max_order, alpha, d_min, grid_nx)
+        P, _, _ = forward(scene)
+        ctx.scene = scene
+        ctx.need_rx = rx.requires_grad
+        return P
+
+    @staticmethod
+    def backward(ctx, gP):
+        gtx, gw, grx = backward(ctx.scene, gP.contiguous().float(), want_rx=ctx.need_rx)
+        return gw, gtx, grx, None, None, None, None
+
+
+def smoothed_power(walls, tx, rx, max_order, alpha, d_min=DEFAULT_DMIN, grid_nx=0):
+    return SmoothedPower.apply(walls, tx, rx, max_order, alpha, d_min, grid_nx)

@@ -14,3 +14,14 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def pytest_collection_modifyitems(config, items):
+    gpu_ok = None
+    for item in items:
+        if "gpu" in item.keywords:
+            if gpu_ok is None:
+                import torch
+                gpu_ok = torch.cuda.is_available()
+            if not gpu_ok:
+                item.add_marker(pytest.mark.skip(reason="no GPU visible"))

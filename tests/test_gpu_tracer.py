@@ -1,0 +1,271 @@
+"""Parity of the HIP tracer (through the C ABI) with the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tracer as T
+from paper_2401_11882_amd import workloads as WL
+
+import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+
+def _tr():
+    from paper_2401_11882_amd import tracer
+    return tracer
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _scene(s, alpha=None, grid=True, rx=None):
+    tr = _tr()
+    rx_np = s.rx if rx is None else rx
+    return tr.Scene(_dev(s.walls), _dev(s.tx), _dev(rx_np), s.max_order,
+                    s.alpha if alpha is None else alpha, grid_nx=(s.grid_n if (grid and rx is None) else 0))
+
+
+def _sample_idx(R, n, seed=0):
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(R, size=n - 2, replace=False)
+    return np.unique(np.concatenate([idx, [0, R - 1]]))
+
+
+# ------------------------------------------------------------- small scene, full
+
+def test_single_segment_forward_full():
+    s = WL.scene_single_segment()
+    sc = _scene(s)
+    P, _, _ = _tr().forward(sc)
+    P0, kap = PU.kappa(s.walls, s.tx, s.rx, 1, s.alpha)
+    st = PU.check_power(P.cpu().numpy(), P0, kap, "single segment")
+    print("single segment forward", st)
+
+
+def test_single_segment_forward_backward_full():
+    s = WL.scene_single_segment()
+    sc = _scene(s)
+    P, L, gtx, gw, grx = _tr().forward_backward(sc, loss="neg_mean_log", want_rx=True)
+    P_o, L_o, gw_o, gt_o, grx_o = T.forward_backward(s.walls, s.tx, s.rx, 1, s.alpha)
+    _, kap = PU.kappa(s.walls, s.tx, s.rx, 1, s.alpha, P0=P_o)
+    PU.check_power(P.cpu().numpy(), P_o, kap, "single segment fb")
+    assert float(L) == pytest.approx(L_o, rel=1e-5)
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, "single segment")
+    assert PU.rel_l2(grx.cpu().numpy(), grx_o) < 1e-3
+
+
+@pytest.mark.parametrize("K", [0, 1, 2, 3])
+def test_small_scene_all_orders(K):
+    s = WL.scene_random_box(2, 6, 8, K, 100.0, seed=21)
+    sc = _scene(s)
+    P, L, gtx, gw, grx = _tr().forward_backward(sc, loss="neg_mean_log", want_rx=True)
+    P_o, L_o, gw_o, gt_o, grx_o = T.forward_backward(s.walls, s.tx, s.rx, K, 100.0)
+    _, kap = PU.kappa(s.walls, s.tx, s.rx, K, 100.0, P0=P_o)
+    PU.check_power(P.cpu().numpy(), P_o, kap, f"K={K}")
+    assert float(L) == pytest.approx(L_o, rel=1e-5)
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, f"K={K}")
+    assert PU.rel_l2(grx.cpu().numpy(), grx_o) < 1e-3
+
+
+@pytest.mark.parametrize("alpha", [10.0, 100.0, 1000.0])
+def test_medium_scene_fused_full(alpha):
+    """Box + 20 segments, 16x16 receivers, order <= 2: every output vs the oracle."""
+    s = WL.scene_random_box(2, 20, 16, 2, alpha, seed=5)
+    sc = _scene(s)
+    P, L, gtx, gw, _ = _tr().forward_backward(sc, loss="neg_mean_log")
+    P_o, L_o, gw_o, gt_o, _ = T.forward_backward(s.walls, s.tx, s.rx, 2, alpha)
+    _, kap = PU.kappa(s.walls, s.tx, s.rx, 2, alpha, P0=P_o)
+    st = PU.check_power(P.cpu().numpy(), P_o, kap, f"medium alpha={alpha}")
+    print("medium", alpha, st)
+    assert float(L) == pytest.approx(L_o, rel=1e-5)
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, f"medium alpha={alpha}")
+
+
+# ------------------------------------------------------------- 64-segment scene, full size
+
+@pytest.mark.parametrize("alpha", [10.0, 100.0, 1000.0])
+def test_scene64_full_size_sampled(alpha):
+    """Box + 64 segments, 256x256 receivers, order <= 2, in the benchmark's launch.
+
+    Power on sampled receivers vs the oracle; gradients with dL/dP masked to
+    those receivers (seed values from the oracle's own power)."""
+    s = WL.scene_64(alpha=alpha)
+    sc = _scene(s)
+    P, L, seed = _tr().forward(sc, loss="neg_mean_log", want_seed=True)
+    Pg = P.cpu().numpy()
+    idx = _sample_idx(s.n_rx, 40, seed=int(alpha))
+    P_o, kap = PU.kappa(s.walls, s.tx, s.rx[idx], 2, alpha)
+    st = PU.check_power(Pg[idx], P_o, kap, f"scene64 alpha={alpha}")
+    print("scene64", alpha, st)
+    # loss reduction consistent with the returned power map
+    L_host = -np.mean(np.log(Pg.astype(np.float64) + 1e-6))
+    assert float(L) == pytest.approx(L_host, rel=1e-5)
+    # seed = dL/dP
+    np.testing.assert_allclose(seed.cpu().numpy(), -1.0 / (s.n_rx * (Pg.astype(np.float64) + 1e-6)), rtol=1e-5)
+    # gradients through a masked seed
+    gsub = idx[:24]
+    g = np.zeros(s.n_rx)
+    g[gsub] = T.loss_seed(P_o[:24], "neg_mean_log") * 24 / s.n_rx
+    gtx, gw, _ = _tr().backward(sc, _dev(g))
+    gw_o, gt_o, _ = T.vjp(s.walls, s.tx, s.rx[gsub], 2, alpha, g[gsub])
+    e = PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, f"scene64 alpha={alpha}")
+    print("scene64 grads", alpha, e)
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_free_space_closed_form():
+    tr = _tr()
+    rx = WL.rx_grid(16)
+    tx = np.array([0.31, 0.47], np.float32)
+    for K in (0, 3):
+        sc = tr.Scene(torch.zeros(0, 4, device="cuda"), _dev(tx), _dev(rx), K, 100.0, grid_nx=16)
+        P, _, _ = tr.forward(sc)
+        d2 = ((rx.astype(np.float64) - tx.astype(np.float64)) ** 2).sum(1)
+        np.testing.assert_allclose(P.cpu().numpy(), 1.0 / np.maximum(d2, 1e-6), rtol=2e-6)
+
+
+def test_tx_on_receiver_uses_floor():
+    s = WL.scene_single_segment()
+    tx = s.rx[100].copy()
+    tr = _tr()
+    sc = tr.Scene(_dev(s.walls), _dev(tx), _dev(s.rx), 1, 100.0, grid_nx=32)
+    P, _, _ = tr.forward(sc)
+    P_o = T.power(s.walls, tx, s.rx[[100, 101]], 1, 100.0)
+    np.testing.assert_allclose(P.cpu().numpy()[[100, 101]], P_o, rtol=1e-4)
+
+
+def test_empty_and_ragged_receivers():
+    tr = _tr()
+    s = WL.scene_random_box(2, 5, 4, 2, 100.0, seed=2)
+    sc = tr.Scene(_dev(s.walls), _dev(s.tx), torch.zeros(0, 2, device="cuda"), 2, 100.0)
+    P, L, _ = tr.forward(sc, loss="sum")
+    assert P.numel() == 0 and float(L) == 0.0
+    gtx, gw, _ = tr.backward(sc, torch.zeros(0, device="cuda"))
+    assert torch.all(gtx == 0) and torch.all(gw == 0)
+    rx = WL.random_points(2, 7, 100)
+    sc = tr.Scene(_dev(s.walls), _dev(s.tx), _dev(rx), 2, 100.0)
+    P, L, gtx, gw, grx = tr.forward_backward(sc, loss="sum", want_rx=True)
+    P_o, L_o, gw_o, gt_o, grx_o = T.forward_backward(s.walls, s.tx, rx, 2, 100.0, kind="sum")
+    _, kap = PU.kappa(s.walls, s.tx, rx, 2, 100.0, P0=P_o)
+    PU.check_power(P.cpu().numpy(), P_o, kap, "ragged")
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, "ragged")
+    assert PU.rel_l2(grx.cpu().numpy(), grx_o) < 1e-3
+
+
+def test_zero_length_wall():
+    tr = _tr()
+    walls = np.concatenate([WL.BOX_WALLS, [[0.5, 0.5, 0.5, 0.5], [0.2, 0.3, 0.6, 0.35]]]).astype(np.float32)
+    rx = WL.rx_grid(8)
+    tx = np.array([0.7, 0.8], np.float32)
+    sc = tr.Scene(_dev(walls), _dev(tx), _dev(rx), 2, 100.0, grid_nx=8)
+    P, L, gtx, gw, _ = tr.forward_backward(sc, loss="neg_mean_log")
+    assert torch.isfinite(P).all() and torch.isfinite(gw).all() and torch.isfinite(gtx).all()
+    P_o = T.power(walls, tx, rx, 2, 100.0)
+    _, kap = PU.kappa(walls, tx, rx, 2, 100.0, P0=P_o)
+    PU.check_power(P.cpu().numpy(), P_o, kap, "zero-length wall")
+
+
+def test_grid_and_linear_mapping_agree_bitwise():
+    tr = _tr()
+    s = WL.scene_random_box(2, 12, 32, 2, 100.0, seed=9)
+    Pa, _, _ = tr.forward(_scene(s, grid=True))
+    Pb, _, _ = tr.forward(_scene(s, grid=False))
+    assert torch.equal(Pa, Pb)
+
+
+def test_deterministic_repeat():
+    tr = _tr()
+    s = WL.scene_random_box(2, 16, 32, 2, 100.0, seed=4)
+    sc = _scene(s)
+    a = [t.clone() for t in tr.forward_backward(sc, loss="neg_mean_log", want_rx=True)]
+    b = [t.clone() for t in tr.forward_backward(sc, loss="neg_mean_log", want_rx=True)]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+# ------------------------------------------------------------- autograd + Adam + graphs
+
+def test_autograd_function():
+    tr = _tr()
+    s = WL.scene_random_box(2, 6, 8, 2, 100.0, seed=13)
+    walls = _dev(s.walls).requires_grad_(True)
+    tx = _dev(s.tx).requires_grad_(True)
+    rx = _dev(s.rx).requires_grad_(True)
+    P = tr.smoothed_power(walls, tx, rx, 2, 100.0)
+    loss = -torch.log(P + 1e-6).mean()
+    loss.backward()
+    _, _, gw_o, gt_o, grx_o = T.forward_backward(s.walls, s.tx, s.rx, 2, 100.0)
+    PU.check_grads(tx.grad.cpu().numpy(), walls.grad.cpu().numpy(), gt_o, gw_o, "autograd")
+    assert PU.rel_l2(rx.grad.cpu().numpy(), grx_o) < 1e-3
+
+
+def test_adam_matches_torch():
+    tr = _tr()
+    x = torch.tensor([0.2, 0.9], device="cuda")
+    m = torch.zeros(2, device="cuda")
+    v = torch.zeros(2, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    xr = torch.tensor([0.2, 0.9], dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([xr], lr=1e-2)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        g = rng.standard_normal(2)
+        tr.adam_tx(x, torch.tensor(g, dtype=torch.float32, device="cuda"), m, v, step, lr=1e-2)
+        opt.zero_grad()
+        xr.grad = torch.tensor(g)
+        opt.step()
+        with torch.no_grad():
+            xr.clamp_(1e-3, 1 - 1e-3)
+    np.testing.assert_allclose(x.cpu().numpy(), xr.detach().numpy(), rtol=1e-5, atol=1e-6)
+    assert int(step) == 20
+
+
+def test_graph_capture_replay_matches_eager():
+    """forward_backward + Adam captured once, replayed; every replay equals eager."""
+    tr = _tr()
+    s = WL.scene_random_box(2, 10, 16, 2, 100.0, seed=3)
+    walls = _dev(s.walls)
+    tx0 = _dev(s.tx)
+    rx = _dev(s.rx)
+
+    def run_eager(n):
+        tx = tx0.clone()
+        m = torch.zeros(2, device="cuda"); v = torch.zeros(2, device="cuda")
+        step = torch.zeros(1, dtype=torch.int32, device="cuda")
+        sc = tr.Scene(walls, tx, rx, 2, 100.0, grid_nx=16)
+        hist = []
+        for _ in range(n):
+            P, L, gtx, gw, _ = tr.forward_backward(sc, loss="neg_mean_log")
+            tr.adam_tx(tx, gtx, m, v, step)
+            hist.append((L.clone(), tx.clone()))
+        return hist
+
+    eager = run_eager(4)
+    tx = tx0.clone()
+    m = torch.zeros(2, device="cuda"); v = torch.zeros(2, device="cuda")
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sc = tr.Scene(walls, tx, rx, 2, 100.0, grid_nx=16)
+    out = (torch.empty(s.n_rx, device="cuda"), torch.empty(1, device="cuda"), torch.empty(2, device="cuda"),
+           torch.empty(s.n_walls, 4, device="cuda"), None)
+    # warm the workspace outside capture
+    tr.forward_backward(sc, loss="neg_mean_log", out=out)
+    tx.copy_(tx0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            tr.forward_backward(sc, loss="neg_mean_log", out=out)
+            tr.adam_tx(tx, out[2], m, v, step)
+    torch.cuda.synchronize()
+    tx.copy_(tx0); m.zero_(); v.zero_(); step.zero_()
+    torch.cuda.synchronize()
+    for i in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[1], eager[i][0]), f"replay {i} loss"
+        assert torch.equal(tx, eager[i][1]), f"replay {i} tx"
+        _ = (tx * 2).sum().item()   # unrelated eager work between replays
