@@ -1,0 +1,154 @@
+"""Benchmark: smoothed path-evaluations per second, forward + adjoint, one GPU.
+
+Workload: box + 64 seeded segments (68 walls), 256 x 256 receiver grid,
+order <= 2 (4,625 wall sequences), alpha = 100, loss = -mean log(P + 1e-6).
+One step = the forward pass (power map, loss, seed dL/dP) followed by the
+adjoint pass (gradients w.r.t. the transmitter and all 272 wall coordinates)
+starting from the contributions the forward recorded -- the same kernels
+drt_forward_backward enqueues, issued as two calls so that HIP events can
+bracket each kernel.  path-evals per step =
+receivers x candidates = 65,536 x 4,625.
+
+Prints one JSON line (see the fields below).  Inputs are resident in device
+memory before timing starts.  --gpus N > 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (datasheet, counts packed issue)
+
+
+def cpu_baseline(alpha: float, n_rx: int):
+    """The FP64 oracle (as it stands) on a bounded receiver sample, fwd + VJP."""
+    import numpy as np
+    import torch
+
+    from oracle import tracer as T
+    from paper_2401_11882_amd import workloads as WL
+
+    s = WL.scene_64(alpha=alpha)
+    idx = np.random.default_rng(7).choice(s.n_rx, size=n_rx, replace=False)
+    rx = s.rx[idx]
+    t0 = time.perf_counter()
+    P = T.power(s.walls, s.tx, rx, s.max_order, alpha)
+    g = T.loss_seed(P, "neg_mean_log") * (n_rx / s.n_rx)
+    T.vjp(s.walls, s.tx, rx, s.max_order, alpha, g)
+    dt = time.perf_counter() - t0
+    n_pe = n_rx * WL.n_candidates(s.n_walls, s.max_order)
+    return {"value": n_pe / dt, "unit": "path-evals/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_rx} random receivers of the 256x256 grid (fwd + VJP, FP64, torch CPU), {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--alpha", type=float, default=100.0)
+    ap.add_argument("--cpu-sample", type=int, default=768, help="receivers for the CPU oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design "
+              "note, not part of this build.", file=sys.stderr)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+
+    import numpy as np
+    import torch
+
+    from paper_2401_11882_amd import tracer as tr
+    from paper_2401_11882_amd import workloads as WL
+
+    dev = torch.device("cuda:0")
+    s = WL.scene_64(alpha=args.alpha)
+    walls = torch.tensor(s.walls, device=dev)
+    tx = torch.tensor(s.tx, device=dev)
+    rx = torch.tensor(s.rx, device=dev)
+    scene = tr.Scene(walls, tx, rx, s.max_order, args.alpha, grid_nx=s.grid_n)
+    n_cand = tr.num_candidates(s.n_walls, s.max_order)
+    pe_per_step = s.n_rx * n_cand
+
+    def step():
+        P, L, seed = tr.forward(scene, loss="neg_mean_log", want_seed=True)
+        ev_mid = torch.cuda.Event(enable_timing=True)
+        ev_mid.record()
+        gtx, gw, _ = tr.backward(scene, seed, reuse_forward=True)
+        return ev_mid, L, gtx
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    mids = []
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for i in range(args.steps):
+        starts[i].record()
+        ev_mid, L, gtx = step()
+        mids.append(ev_mid)
+        ends[i].record()
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    fwd_ms = float(np.mean([starts[i].elapsed_time(mids[i]) for i in range(args.steps)]))
+    bwd_ms = float(np.mean([mids[i].elapsed_time(ends[i]) for i in range(args.steps)]))
+    total_s = max(wall_s, gpu_ms / 1e3)
+    ms_per_step = 1e3 * total_s / args.steps
+    value = pe_per_step * args.steps / total_s
+
+    # algorithmic FLOPs per path evaluation (oracle-derived counts, bench_work_model.json)
+    roofline = None
+    wm_path = os.path.join(ROOT, "bench_work_model.json")
+    if os.path.exists(wm_path):
+        with open(wm_path) as f:
+            wm = json.load(f)
+        pa = wm["per_alpha"].get(str(int(args.alpha)))
+        if pa is not None:
+            if bwd_ms >= fwd_ms:
+                name, ms, per = "k_backward (adjoint)", bwd_ms, pa["bwd_flops_per_path_eval"]
+            else:
+                name, ms, per = "k_forward", fwd_ms, pa["fwd_flops_per_path_eval"]
+            achieved = per * pe_per_step / (ms * 1e-3) / 1e12
+            roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                        "traffic": None, "kernel": name, "kernel_ms": round(ms, 4),
+                        "flops_per_path_eval": round(per, 2)}
+
+    out = {
+        "metric": "smoothed path-evals/s fwd+bwd (rx x candidates)",
+        "value": value, "unit": "path-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "box + 64 segments, 256x256 rx grid, order<=2 (4625 candidates), alpha=100, "
+                               "fwd + adjoint w.r.t. tx and all wall endpoints",
+                   "receivers": s.n_rx, "candidates": n_cand, "alpha": args.alpha,
+                   "path_evals_per_step": pe_per_step},
+        "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
+        "roofline": roofline,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.alpha, args.cpu_sample)
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

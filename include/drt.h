@@ -112,6 +112,14 @@ int drt_num_candidates(int32_t n_walls, int32_t max_order, int64_t* count);
    candidates handed to one wavefront (0 = automatic).  Process-wide. */
 int drt_set_launch_config(int32_t nw, int32_t cchunk);
 
+/* Upper bound (bytes) on the contribution cache that drt_workspace_size
+   reserves: drt_forward records, per wavefront, the candidates with a
+   nonzero contribution and their per-receiver values, so that the adjoint
+   can start from them instead of re-evaluating the forward.  A smaller
+   limit only costs speed (overflowing wavefronts re-evaluate); 0 disables
+   the cache.  Default 32 GiB.  Process-wide; affects later size queries. */
+int drt_set_cache_limit(int64_t bytes);
+
 /* Workspace bytes that drt_forward / drt_backward / drt_forward_backward
    need for this scene (depends on n_walls, n_rx and the launch shape).
    Host only; reads no device memory. */
@@ -129,8 +137,14 @@ int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps,
 
 /* Adjoint pass: given grad_power_dev = dL/dP(r) [n_rx], writes
    grad_tx_dev [2], grad_walls_dev [n_walls][4] and, if not NULL,
-   grad_rx_dev [n_rx][2].  Outputs are overwritten, not accumulated. */
-int drt_backward(const drt_scene* scene, const float* grad_power_dev,
+   grad_rx_dev [n_rx][2].  Outputs are overwritten, not accumulated.
+   flags: 0, or DRT_BWD_REUSE_FORWARD when the workspace still holds what
+   the last drt_forward on this same scene (same device inputs, same
+   workspace, nothing changed since) recorded; the adjoint then starts from
+   the recorded contributions.  With any other history the flag gives wrong
+   gradients: pass 0. */
+#define DRT_BWD_REUSE_FORWARD 1
+int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t flags,
                  float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,
                  void* ws_dev, size_t ws_bytes, void* stream);
 

@@ -1,0 +1,73 @@
+"""Write the algorithmic work model of the benchmark workload.
+
+Runs only oracle code (FP64, CPU) on a seeded receiver sample of the
+64-segment scene (box + 64 segments, 256x256 receivers, order <= 2) and
+writes per-path-evaluation counts to bench_work_model.json at the repository
+root.  bench.py turns them into algorithmic FLOPs with the per-operation
+weights stored alongside.
+
+Usage: python -m oracle.count_work [--sample 256]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import tracer as T  # noqa: E402
+from paper_2401_11882_amd import workloads as WL  # noqa: E402
+
+# FLOPs per operation (FMA = 2, add/mul/compare = 1, exp2/rcp = 1), taken
+# from the arithmetic each step needs ("Algorithmic work").
+WEIGHTS = {
+    "fwd_per_path_eval": 13,          # |r - I_k|^2, floor, divide, compensated sum
+    "fwd_per_interaction": 40,        # back-trace step (20) + in(t) in(u) (20)
+    "fwd_per_test": 18,               # den, tau/ups numerators, band check
+    "fwd_per_unsaturated": 26,        # reciprocal, 4 exp, stable 1 - in*in, product
+    "bwd_per_active_path_eval": 12,   # dL/dc, |r - I_k|^2 adjoint
+    "bwd_per_active_interaction": 80, # back-trace + mirror adjoint, in(t) in(u) and its derivative
+    "bwd_per_active_test": 18,        # den, tau/ups numerators, band check
+    "bwd_per_unsaturated": 76,        # tau, ups, 4 exp, dlog q / d(tau, ups), quotient-rule chain
+}
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sample", type=int, default=256)
+    ap.add_argument("--alphas", default="10,100,1000")
+    args = ap.parse_args()
+    out = {"workload": "box + 64 segments, 256x256 receivers, order <= 2 (4,625 candidates)",
+           "sample_receivers": args.sample, "weights": WEIGHTS, "per_alpha": {}}
+    for a in [float(x) for x in args.alphas.split(",")]:
+        s = WL.scene_64(alpha=a)
+        idx = np.random.default_rng(11882).choice(s.n_rx, size=args.sample, replace=False)
+        c = T.work_counts(s.walls, s.tx, s.rx[idx], s.max_order, a)
+        n = c["path_evals"]
+        per = {k: v / n for k, v in c.items()}
+        W = WEIGHTS
+        fwd = (W["fwd_per_path_eval"] + W["fwd_per_interaction"] * per["interactions"] +
+               W["fwd_per_test"] * per["tests"] + W["fwd_per_unsaturated"] * per["unsaturated"])
+        # reverse sweep from the recorded contributions: it needs the test
+        # geometry and the smoothed values again, then their derivatives
+        bwd = (W["bwd_per_active_path_eval"] * per["active"] +
+               W["bwd_per_active_interaction"] * per["active_interactions"] +
+               W["bwd_per_active_test"] * per["tests"] +
+               W["bwd_per_unsaturated"] * per["unsaturated"])
+        out["per_alpha"][str(int(a))] = {
+            "counts": c, "per_path_eval": per,
+            "fwd_flops_per_path_eval": fwd,
+            "bwd_flops_per_path_eval": bwd,
+        }
+        print(a, json.dumps(out["per_alpha"][str(int(a))]), flush=True)
+    with open(os.path.join(ROOT, "bench_work_model.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -333,13 +333,22 @@ def path_details(walls, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_D
     return out
 
 
-def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0):
-    """Obstruction-test counts: total, and how many are unsaturated.
+def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
+                active_log_floor: float = -88.72):
+    """Algorithmic work of the method at these receivers (instrumentation).
 
-    A test is unsaturated when both tau and upsilon lie within margin/alpha of
-    [0, 1] (outside that band the product inside(tau)inside(upsilon) is below
-    2^-25, so the factor rounds to 1 in FP32).  Also counts interaction
-    evaluations.  Used for algorithmic-work accounting only.
+    Counts, over all (receiver, candidate) pairs ("path evaluations"):
+      * ``path_evals`` and ``interactions`` (reflections evaluated);
+      * ``active``: pairs whose product of interaction factors is above
+        exp(active_log_floor) -- below it the product of the four
+        (1 + exp) terms exceeds the FP32 range, the factor is exactly 0 in
+        FP32 and the obstruction tests of that pair contribute nothing;
+      * ``tests``: obstruction tests of active pairs (a leg is not tested
+        against its own end walls);
+      * ``unsaturated``: tests of active pairs whose tau and upsilon both lie
+        within margin/alpha of [0, 1] (outside that band the smoothed factor
+        is within 2^-25 of 1 and rounds to 1 in FP32);
+      * ``active_interactions``: interactions of active pairs.
     """
     W = _as64(walls).reshape(-1, 4)
     T = _as64(tx).reshape(2)
@@ -349,7 +358,7 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0):
     groups = _groups(W.shape[0], max_order)
     cs = _chunk_size(Rx.shape[0], groups, W.shape[0])
     band = margin / alpha
-    tot = uns = inter = 0
+    out = dict(path_evals=0, interactions=0, active=0, active_interactions=0, tests=0, unsaturated=0)
     with torch.no_grad():
         for s in range(0, Rx.shape[0], cs):
             rxc = Rx[s:s + cs]
@@ -357,23 +366,30 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0):
                 _, info = _group_terms(W, T, rxc, seq, alpha, "sigmoid", DEFAULT_DMIN, True)
                 X = info["X"]
                 Cn = seq.shape[0]
-                inter += rxc.shape[0] * Cn * k
+                logf = torch.zeros(rxc.shape[0], Cn, dtype=DTYPE)
+                for i, (t, u) in info["params"].items():
+                    logf = logf + _log_inside(t, alpha) + _log_inside(u, alpha)
+                act = info["valid"] & (logf > active_log_floor)
+                out["path_evals"] += rxc.shape[0] * Cn
+                out["interactions"] += rxc.shape[0] * Cn * k
+                out["active"] += int(act.sum())
+                out["active_interactions"] += int(act.sum()) * k
+                jidx = torch.arange(W.shape[0])
                 for l in range(k + 1):
                     D = (X[l + 1] - X[l])[:, :, None, :]
                     w0 = a[None, None] - X[l][:, :, None, :]
                     den = _cross(D, e[None, None])
                     excl = torch.zeros(Cn, W.shape[0], dtype=torch.bool)
-                    jidx = torch.arange(W.shape[0])
                     if l >= 1:
                         excl |= seq[:, l - 1][:, None] == jidx[None]
                     if l + 1 <= k:
                         excl |= seq[:, l][:, None] == jidx[None]
-                    use = ~excl[None].expand_as(den)
+                    use = (~excl[None]) & act[:, :, None]
                     den_s = torch.where(den != 0, den, torch.ones_like(den))
                     tau = _cross(w0, D) / den_s
                     ups = _cross(w0, e[None, None]) / den_s
                     live = use & (den != 0) & ((tau - 0.5).abs() < 0.5 + band) & \
                         ((ups - 0.5).abs() < 0.5 + band)
-                    tot += int(use.sum())
-                    uns += int(live.sum())
-    return {"tests": tot, "unsaturated": uns, "interactions": inter}
+                    out["tests"] += int(use.sum())
+                    out["unsaturated"] += int(live.sum())
+    return out

@@ -20,6 +20,7 @@ c_size_t = ctypes.c_size_t
 
 DRT_OK, DRT_EINVAL, DRT_EWORKSPACE, DRT_ENOTSUP, DRT_EHIP = 0, -1, -2, -3, -4
 DRT_SIGMOID = 0
+DRT_BWD_REUSE_FORWARD = 1
 LOSS = {"none": 0, "sum": 1, "neg_mean_log": 2}
 
 
@@ -47,8 +48,9 @@ _SIGS = {
     "drt_workspace_size": ([ctypes.POINTER(DrtScene), ctypes.POINTER(c_size_t)], c_int32),
     "drt_forward": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_void_p, c_void_p, c_void_p,
                      c_void_p, c_size_t, c_void_p], c_int32),
-    "drt_backward": ([ctypes.POINTER(DrtScene), c_void_p, c_void_p, c_void_p, c_void_p,
+    "drt_backward": ([ctypes.POINTER(DrtScene), c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                       c_void_p, c_size_t, c_void_p], c_int32),
+    "drt_set_cache_limit": ([ctypes.c_int64], c_int32),
     "drt_forward_backward": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "drt_adam_tx": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,

@@ -31,6 +31,8 @@ int hip_fail(hipError_t e, const char* what) {
 // Launch shape overrides (0 = automatic).
 int g_nw_override = 0;
 int g_cchunk_override = 0;
+// Largest contribution cache placed in a workspace (bytes); 0 disables it.
+int64_t g_cache_limit = 32LL << 30;
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -48,8 +50,9 @@ struct Plan {
   int n_tiles;
   int nw;
   int cchunk;
-  int ncol;  // 2 + 4 W
-  size_t off_walls, off_loss, off_seed, off_grad, total;
+  int ncol;       // 2 + 4 W
+  int cache_cap;  // 0 = no contribution cache
+  size_t off_walls, off_loss, off_seed, off_grad, off_cache_c, off_cache_idx, off_cache_n, total;
 };
 
 int pick_nw(int n_tiles, int n_walls) {
@@ -99,6 +102,25 @@ Plan make_plan(const drt_scene* s) {
   off = align_up(off + sizeof(float) * (size_t)(s->n_rx > 0 ? s->n_rx : 1));
   p.off_grad = off;
   off = align_up(off + sizeof(float) * (size_t)p.ncol * (size_t)(p.n_tiles > 0 ? p.n_tiles : 1));
+  // contribution cache: a wavefront meets at most ceil(C / (nw*cchunk)) chunks
+  const int64_t n_cand = count_candidates(s->n_walls, s->max_order);
+  const int64_t per_wave = (n_cand + (int64_t)p.nw * p.cchunk - 1) / ((int64_t)p.nw * p.cchunk) * p.cchunk;
+  const int64_t slots = (int64_t)p.n_tiles * p.nw;
+  const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int);
+  int64_t cap = per_wave;
+  if (slots > 0 && g_cache_limit > 0) {
+    const int64_t fit = (g_cache_limit - slots * (int64_t)sizeof(int)) / (slots * entry);
+    if (fit < cap) cap = fit;
+  } else {
+    cap = 0;
+  }
+  p.cache_cap = cap > 0 ? (int)cap : 0;
+  p.off_cache_c = off;
+  off = align_up(off + sizeof(float) * (size_t)slots * p.cache_cap * drt::kWave);
+  p.off_cache_idx = off;
+  off = align_up(off + sizeof(int) * (size_t)slots * p.cache_cap);
+  p.off_cache_n = off;
+  off = align_up(off + sizeof(int) * (size_t)(p.cache_cap > 0 ? slots : 0));
   p.total = off;
   return p;
 }
@@ -117,6 +139,13 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.a2 = s->alpha * drt::kLog2e;
   A.band_k = 1.0f + 2.0f * 18.0f / s->alpha;
   A.dmin2 = s->d_min * s->d_min;
+  if (p.cache_cap > 0) {
+    char* w = static_cast<char*>(ws);
+    A.cache_c = reinterpret_cast<float*>(w + p.off_cache_c);
+    A.cache_idx = reinterpret_cast<int*>(w + p.off_cache_idx);
+    A.cache_n = reinterpret_cast<int*>(w + p.off_cache_n);
+    A.cache_cap = p.cache_cap;
+  }
   return A;
 }
 
@@ -159,12 +188,12 @@ int enqueue_forward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, 
 }
 
 int enqueue_backward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, const float* gP,
-                     float* gtx, float* gwalls, float* grx, void* ws, hipStream_t st) {
+                     float* gtx, float* gwalls, float* grx, int reuse, void* ws, hipStream_t st) {
   char* w = static_cast<char*>(ws);
   float* part = reinterpret_cast<float*>(w + p.off_grad);
   hipError_t e;
   if (p.n_tiles > 0) {
-    e = drt::launch_backward(A, p.n_tiles, p.nw, gP, part, grx, st);
+    e = drt::launch_backward(A, p.n_tiles, p.nw, gP, part, grx, reuse, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }
   e = drt::launch_reduce_cols(part, p.n_tiles, p.ncol, gtx, 2, gwalls, st);
@@ -200,6 +229,12 @@ int drt_set_launch_config(int32_t nw, int32_t cchunk) {
   return DRT_OK;
 }
 
+int drt_set_cache_limit(int64_t bytes) {
+  if (bytes < 0) return fail(DRT_EINVAL, "cache limit %lld is negative", (long long)bytes);
+  g_cache_limit = bytes;
+  return DRT_OK;
+}
+
 int drt_num_candidates(int32_t n_walls, int32_t max_order, int64_t* count) {
   if (!count) return fail(DRT_EINVAL, "count is NULL");
   if (n_walls < 0 || n_walls > DRT_MAX_WALLS || max_order < 0 || max_order > DRT_MAX_ORDER)
@@ -230,11 +265,12 @@ int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps, float*
                          static_cast<hipStream_t>(stream));
 }
 
-int drt_backward(const drt_scene* scene, const float* grad_power_dev, float* grad_tx_dev,
-                 float* grad_walls_dev, float* grad_rx_dev, void* ws_dev, size_t ws_bytes,
-                 void* stream) {
+int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t flags,
+                 float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev, void* ws_dev,
+                 size_t ws_bytes, void* stream) {
   int rc = check_scene(scene);
   if (rc) return rc;
+  if (flags & ~DRT_BWD_REUSE_FORWARD) return fail(DRT_EINVAL, "unknown flags 0x%x", flags);
   if (scene->n_rx > 0 && !grad_power_dev) return fail(DRT_EINVAL, "grad_power_dev is NULL");
   if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
   if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
@@ -247,7 +283,7 @@ int drt_backward(const drt_scene* scene, const float* grad_power_dev, float* gra
                                         reinterpret_cast<drt::WallRec*>(w + p.off_walls), st);
   if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
   return enqueue_backward(scene, p, A, grad_power_dev, grad_tx_dev, grad_walls_dev, grad_rx_dev,
-                          ws_dev, st);
+                          (flags & DRT_BWD_REUSE_FORWARD) ? 1 : 0, ws_dev, st);
 }
 
 int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
@@ -267,7 +303,7 @@ int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_ep
   float* seed = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + p.off_seed);
   rc = enqueue_forward(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed, ws_dev, st);
   if (rc) return rc;
-  return enqueue_backward(scene, p, A, seed, grad_tx_dev, grad_walls_dev, grad_rx_dev, ws_dev, st);
+  return enqueue_backward(scene, p, A, seed, grad_tx_dev, grad_walls_dev, grad_rx_dev, 1, ws_dev, st);
 }
 
 int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev, int32_t* step_dev,

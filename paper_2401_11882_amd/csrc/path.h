@@ -1,0 +1,442 @@
+// Per-(receiver, candidate) evaluation of the smoothed image-method path and
+// its adjoint, as inline device code shared by the single-scene and the
+// batched kernels.  One lane = one receiver; the candidate and the wall under
+// test are wave-uniform.
+//
+// Method (arXiv 2401.11882): image method in the relaxed scene (Sec. IV,
+// Sec. IV-B); every validity comparison x0 > x1 smoothed as
+// s(x0 - x1) = sigmoid(alpha (x0 - x1)) (Sec. IV-A, Eq. 3, Eq. 4); power
+// V / max(|r - I_k|^2, d_min^2) per path (Eq. 7 with identity coefficient).
+//
+// Exactness of the skips used below (none changes the FP32 result):
+//  * exp2(z) is +inf for z >= 128, so an interaction whose exponent argument
+//    reaches 128 has in(t) in(u) = 1 / inf = 0 exactly;
+//  * an obstruction test with tau or upsilon more than 18/alpha outside
+//    [0, 1] has in(tau) in(ups) < e^-18 < 2^-25, so 1 - in*in rounds to 1.0f.
+#pragma once
+#include "dev.h"
+
+namespace drt {
+
+struct SceneView {
+  const WallRec* walls;  // prepared records [n_walls]
+  int n_walls;
+  float alpha;
+  float a2;      // alpha * log2(e)
+  float band_k;  // 1 + 2 * 18 / alpha
+  float dmin2;
+};
+
+template <int K>
+struct Path {
+  static constexpr int KI = K > 0 ? K : 1;
+  float Ix[K + 1], Iy[K + 1];   // images I_0 = tx .. I_K (wave-uniform values)
+  float Xx[K + 2], Xy[K + 2];   // X_0 = tx, X_1..X_K interaction points, X_{K+1} = r
+  float t[KI], u[KI], inv[KI];  // interaction i (stored at i-1): wall and side parameters
+  float dx[KI], dy[KI], wx[KI], wy[KI];
+  int s[KI];                    // wall of interaction i
+  int lo[K + 1], hi[K + 1];     // walls a leg is not tested against (its own ends)
+  float F;                      // product of interaction factors
+};
+
+// E / (1 + E) = 1 - s, accurate for small E and exactly 1 for huge or infinite E.
+__device__ __forceinline__ float one_minus_s(float E) { return E < kBig ? E * rcp(1.0f + E) : 1.0f; }
+
+// Images, back-trace and (if WANT_F) the interaction factors of candidate cd.
+// With WANT_F, returns false as soon as every lane's factor is exactly 0
+// (then P.F = 0 and the remaining fields are not filled).
+template <int K, bool WANT_F>
+__device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, float txx, float txy,
+                                           float rxx, float rxy, bool live, Path<K>& P) {
+  const int sv[3] = {cd.s0, cd.s1, cd.s2};
+#pragma unroll
+  for (int i = 0; i < Path<K>::KI; ++i) P.s[i] = (i < K) ? sv[i] : -1;
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    P.lo[l] = (l >= 1) ? sv[l - 1] : -1;
+    P.hi[l] = (l + 1 <= K) ? sv[l] : -1;
+  }
+  P.Ix[0] = txx;
+  P.Iy[0] = txy;
+  bool ok = live;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const WallRec w = S.walls[P.s[i]];
+    const float nx = -w.ey, ny = w.ex;
+    const float nn = nx * nx + ny * ny;
+    ok = ok && (nn > 0.0f);
+    const float h = ((P.Ix[i] - w.ax) * nx + (P.Iy[i] - w.ay) * ny) / (nn > 0.0f ? nn : 1.0f);
+    P.Ix[i + 1] = P.Ix[i] - 2.0f * h * nx;
+    P.Iy[i + 1] = P.Iy[i] - 2.0f * h * ny;
+  }
+  P.Xx[0] = txx;
+  P.Xy[0] = txy;
+  P.Xx[K + 1] = rxx;
+  P.Xy[K + 1] = rxy;
+  float F = ok ? 1.0f : 0.0f;
+#pragma unroll
+  for (int i = K; i >= 1; --i) {
+    const WallRec w = S.walls[P.s[i - 1]];
+    const float dx = P.Ix[i] - P.Xx[i + 1], dy = P.Iy[i] - P.Xy[i + 1];
+    const float wx = w.ax - P.Xx[i + 1], wy = w.ay - P.Xy[i + 1];
+    const float den = dx * w.ey - dy * w.ex;
+    const bool good = den != 0.0f;
+    const float inv = good ? rcp(den) : 0.0f;
+    const float t = (wx * dy - wy * dx) * inv;      // along the wall segment
+    const float u = (wx * w.ey - wy * w.ex) * inv;  // between X_{i+1} and the image
+    P.Xx[i] = fmaf(t, w.ex, w.ax);
+    P.Xy[i] = fmaf(t, w.ey, w.ay);
+    P.t[i - 1] = t;
+    P.u[i - 1] = u;
+    P.inv[i - 1] = inv;
+    P.dx[i - 1] = dx;
+    P.dy[i - 1] = dy;
+    P.wx[i - 1] = wx;
+    P.wy[i - 1] = wy;
+    if (WANT_F) {
+      // exponents of E = exp(-alpha x) for x = t, 1 - t, u, 1 - u
+      const float z1 = -S.a2 * t, z2 = fmaf(S.a2, t, -S.a2);
+      const float z3 = -S.a2 * u, z4 = fmaf(S.a2, u, -S.a2);
+      F = good ? F : 0.0f;
+      const bool zero = (F == 0.0f) | (z1 >= 128.0f) | (z2 >= 128.0f) | (z3 >= 128.0f) | (z4 >= 128.0f);
+      if (ballot(!zero) == 0) {
+        P.F = 0.0f;
+        return false;
+      }
+      const float E1 = ex2(z1), E2 = ex2(z2), E3 = ex2(z3), E4 = ex2(z4);
+      F *= rcp(((1.0f + E1) * (1.0f + E2)) * ((1.0f + E3) * (1.0f + E4)));
+    }
+  }
+  P.F = F;
+  return true;
+}
+
+struct LegGeom {
+  float Dx, Dy, nXD, Xx, Xy;
+};
+
+template <int K>
+__device__ __forceinline__ void leg_geoms(const Path<K>& P, LegGeom (&L)[K + 1]) {
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    L[l].Dx = P.Xx[l + 1] - P.Xx[l];
+    L[l].Dy = P.Xy[l + 1] - P.Xy[l];
+    L[l].nXD = -(P.Xx[l] * L[l].Dy - P.Xy[l] * L[l].Dx);
+    L[l].Xx = P.Xx[l];
+    L[l].Xy = P.Xy[l];
+  }
+}
+
+// Obstruction test of a leg by wall w, in two stages so a wavefront can stop
+// after the first when no lane's tau is inside the band.
+__device__ __forceinline__ bool tau_in_band(const LegGeom& L, const WallRec& w, float band_k, float& den,
+                                            float& tn, float& kd) {
+  den = L.Dx * w.ey - L.Dy * w.ex;
+  tn = fmaf(w.ax, L.Dy, fmaf(-w.ay, L.Dx, L.nXD));  // (a - X) x D
+  kd = band_k * fabsf(den);
+  return fabsf(fmaf(2.0f, tn, -den)) < kd;
+}
+
+__device__ __forceinline__ bool ups_in_band(const LegGeom& L, const WallRec& w, float den, float kd,
+                                            float& un) {
+  un = fmaf(L.Xy, w.ex, fmaf(-L.Xx, w.ey, w.axe));  // (a - X) x e
+  return fabsf(fmaf(2.0f, un, -den)) < kd;
+}
+
+struct ObsVals {
+  float tau, ups, inv, E1, E2, E3, E4, nt, nu, num;
+};
+
+// 1 - in(tau) in(ups) = num / (1 + num), num = nt + nu + nt nu, nt = E1 + E2 + E1 E2.
+__device__ __forceinline__ ObsVals obstruction_vals(float den, float tn, float un, float a2) {
+  ObsVals o;
+  o.inv = rcp(den);
+  o.tau = tn * o.inv;
+  o.ups = un * o.inv;
+  o.E1 = ex2(-a2 * o.tau);
+  o.E2 = ex2(fmaf(a2, o.tau, -a2));
+  o.E3 = ex2(-a2 * o.ups);
+  o.E4 = ex2(fmaf(a2, o.ups, -a2));
+  o.nt = fmaf(o.E1, o.E2, o.E1 + o.E2);
+  o.nu = fmaf(o.E3, o.E4, o.E3 + o.E4);
+  o.num = fmaf(o.nt, o.nu, o.nt + o.nu);
+  return o;
+}
+
+// V times every obstruction factor of the path.
+template <int K>
+__device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>& P, float V) {
+  LegGeom L[K + 1];
+  leg_geoms<K>(P, L);
+  for (int j = 0; j < S.n_walls; ++j) {
+    const WallRec w = S.walls[j];
+#pragma unroll
+    for (int l = 0; l <= K; ++l) {
+      if (j == P.lo[l] || j == P.hi[l]) continue;
+      float den, tn, kd, un;
+      const bool it = tau_in_band(L[l], w, S.band_k, den, tn, kd);
+      if (ballot(it) == 0) continue;
+      if (it && ups_in_band(L[l], w, den, kd, un)) {
+        const ObsVals o = obstruction_vals(den, tn, un, S.a2);
+        V *= o.num * rcp(1.0f + o.num);
+      }
+    }
+  }
+  return V;
+}
+
+// Contribution c = V / max(|r - I_K|^2, d_min^2) of candidate cd at this lane.
+template <int K>
+__device__ __forceinline__ float path_power(const SceneView& S, const Cand& cd, float txx, float txy,
+                                            float rxx, float rxy, bool live) {
+  Path<K> P;
+  if (!setup_path<K, true>(S, cd, txx, txy, rxx, rxy, live, P)) return 0.0f;
+  if (ballot(P.F != 0.0f) == 0) return 0.0f;
+  const float V = obstruct_all<K>(S, P, P.F);
+  const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
+  const float d2 = fmaf(ex, ex, ey * ey);
+  return V / fmaxf(d2, S.dmin2);
+}
+
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
+  const float y = x - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
+// Per-wave accumulator layout: [0,1] = d/dtx, [2 + 4j + c] = d/d walls[j][c].
+__device__ __forceinline__ void acc_wall(float* acc, int j, float dax, float day, float dbx, float dby,
+                                         int lane) {
+  const float s0 = wave_sum(dax), s1 = wave_sum(day), s2 = wave_sum(dbx), s3 = wave_sum(dby);
+  if (lane == 0) {
+    float* p = acc + 2 + 4 * j;
+    p[0] += s0;
+    p[1] += s1;
+    p[2] += s2;
+    p[3] += s3;
+  }
+}
+
+struct LaneGrad {
+  float tx_x, tx_y, rx_x, rx_y;
+};
+
+// Reverse sweep of one path given Wl = g(r) * c (= dL/dlog V at this lane).
+// Adds wall and transmitter gradients to the wave's accumulator and per-lane
+// transmitter / receiver gradients to G.
+template <int K>
+__device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path<K>& P, float Wl,
+                                                  float rxx, float rxy, float* acc, int lane,
+                                                  LaneGrad& G) {
+  const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
+  const float d2 = fmaf(ex, ex, ey * ey);
+
+  // -- obstruction tests, reverse: dlog q / dtau, dlog q / dups -> geometry
+  LegGeom L[K + 1];
+  leg_geoms<K>(P, L);
+  float Sgwx[K + 1], Sgwy[K + 1], SgDx[K + 1], SgDy[K + 1];
+#pragma unroll
+  for (int l = 0; l <= K; ++l) Sgwx[l] = Sgwy[l] = SgDx[l] = SgDy[l] = 0.0f;
+  const bool act = Wl != 0.0f;
+  const float nalpha = -S.alpha;
+  for (int j = 0; j < S.n_walls; ++j) {
+    const WallRec w = S.walls[j];
+    float gax = 0.0f, gay = 0.0f, gex = 0.0f, gey = 0.0f;
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l <= K; ++l) {
+      if (j == P.lo[l] || j == P.hi[l]) continue;
+      float den, tn, kd, un;
+      const bool it = tau_in_band(L[l], w, S.band_k, den, tn, kd) && act;
+      if (ballot(it) == 0) continue;
+      if (it && ups_in_band(L[l], w, den, kd, un)) {
+        const ObsVals o = obstruction_vals(den, tn, un, S.a2);
+        const float Ab = 1.0f + o.nt, Bb = 1.0f + o.nu;
+        const float coef = nalpha * Wl * rcp(o.num * Ab * Bb);
+        const float gt = coef * (o.E1 - o.E2) * Bb;
+        const float gu = coef * (o.E3 - o.E4) * Ab;
+        const float w0x = w.ax - L[l].Xx, w0y = w.ay - L[l].Xy;
+        const float s = fmaf(gt, o.tau, gu * o.ups);
+        const float gw0x = o.inv * fmaf(gt, L[l].Dy, gu * w.ey);
+        const float gw0y = -o.inv * fmaf(gt, L[l].Dx, gu * w.ex);
+        const float gDx = -o.inv * fmaf(gt, w0y, s * w.ey);
+        const float gDy = o.inv * fmaf(gt, w0x, s * w.ex);
+        const float gEx = o.inv * fmaf(-gu, w0y, s * L[l].Dy);
+        const float gEy = o.inv * fmaf(gu, w0x, -s * L[l].Dx);
+        Sgwx[l] += gw0x;
+        Sgwy[l] += gw0y;
+        SgDx[l] += gDx;
+        SgDy[l] += gDy;
+        gax += gw0x;
+        gay += gw0y;
+        gex += gEx;
+        gey += gEy;
+        any = true;
+      }
+    }
+    if (ballot(any) != 0) acc_wall(acc, j, gax - gex, gay - gey, gex, gey, lane);
+  }
+
+  // -- gradients of the points X_0..X_{K+1} from the legs
+  float gXx[K + 2], gXy[K + 2];
+#pragma unroll
+  for (int i = 0; i < K + 2; ++i) gXx[i] = gXy[i] = 0.0f;
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    gXx[l] -= Sgwx[l] + SgDx[l];
+    gXy[l] -= Sgwy[l] + SgDy[l];
+    gXx[l + 1] += SgDx[l];
+    gXy[l + 1] += SgDy[l];
+  }
+  // -- image distance |r - I_K|^2 (zero gradient under the d_min floor)
+  float gIx[K + 1], gIy[K + 1];
+#pragma unroll
+  for (int i = 0; i <= K; ++i) gIx[i] = gIy[i] = 0.0f;
+  if (d2 > S.dmin2) {
+    const float f = 2.0f * Wl / d2;
+    gIx[K] += f * ex;
+    gIy[K] += f * ey;
+    gXx[K + 1] -= f * ex;
+    gXy[K + 1] -= f * ey;
+  }
+  // -- interactions i = 1..K: smoothed factors and back-trace, in order
+#pragma unroll
+  for (int i = 1; i <= K; ++i) {
+    const WallRec w = S.walls[P.s[i - 1]];
+    const float t = P.t[i - 1], u = P.u[i - 1], inv = P.inv[i - 1];
+    const float E1 = ex2(-S.a2 * t), E2 = ex2(fmaf(S.a2, t, -S.a2));
+    const float E3 = ex2(-S.a2 * u), E4 = ex2(fmaf(S.a2, u, -S.a2));
+    const float aw = S.alpha * Wl;
+    const float gti = aw * (one_minus_s(E1) - one_minus_s(E2));
+    const float gu = aw * (one_minus_s(E3) - one_minus_s(E4));
+    // X_i = a + t e
+    const float gt = gti + gXx[i] * w.ex + gXy[i] * w.ey;
+    float gax = gXx[i], gay = gXy[i];
+    float gex = t * gXx[i], gey = t * gXy[i];
+    // t = (w x d)/den, u = (w x e)/den with w = a - X_{i+1}, d = I_i - X_{i+1}
+    const float dx = P.dx[i - 1], dy = P.dy[i - 1], wx = P.wx[i - 1], wy = P.wy[i - 1];
+    const float s = fmaf(gt, t, gu * u);
+    const float gwx = inv * fmaf(gt, dy, gu * w.ey);
+    const float gwy = -inv * fmaf(gt, dx, gu * w.ex);
+    const float gdx = -inv * fmaf(gt, wy, s * w.ey);
+    const float gdy = inv * fmaf(gt, wx, s * w.ex);
+    gex += inv * fmaf(-gu, wy, s * dy);
+    gey += inv * fmaf(gu, wx, -s * dx);
+    gIx[i] += gdx;
+    gIy[i] += gdy;
+    gXx[i + 1] -= gdx + gwx;
+    gXy[i + 1] -= gdy + gwy;
+    gax += gwx;
+    gay += gwy;
+    acc_wall(acc, P.s[i - 1], gax - gex, gay - gey, gex, gey, lane);
+  }
+  // -- per-lane transmitter and receiver gradients
+  G.tx_x += gXx[0];
+  G.tx_y += gXy[0];
+  G.rx_x += gXx[K + 1];
+  G.rx_y += gXy[K + 1];
+  if (K == 0) {
+    // I_0 is the transmitter itself
+    G.tx_x += gIx[0];
+    G.tx_y += gIy[0];
+  } else {
+    // -- images: reduce over lanes, then mirror adjoint on uniform values
+    float GIx[K + 1], GIy[K + 1];
+#pragma unroll
+    for (int i = 1; i <= K; ++i) {
+      GIx[i] = wave_sum(gIx[i]);
+      GIy[i] = wave_sum(gIy[i]);
+    }
+    GIx[0] = 0.0f;
+    GIy[0] = 0.0f;
+#pragma unroll
+    for (int i = K; i >= 1; --i) {
+      const WallRec w = S.walls[P.s[i - 1]];
+      const float nx = -w.ey, ny = w.ex;
+      const float nn = nx * nx + ny * ny;
+      const float px = P.Ix[i - 1] - w.ax, py = P.Iy[i - 1] - w.ay;
+      const float h = (px * nx + py * ny) / nn;
+      const float Gx = GIx[i], Gy = GIy[i];
+      const float Gn = Gx * nx + Gy * ny;
+      const float kk = 2.0f * Gn / nn;
+      GIx[i - 1] += Gx - kk * nx;
+      GIy[i - 1] += Gy - kk * ny;
+      const float gax = kk * nx, gay = kk * ny;
+      const float gnx = -2.0f * (Gn * (px - 2.0f * h * nx) / nn + h * Gx);
+      const float gny = -2.0f * (Gn * (py - 2.0f * h * ny) / nn + h * Gy);
+      const float gex = gny, gey = -gnx;
+      if (lane == 0) {
+        float* p = acc + 2 + 4 * P.s[i - 1];
+        p[0] += gax - gex;
+        p[1] += gay - gey;
+        p[2] += gex;
+        p[3] += gey;
+      }
+    }
+    if (lane == 0) {
+      acc[0] += GIx[0];
+      acc[1] += GIy[0];
+    }
+  }
+}
+
+// Adjoint of one candidate, re-evaluating its forward value first.
+template <int K>
+__device__ __forceinline__ void path_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
+                                             float rxx, float rxy, bool live, float g, float* acc,
+                                             int lane, LaneGrad& G) {
+  Path<K> P;
+  if (!setup_path<K, true>(S, cd, txx, txy, rxx, rxy, live, P)) return;
+  if (ballot(P.F != 0.0f && g != 0.0f) == 0) return;
+  const float V = obstruct_all<K>(S, P, P.F);
+  const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
+  const float d2 = fmaf(ex, ex, ey * ey);
+  const float Wl = g * (V / fmaxf(d2, S.dmin2));
+  if (ballot(Wl != 0.0f) == 0) return;
+  path_adjoint_core<K>(S, P, Wl, rxx, rxy, acc, lane, G);
+}
+
+// Adjoint of one candidate whose contribution c is already known.
+template <int K>
+__device__ __forceinline__ void path_adjoint_known(const SceneView& S, const Cand& cd, float txx,
+                                                   float txy, float rxx, float rxy, bool live, float Wl,
+                                                   float* acc, int lane, LaneGrad& G) {
+  Path<K> P;
+  setup_path<K, false>(S, cd, txx, txy, rxx, rxy, live, P);
+  path_adjoint_core<K>(S, P, Wl, rxx, rxy, acc, lane, G);
+}
+
+__device__ __forceinline__ float candidate_power(const SceneView& S, const Cand& cd, float txx, float txy,
+                                                 float rxx, float rxy, bool live) {
+  switch (cd.k) {
+    case 0: return path_power<0>(S, cd, txx, txy, rxx, rxy, live);
+    case 1: return path_power<1>(S, cd, txx, txy, rxx, rxy, live);
+    case 2: return path_power<2>(S, cd, txx, txy, rxx, rxy, live);
+    default: return path_power<3>(S, cd, txx, txy, rxx, rxy, live);
+  }
+}
+
+__device__ __forceinline__ void candidate_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
+                                                  float rxx, float rxy, bool live, float g, float* acc,
+                                                  int lane, LaneGrad& G) {
+  switch (cd.k) {
+    case 0: path_adjoint<0>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    case 1: path_adjoint<1>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    case 2: path_adjoint<2>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    default: path_adjoint<3>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+  }
+}
+
+__device__ __forceinline__ void candidate_adjoint_known(const SceneView& S, const Cand& cd, float txx,
+                                                        float txy, float rxx, float rxy, bool live,
+                                                        float Wl, float* acc, int lane, LaneGrad& G) {
+  switch (cd.k) {
+    case 0: path_adjoint_known<0>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    case 1: path_adjoint_known<1>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    case 2: path_adjoint_known<2>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    default: path_adjoint_known<3>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+  }
+}
+
+}  // namespace drt

@@ -21,13 +21,18 @@ struct TraceArgs {
   float a2;              // alpha * log2(e)
   float band_k;          // 1 + 2 * 18 / alpha: unsaturated-test band
   float dmin2;
+  // contribution cache (all NULL when disabled): per (tile, wavefront) slot
+  float* cache_c;    // [slots][cache_cap][64] per-lane contributions
+  int* cache_idx;    // [slots][cache_cap] candidate index of each entry
+  int* cache_n;      // [slots] entries, or -1 when the list overflowed
+  int cache_cap;
 };
 
 hipError_t launch_prep_walls(const float* walls, int n, WallRec* out, hipStream_t st);
 hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power, float* seed,
                           float* loss_part, int loss_kind, float log_eps, hipStream_t st);
 hipError_t launch_backward(const TraceArgs& A, int n_tiles, int nw, const float* gP, float* part,
-                           float* grad_rx, hipStream_t st);
+                           float* grad_rx, int reuse, hipStream_t st);
 size_t backward_lds_bytes(int nw, int n_walls);
 hipError_t launch_reduce_cols(const float* part, int n_rows, int ncol, float* out_head, int n_head,
                               float* out_tail, hipStream_t st);

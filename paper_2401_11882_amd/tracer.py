@@ -100,6 +100,10 @@ def set_launch_config(nw: int = 0, cchunk: int = 0) -> None:
     check(lib().drt_set_launch_config(int(nw), int(cchunk)))
 
 
+def set_cache_limit(nbytes: int) -> None:
+    check(lib().drt_set_cache_limit(int(nbytes)))
+
+
 def forward(scene: Scene, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS,
             want_seed: bool = False, stream=None):
     """P(r) [R]; plus the loss scalar (and dL/dP) when loss != 'none'."""
@@ -113,8 +117,12 @@ def forward(scene: Scene, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS,
     return P, L, seed
 
 
-def backward(scene: Scene, grad_power: torch.Tensor, want_rx: bool = False, stream=None):
-    """(dL/dtx [2], dL/dwalls [W,4], dL/drx [R,2] or None) for a given dL/dP."""
+def backward(scene: Scene, grad_power: torch.Tensor, want_rx: bool = False, reuse_forward: bool = False,
+             stream=None):
+    """(dL/dtx [2], dL/dwalls [W,4], dL/drx [R,2] or None) for a given dL/dP.
+
+    reuse_forward=True starts from the contributions the last forward() on
+    this same scene recorded in the shared workspace (see drt_backward)."""
     _dev_f32(grad_power, "grad_power")
     if grad_power.numel() != scene.n_rx:
         raise ValueError("grad_power must have one entry per receiver")
@@ -123,7 +131,8 @@ def backward(scene: Scene, grad_power: torch.Tensor, want_rx: bool = False, stre
     gtx = torch.empty(2, dtype=torch.float32, device=scene.device)
     gw = torch.empty(scene.n_walls, 4, dtype=torch.float32, device=scene.device)
     grx = torch.empty(scene.n_rx, 2, dtype=torch.float32, device=scene.device) if want_rx else None
-    check(lib().drt_backward(ctypes.byref(sc), _ptr(grad_power), _ptr(gtx), _ptr(gw if scene.n_walls else None),
+    flags = _lib.DRT_BWD_REUSE_FORWARD if reuse_forward else 0
+    check(lib().drt_backward(ctypes.byref(sc), _ptr(grad_power), flags, _ptr(gtx), _ptr(gw if scene.n_walls else None),
                              _ptr(grx), _ptr(ws), nbytes, stream_handle(stream)))
     return gtx, gw, grx
 

@@ -47,6 +47,18 @@ def test_num_candidates():
     assert L.drt_num_candidates(-1, 1, ctypes.byref(c)) == _lib.DRT_EINVAL
 
 
+def test_cache_limit_changes_workspace():
+    L = _lib.lib()
+    sc = _scene(n_walls=68, n_rx=65536, rx_grid_nx=256, max_order=2)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.drt_workspace_size(ctypes.byref(sc), ctypes.byref(a)) == 0
+    assert L.drt_set_cache_limit(0) == 0
+    assert L.drt_workspace_size(ctypes.byref(sc), ctypes.byref(b)) == 0
+    assert L.drt_set_cache_limit(32 << 30) == 0
+    # full cache: 1024 tiles x 8 wavefronts x 579 entries x 260 bytes
+    assert a.value - b.value >= 1024 * 8 * 579 * 260
+
+
 def test_workspace_size_host_only():
     L = _lib.lib()
     n = ctypes.c_size_t()
@@ -100,8 +112,10 @@ def test_call_validation_before_launch():
     assert L.drt_forward(ctypes.byref(sc), 2, 0.0, BOGUS, None, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
     # missing outputs
     assert L.drt_forward(ctypes.byref(sc), 0, 1e-6, None, None, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
-    assert L.drt_backward(ctypes.byref(sc), BOGUS, None, BOGUS, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
-    assert L.drt_backward(ctypes.byref(sc), None, BOGUS, BOGUS, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
+    assert L.drt_backward(ctypes.byref(sc), BOGUS, 0, None, BOGUS, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
+    assert L.drt_backward(ctypes.byref(sc), None, 0, BOGUS, BOGUS, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
+    assert L.drt_backward(ctypes.byref(sc), BOGUS, 4, BOGUS, BOGUS, None, BOGUS, n.value, None) == _lib.DRT_EINVAL
+    assert L.drt_set_cache_limit(-1) == _lib.DRT_EINVAL
     assert L.drt_forward_backward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, None, BOGUS, n.value,
                                   None) == _lib.DRT_EINVAL
     # adam arguments

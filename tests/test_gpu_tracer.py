@@ -176,6 +176,28 @@ def test_grid_and_linear_mapping_agree_bitwise():
     assert torch.equal(Pa, Pb)
 
 
+def test_contribution_cache_reuse_and_overflow():
+    """Adjoint from recorded contributions == adjoint that re-evaluates; a cache
+    too small for the lists falls back to re-evaluation with the same result."""
+    tr = _tr()
+    s = WL.scene_random_box(2, 12, 16, 2, 100.0, seed=8)
+    sc = _scene(s)
+    P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    a = tr.backward(sc, seed, want_rx=True, reuse_forward=True)
+    b = tr.backward(sc, seed, want_rx=True)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x.cpu().numpy(), y.cpu().numpy(), rtol=1e-6, atol=1e-6 * float(y.abs().max()))
+    try:
+        slots = (s.n_rx // 64) * 16
+        tr.set_cache_limit(slots * (4 + 3 * 260))   # 3 entries per wavefront: most overflow
+        out = tr.forward_backward(sc, loss="neg_mean_log", want_rx=True)
+    finally:
+        tr.set_cache_limit(32 << 30)
+    np.testing.assert_allclose(out[2].cpu().numpy(), b[0].cpu().numpy(), rtol=1e-6)
+    np.testing.assert_allclose(out[3].cpu().numpy(), b[1].cpu().numpy(), rtol=1e-6,
+                               atol=1e-6 * float(b[1].abs().max()))
+
+
 def test_deterministic_repeat():
     tr = _tr()
     s = WL.scene_random_box(2, 16, 32, 2, 100.0, seed=4)
