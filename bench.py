@@ -28,6 +28,31 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (datasheet, counts packed issue)
 
 
+def source_hash() -> str:
+    """sha256 over the HIP sources; HBM traffic figures are valid for this hash only."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2401_11882_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tag: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
+    when the kernels changed since those counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_hash():
+        return None
+    k = t["kernels"].get(kernel)
+    return None if k is None else int(k["hbm_bytes"])
+
+
 def cpu_baseline(alpha: float, n_rx: int):
     """The FP64 oracle (as it stands) on a bounded receiver sample, fwd + VJP."""
     import numpy as np
@@ -58,6 +83,8 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=100.0)
     ap.add_argument("--cpu-sample", type=int, default=768, help="receivers for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design "
@@ -113,6 +140,14 @@ def main() -> int:
     ms_per_step = 1e3 * total_s / args.steps
     value = pe_per_step * args.steps / total_s
 
+    if args.copy_calib_mb > 0:
+        n = args.copy_calib_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     # algorithmic FLOPs per path evaluation (oracle-derived counts, bench_work_model.json)
     roofline = None
     wm_path = os.path.join(ROOT, "bench_work_model.json")
@@ -122,13 +157,14 @@ def main() -> int:
         pa = wm["per_alpha"].get(str(int(args.alpha)))
         if pa is not None:
             if bwd_ms >= fwd_ms:
-                name, ms, per = "k_backward (adjoint)", bwd_ms, pa["bwd_flops_per_path_eval"]
+                name, ms, per = "k_backward", bwd_ms, pa["bwd_flops_per_path_eval"]
             else:
                 name, ms, per = "k_forward", fwd_ms, pa["fwd_flops_per_path_eval"]
             achieved = per * pe_per_step / (ms * 1e-3) / 1e12
             roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                        "traffic": None, "kernel": name, "kernel_ms": round(ms, 4),
+                        "traffic": measured_traffic(f"scene64_alpha{int(args.alpha)}", name),
+                        "kernel": name, "kernel_ms": round(ms, 4),
                         "flops_per_path_eval": round(per, 2)}
 
     out = {
