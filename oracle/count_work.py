@@ -23,17 +23,19 @@ sys.path.insert(0, ROOT)
 from oracle import tracer as T  # noqa: E402
 from paper_2401_11882_amd import workloads as WL  # noqa: E402
 
-# FLOPs per operation (FMA = 2, add/mul/compare = 1, exp2/rcp = 1), taken
-# from the arithmetic each step needs ("Algorithmic work").
+# FLOPs per operation (FMA = 2, add/mul/compare = 1, exp2/rcp = 1).  Only
+# work whose result can change the output is counted: an obstruction test
+# whose smoothed factor is 1.0f in FP32 (saturated) and the obstruction tests
+# of a pair whose interaction factor is exactly 0 count nothing, however an
+# implementation proves them away.
 WEIGHTS = {
-    "fwd_per_path_eval": 13,          # |r - I_k|^2, floor, divide, compensated sum
-    "fwd_per_interaction": 40,        # back-trace step (20) + in(t) in(u) (20)
-    "fwd_per_test": 18,               # den, tau/ups numerators, band check
-    "fwd_per_unsaturated": 26,        # reciprocal, 4 exp, stable 1 - in*in, product
-    "bwd_per_active_path_eval": 12,   # dL/dc, |r - I_k|^2 adjoint
-    "bwd_per_active_interaction": 80, # back-trace + mirror adjoint, in(t) in(u) and its derivative
-    "bwd_per_active_test": 18,        # den, tau/ups numerators, band check
-    "bwd_per_unsaturated": 76,        # tau, ups, 4 exp, dlog q / d(tau, ups), quotient-rule chain
+    "fwd_per_path_eval": 13,           # |r - I_k|^2, floor, divide, compensated sum
+    "fwd_per_interaction": 20,         # back-trace step (needed to decide the factor)
+    "fwd_per_active_interaction": 20,  # in(t) in(u): 4 exp, reciprocal, products
+    "fwd_per_unsaturated": 44,         # den, tau/ups (18) + reciprocal, 4 exp, stable 1 - in*in (26)
+    "bwd_per_active_path_eval": 12,    # dL/dc, |r - I_k|^2 adjoint
+    "bwd_per_active_interaction": 80,  # back-trace + mirror adjoint, in(t) in(u) and its derivative
+    "bwd_per_unsaturated": 94,         # the test's values (44) + dlog q/d(tau, ups) and the chain (50)
 }
 
 
@@ -52,12 +54,11 @@ def main() -> None:
         per = {k: v / n for k, v in c.items()}
         W = WEIGHTS
         fwd = (W["fwd_per_path_eval"] + W["fwd_per_interaction"] * per["interactions"] +
-               W["fwd_per_test"] * per["tests"] + W["fwd_per_unsaturated"] * per["unsaturated"])
-        # reverse sweep from the recorded contributions: it needs the test
-        # geometry and the smoothed values again, then their derivatives
+               W["fwd_per_active_interaction"] * per["active_interactions"] +
+               W["fwd_per_unsaturated"] * per["unsaturated"])
+        # reverse sweep from the recorded contributions
         bwd = (W["bwd_per_active_path_eval"] * per["active"] +
                W["bwd_per_active_interaction"] * per["active_interactions"] +
-               W["bwd_per_active_test"] * per["tests"] +
                W["bwd_per_unsaturated"] * per["unsaturated"])
         out["per_alpha"][str(int(a))] = {
             "counts": c, "per_path_eval": per,

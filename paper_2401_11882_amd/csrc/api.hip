@@ -52,7 +52,7 @@ struct Plan {
   int cchunk;
   int ncol;       // 2 + 4 W
   int cache_cap;  // 0 = no contribution cache
-  size_t off_walls, off_loss, off_seed, off_grad, off_cache_c, off_cache_idx, off_cache_n, total;
+  size_t off_walls, off_boxes, off_loss, off_seed, off_grad, off_cache_c, off_cache_idx, off_cache_n, total;
 };
 
 int pick_nw(int n_tiles, int n_walls) {
@@ -96,6 +96,8 @@ Plan make_plan(const drt_scene* s) {
   size_t off = 0;
   p.off_walls = off;
   off = align_up(off + sizeof(drt::WallRec) * (size_t)(s->n_walls > 0 ? s->n_walls : 1));
+  p.off_boxes = off;
+  off = align_up(off + sizeof(drt::WallBox) * (size_t)(s->n_walls > 0 ? s->n_walls : 1));
   p.off_loss = off;
   off = align_up(off + sizeof(float) * (size_t)(p.n_tiles > 0 ? p.n_tiles : 1));
   p.off_seed = off;
@@ -128,6 +130,7 @@ Plan make_plan(const drt_scene* s) {
 drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   drt::TraceArgs A{};
   A.walls = reinterpret_cast<const drt::WallRec*>(static_cast<char*>(ws) + p.off_walls);
+  A.boxes = reinterpret_cast<const drt::WallBox*>(static_cast<char*>(ws) + p.off_boxes);
   A.tx = s->tx_dev;
   A.rx = s->rx_dev;
   A.n_walls = s->n_walls;
@@ -137,7 +140,8 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.cchunk = p.cchunk;
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
-  A.band_k = 1.0f + 2.0f * 18.0f / s->alpha;
+  A.band_k = 1.0f + 2.0f * drt::kBandMargin / s->alpha;
+  A.cull_c = drt::kCullMargin / s->alpha;
   A.dmin2 = s->d_min * s->d_min;
   if (p.cache_cap > 0) {
     char* w = static_cast<char*>(ws);
@@ -169,8 +173,9 @@ int check_loss(int32_t loss_kind, float log_eps) {
 int enqueue_forward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, int32_t loss_kind,
                     float log_eps, float* power, float* loss, float* seed, void* ws, hipStream_t st) {
   char* w = static_cast<char*>(ws);
-  hipError_t e = drt::launch_prep_walls(s->walls_dev, s->n_walls,
-                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls), st);
+  hipError_t e = drt::launch_prep_walls(s->walls_dev, s->n_walls, s->alpha,
+                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls),
+                                        reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
   if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
   float* loss_part = reinterpret_cast<float*>(w + p.off_loss);
   if (p.n_tiles > 0) {
@@ -279,8 +284,9 @@ int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t fl
   const drt::TraceArgs A = make_args(scene, p, ws_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws_dev);
-  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls,
-                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls), st);
+  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls, scene->alpha,
+                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls),
+                                        reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
   if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
   return enqueue_backward(scene, p, A, grad_power_dev, grad_tx_dev, grad_walls_dev, grad_rx_dev,
                           (flags & DRT_BWD_REUSE_FORWARD) ? 1 : 0, ws_dev, st);

@@ -15,6 +15,18 @@ struct WallRec {
   float ax, ay, ex, ey, axe, pad0, pad1, pad2;
 };
 
+// Axis-aligned box of a wall extended along itself by the culling band:
+// [a - c e, b + c e], c = kCullMargin / alpha.
+struct WallBox {
+  float xmin, xmax, ymin, ymax;
+};
+
+// Obstruction tests are evaluated only when both parameters lie within
+// kBandMargin / alpha of [0, 1]; the culling boxes use the wider kCullMargin
+// so that a culled test is one the per-lane check would also skip.
+constexpr float kBandMargin = 18.0f;
+constexpr float kCullMargin = 20.0f;
+
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -37,6 +49,30 @@ __device__ __forceinline__ float wave_sum(float x) {
   x += __builtin_amdgcn_update_dpp(0.0f, x, 0x118, 0xf, 0xf, false);  // row_shr:8
   x += __builtin_amdgcn_update_dpp(0.0f, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
   x += __builtin_amdgcn_update_dpp(0.0f, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Minimum / maximum over the 64 lanes (same DPP pattern as wave_sum; lanes
+// whose source is out of range keep the identity).  Wave-uniform result.
+__device__ __forceinline__ float wave_min(float x) {
+  const float I = __builtin_inff();
+  x = fminf(x, __builtin_amdgcn_update_dpp(I, x, 0xb1, 0xf, 0xf, false));
+  x = fminf(x, __builtin_amdgcn_update_dpp(I, x, 0x4e, 0xf, 0xf, false));
+  x = fminf(x, __builtin_amdgcn_update_dpp(I, x, 0x114, 0xf, 0xf, false));
+  x = fminf(x, __builtin_amdgcn_update_dpp(I, x, 0x118, 0xf, 0xf, false));
+  x = fminf(x, __builtin_amdgcn_update_dpp(I, x, 0x142, 0xa, 0xf, false));
+  x = fminf(x, __builtin_amdgcn_update_dpp(I, x, 0x143, 0xc, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ float wave_max(float x) {
+  const float I = -__builtin_inff();
+  x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0xb1, 0xf, 0xf, false));
+  x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x4e, 0xf, 0xf, false));
+  x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x114, 0xf, 0xf, false));
+  x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x118, 0xf, 0xf, false));
+  x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x142, 0xa, 0xf, false));
+  x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x143, 0xc, 0xf, false));
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 

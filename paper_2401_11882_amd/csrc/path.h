@@ -20,10 +20,12 @@ namespace drt {
 
 struct SceneView {
   const WallRec* walls;  // prepared records [n_walls]
+  const WallBox* boxes;  // culling boxes [n_walls]
   int n_walls;
   float alpha;
   float a2;      // alpha * log2(e)
-  float band_k;  // 1 + 2 * 18 / alpha
+  float band_k;  // 1 + 2 * kBandMargin / alpha
+  float cull_c;  // kCullMargin / alpha
   float dmin2;
 };
 
@@ -163,16 +165,74 @@ __device__ __forceinline__ ObsVals obstruction_vals(float den, float tn, float u
   return o;
 }
 
+// Wave-uniform box around the band-extended legs [X_l - c D, X_{l+1} + c D]
+// of the live lanes.  A wall whose band-extended box misses it cannot give an
+// unsaturated test on that leg in any lane.
+struct LegBox {
+  float xmin, xmax, ymin, ymax;
+};
+
+template <int K>
+__device__ __forceinline__ void leg_boxes(const Path<K>& P, const LegGeom (&L)[K + 1], bool lane_live,
+                                          float c, LegBox (&B)[K + 1]) {
+  const float I = __builtin_inff();
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    const float q0x = fmaf(-c, L[l].Dx, L[l].Xx), q0y = fmaf(-c, L[l].Dy, L[l].Xy);
+    const float q1x = fmaf(c, L[l].Dx, P.Xx[l + 1]), q1y = fmaf(c, L[l].Dy, P.Xy[l + 1]);
+    B[l].xmin = wave_min(lane_live ? fminf(q0x, q1x) : I);
+    B[l].xmax = wave_max(lane_live ? fmaxf(q0x, q1x) : -I);
+    B[l].ymin = wave_min(lane_live ? fminf(q0y, q1y) : I);
+    B[l].ymax = wave_max(lane_live ? fmaxf(q0y, q1y) : -I);
+  }
+}
+
+// Calls fn(wall, masks, bit) for every wall whose box overlaps some leg box
+// (walls in increasing order); masks[l] bit `bit` tells whether leg l needs
+// the test (its own end walls are excluded here).  Lane j of the wavefront
+// checks wall b + j of each 64-wall batch.
+template <int K, class Fn>
+__device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P, const LegBox (&B)[K + 1],
+                                            Fn&& fn) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int b = 0; b < S.n_walls; b += kWave) {
+    const int wj = b + lane;
+    WallBox wb;
+    if (wj < S.n_walls) {
+      wb = S.boxes[wj];
+    } else {
+      wb.xmin = wb.ymin = __builtin_inff();
+      wb.xmax = wb.ymax = -__builtin_inff();
+    }
+    uint64_t m[K + 1];
+    uint64_t uni = 0;
+#pragma unroll
+    for (int l = 0; l <= K; ++l) {
+      const bool ov = (wb.xmin <= B[l].xmax) & (wb.xmax >= B[l].xmin) & (wb.ymin <= B[l].ymax) &
+                      (wb.ymax >= B[l].ymin) & (wj != P.lo[l]) & (wj != P.hi[l]);
+      m[l] = ballot(ov);
+      uni |= m[l];
+    }
+    while (uni) {
+      const int j = __builtin_ctzll(uni);
+      uni &= uni - 1;
+      fn(b + j, m, j);
+    }
+  }
+}
+
 // V times every obstruction factor of the path.
 template <int K>
 __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>& P, float V) {
   LegGeom L[K + 1];
   leg_geoms<K>(P, L);
-  for (int j = 0; j < S.n_walls; ++j) {
-    const WallRec w = S.walls[j];
+  LegBox B[K + 1];
+  leg_boxes<K>(P, L, P.F != 0.0f, S.cull_c, B);
+  visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
+    const WallRec w = S.walls[jw];
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
-      if (j == P.lo[l] || j == P.hi[l]) continue;
+      if (((m[l] >> j) & 1ull) == 0) continue;
       float den, tn, kd, un;
       const bool it = tau_in_band(L[l], w, S.band_k, den, tn, kd);
       if (ballot(it) == 0) continue;
@@ -181,7 +241,7 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
         V *= o.num * rcp(1.0f + o.num);
       }
     }
-  }
+  });
   return V;
 }
 
@@ -240,13 +300,15 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
   for (int l = 0; l <= K; ++l) Sgwx[l] = Sgwy[l] = SgDx[l] = SgDy[l] = 0.0f;
   const bool act = Wl != 0.0f;
   const float nalpha = -S.alpha;
-  for (int j = 0; j < S.n_walls; ++j) {
-    const WallRec w = S.walls[j];
+  LegBox B[K + 1];
+  leg_boxes<K>(P, L, act, S.cull_c, B);
+  visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
+    const WallRec w = S.walls[jw];
     float gax = 0.0f, gay = 0.0f, gex = 0.0f, gey = 0.0f;
     bool any = false;
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
-      if (j == P.lo[l] || j == P.hi[l]) continue;
+      if (((m[l] >> j) & 1ull) == 0) continue;
       float den, tn, kd, un;
       const bool it = tau_in_band(L[l], w, S.band_k, den, tn, kd) && act;
       if (ballot(it) == 0) continue;
@@ -275,8 +337,8 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
         any = true;
       }
     }
-    if (ballot(any) != 0) acc_wall(acc, j, gax - gex, gay - gey, gex, gey, lane);
-  }
+    if (ballot(any) != 0) acc_wall(acc, jw, gax - gex, gay - gey, gex, gey, lane);
+  });
 
   // -- gradients of the points X_0..X_{K+1} from the legs
   float gXx[K + 2], gXy[K + 2];

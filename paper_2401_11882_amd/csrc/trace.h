@@ -7,9 +7,11 @@
 namespace drt {
 
 struct WallRec;
+struct WallBox;
 
 struct TraceArgs {
   const WallRec* walls;  // prepared wall records [n_walls]
+  const WallBox* boxes;  // culling boxes [n_walls]
   const float* tx;       // [2]
   const float* rx;       // [n_rx][2]
   int n_walls;
@@ -20,6 +22,7 @@ struct TraceArgs {
   float alpha;
   float a2;              // alpha * log2(e)
   float band_k;          // 1 + 2 * 18 / alpha: unsaturated-test band
+  float cull_c;          // 20 / alpha: culling-box extension
   float dmin2;
   // contribution cache (all NULL when disabled): per (tile, wavefront) slot
   float* cache_c;    // [slots][cache_cap][64] per-lane contributions
@@ -28,7 +31,8 @@ struct TraceArgs {
   int cache_cap;
 };
 
-hipError_t launch_prep_walls(const float* walls, int n, WallRec* out, hipStream_t st);
+hipError_t launch_prep_walls(const float* walls, int n, float alpha, WallRec* out, WallBox* boxes,
+                             hipStream_t st);
 hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power, float* seed,
                           float* loss_part, int loss_kind, float log_eps, hipStream_t st);
 hipError_t launch_backward(const TraceArgs& A, int n_tiles, int nw, const float* gP, float* part,

@@ -48,10 +48,12 @@ namespace drt {
 __device__ __forceinline__ SceneView view_of(const TraceArgs& A) {
   SceneView S;
   S.walls = A.walls;
+  S.boxes = A.boxes;
   S.n_walls = A.n_walls;
   S.alpha = A.alpha;
   S.a2 = A.a2;
   S.band_k = A.band_k;
+  S.cull_c = A.cull_c;
   S.dmin2 = A.dmin2;
   return S;
 }
@@ -205,11 +207,14 @@ __global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const floa
 // Small kernels
 // ---------------------------------------------------------------------------
 
-__global__ void k_prep_walls(const float* __restrict__ walls, int n, WallRec* __restrict__ out) {
+// Wall records (a, e = b - a, a x e) and culling boxes of [a - c e, b + c e].
+__global__ void k_prep_walls(const float* __restrict__ walls, int n, float c, WallRec* __restrict__ out,
+                             WallBox* __restrict__ boxes) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const float ax = walls[4 * j], ay = walls[4 * j + 1];
-  const float ex = walls[4 * j + 2] - ax, ey = walls[4 * j + 3] - ay;
+  const float bx = walls[4 * j + 2], by = walls[4 * j + 3];
+  const float ex = bx - ax, ey = by - ay;
   WallRec r;
   r.ax = ax;
   r.ay = ay;
@@ -218,6 +223,14 @@ __global__ void k_prep_walls(const float* __restrict__ walls, int n, WallRec* __
   r.axe = ax * ey - ay * ex;
   r.pad0 = r.pad1 = r.pad2 = 0.0f;
   out[j] = r;
+  const float p0x = fmaf(-c, ex, ax), p0y = fmaf(-c, ey, ay);
+  const float p1x = fmaf(c, ex, bx), p1y = fmaf(c, ey, by);
+  WallBox q;
+  q.xmin = fminf(p0x, p1x);
+  q.xmax = fmaxf(p0x, p1x);
+  q.ymin = fminf(p0y, p1y);
+  q.ymax = fmaxf(p0y, p1y);
+  boxes[j] = q;
 }
 
 // Column sums of part[n_rows][ncol] in FP64 with a fixed order: a workgroup
@@ -264,9 +277,11 @@ __global__ void k_reduce_scalar(const float* __restrict__ part, int n, double sc
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_prep_walls(const float* walls, int n, WallRec* out, hipStream_t st) {
+hipError_t launch_prep_walls(const float* walls, int n, float alpha, WallRec* out, WallBox* boxes,
+                             hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep_walls, dim3((n + 255) / 256), dim3(256), 0, st, walls, n, out);
+  hipLaunchKernelGGL(k_prep_walls, dim3((n + 255) / 256), dim3(256), 0, st, walls, n, kCullMargin / alpha,
+                     out, boxes);
   return hipGetLastError();
 }
 
