@@ -165,6 +165,88 @@ int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev
                 int32_t* step_dev, float lr, float b1, float b2, float eps,
                 float lo, float hi, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Many scenes in one persistent launch
+ *
+ * Scenes of uneven wall count and receiver count are traced, seeded with
+ * their loss and differentiated in ONE persistent kernel: work items
+ * (scene, 64-receiver tile) are sorted longest first when the plan is made;
+ * the workgroups that fit on the GPU pull items from a device counter.  Each
+ * scene's loss is its own (mean over its receivers).  The launch shape
+ * (wavefronts per workgroup, candidate chunk, workgroups per CU, tile width)
+ * is chosen by drt_batched_autotune and can be stored in a text cache keyed
+ * by device and batch shape.
+ * ------------------------------------------------------------------------ */
+
+/* Host-side shape of a batch, read by drt_plan_create only.  Scene s owns
+   walls rows [sum_{q<s} n_walls[q], +n_walls[s]) and receivers likewise. */
+typedef struct drt_batch_shape {
+  int32_t n_scenes;           /* > 0 */
+  const int32_t* n_walls;     /* host [n_scenes], each 0 .. DRT_MAX_WALLS */
+  const int32_t* n_rx;        /* host [n_scenes], each >= 0 */
+  const int32_t* rx_grid_nx;  /* host [n_scenes] or NULL: row length of a
+                                 row-major receiver grid (0 = not a grid) */
+  int32_t max_order;          /* K for every scene, 0 .. DRT_MAX_ORDER */
+} drt_batch_shape;
+
+/* Device data of a batch (layouts follow drt_batch_shape). */
+typedef struct drt_batch {
+  const float* walls_dev;  /* [sum n_walls][4] */
+  const float* tx_dev;     /* [n_scenes][2] */
+  const float* rx_dev;     /* [sum n_rx][2] */
+  const float* alpha_dev;  /* [n_scenes], each finite and > 0 (not checked
+                              on the host: it lives on the device) */
+  float d_min;             /* finite, > 0 */
+} drt_batch;
+
+/* Launch shape of a plan.  nw: 4, 8 or 16 wavefronts per workgroup; cchunk:
+   1..64 consecutive candidates per wavefront turn; blocks_per_cu: persistent
+   workgroups per CU (0 = as many as fit); tile_w: 8, 16 or 32 receivers per
+   tile row on grid scenes. */
+typedef struct drt_plan_config {
+  int32_t nw, cchunk, blocks_per_cu, tile_w;
+} drt_plan_config;
+
+typedef struct drt_plan drt_plan;  /* opaque; owns its device buffers */
+
+/* Builds the work list and allocates the plan's device buffers on the
+   current device (allocates and synchronises; not for graph capture).  If
+   tune_cache_path names a file with a line for this device and batch shape,
+   its launch shape is used, otherwise a default.  *out must be released with
+   drt_plan_destroy. */
+int drt_plan_create(const drt_batch_shape* shape, const char* tune_cache_path, drt_plan** out);
+
+/* Waits for the device, frees the plan's buffers.  NULL is a no-op. */
+int drt_plan_destroy(drt_plan* plan);
+
+/* Current launch shape (blocks_per_cu resolved). */
+int drt_plan_get_config(const drt_plan* plan, drt_plan_config* cfg);
+
+/* Sets the launch shape; may reallocate the plan's cache (synchronises). */
+int drt_plan_set_config(drt_plan* plan, const drt_plan_config* cfg);
+
+/* Work-list facts: items, total path evaluations (receivers x candidates
+   summed over scenes), per-wavefront cache capacity.  Any pointer may be NULL. */
+int drt_plan_info(const drt_plan* plan, int64_t* n_items, int64_t* path_evals, int32_t* cache_cap);
+
+/* Forward, per-scene loss and adjoint of every scene in one persistent launch.
+   loss_kind: DRT_LOSS_SUM_POWER or DRT_LOSS_NEG_MEAN_LOG_POWER (per scene).
+   power_dev out [sum n_rx]; loss_dev out [n_scenes] or NULL;
+   grad_tx_dev out [n_scenes][2]; grad_walls_dev out [sum n_walls][4].
+   Enqueues only (no allocation, no memset): graph-capturable.  Calls on the
+   same plan must not overlap (they share its buffers). */
+int drt_batched_forward_backward(drt_plan* plan, const drt_batch* batch, int32_t loss_kind, float log_eps,
+                                 float* power_dev, float* loss_dev, float* grad_tx_dev,
+                                 float* grad_walls_dev, void* stream);
+
+/* Times every launch shape of a small grid (nw x cchunk x tile_w x
+   workgroups per CU) on this batch, keeps the fastest in the plan and, if
+   cache_path is not NULL, appends it there.  Synchronises; outputs hold the
+   last run's results. */
+int drt_batched_autotune(drt_plan* plan, const drt_batch* batch, int32_t loss_kind, float log_eps,
+                         float* power_dev, float* loss_dev, float* grad_tx_dev, float* grad_walls_dev,
+                         const char* cache_path, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

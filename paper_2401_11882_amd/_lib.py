@@ -33,6 +33,20 @@ class DrtScene(ctypes.Structure):
     ]
 
 
+class DrtBatchShape(ctypes.Structure):
+    _fields_ = [("n_scenes", c_int32), ("n_walls", ctypes.POINTER(c_int32)), ("n_rx", ctypes.POINTER(c_int32)),
+                ("rx_grid_nx", ctypes.POINTER(c_int32)), ("max_order", c_int32)]
+
+
+class DrtBatch(ctypes.Structure):
+    _fields_ = [("walls_dev", c_void_p), ("tx_dev", c_void_p), ("rx_dev", c_void_p), ("alpha_dev", c_void_p),
+                ("d_min", c_float)]
+
+
+class DrtPlanConfig(ctypes.Structure):
+    _fields_ = [("nw", c_int32), ("cchunk", c_int32), ("blocks_per_cu", c_int32), ("tile_w", c_int32)]
+
+
 class DrtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(msg)
@@ -55,6 +69,16 @@ _SIGS = {
                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "drt_adam_tx": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,
                      c_float, c_float, c_float, c_void_p], c_int32),
+    "drt_plan_create": ([ctypes.POINTER(DrtBatchShape), ctypes.c_char_p, ctypes.POINTER(c_void_p)], c_int32),
+    "drt_plan_destroy": ([c_void_p], c_int32),
+    "drt_plan_get_config": ([c_void_p, ctypes.POINTER(DrtPlanConfig)], c_int32),
+    "drt_plan_set_config": ([c_void_p, ctypes.POINTER(DrtPlanConfig)], c_int32),
+    "drt_plan_info": ([c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                       ctypes.POINTER(c_int32)], c_int32),
+    "drt_batched_forward_backward": ([c_void_p, ctypes.POINTER(DrtBatch), c_int32, c_float, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p], c_int32),
+    "drt_batched_autotune": ([c_void_p, ctypes.POINTER(DrtBatch), c_int32, c_float, c_void_p, c_void_p,
+                              c_void_p, c_void_p, ctypes.c_char_p, c_void_p], c_int32),
 }
 
 _lib = None

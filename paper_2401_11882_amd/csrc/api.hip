@@ -210,6 +210,14 @@ int enqueue_backward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A,
 
 extern "C" {
 
+// Error reporting shared with the other translation units of the library.
+__attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char* msg) {
+  g_err = msg ? msg : "";
+  return code;
+}
+
+__attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void) { return g_cache_limit; }
+
 int drt_abi_version(void) { return DRT_ABI_VERSION; }
 
 const char* drt_status_string(int status) {

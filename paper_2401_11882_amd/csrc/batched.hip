@@ -1,0 +1,261 @@
+// Many scenes in one persistent launch: forward, loss seed and adjoint fused
+// per work item.
+//
+// A work item is (scene, tile of 64 receivers).  Items are sorted by cost
+// (candidates x receivers, longest first) on the host when the plan is made.
+// The grid holds as many workgroups as fit on the GPU at once; each
+// workgroup takes items from a device counter until the list is exhausted
+// (every workgroup reaches that exit).  For its item the workgroup's NW
+// wavefronts split the scene's candidates, record their nonzero
+// contributions in the workgroup's own cache region, combine the per-wave
+// power sums in LDS (so P(r) is complete), form dL/dP(r), and then run the
+// adjoint from the recorded contributions.  Per-item gradient partials go to
+// a per-item slot; a second kernel sums each scene's items in a fixed order,
+// so results do not depend on which workgroup took which item.
+#include "batched.h"
+#include "path.h"
+
+namespace drt {
+
+__global__ void k_batch_reset(int* counter) { *counter = 0; }
+
+// Wall records and culling boxes for every wall of every scene (one
+// workgroup per scene, alpha per scene).
+__global__ void k_batch_prep(const float* __restrict__ walls, const int* __restrict__ wall_off,
+                             const float* __restrict__ alpha, WallRec* __restrict__ rec,
+                             WallBox* __restrict__ boxes) {
+  const int s = blockIdx.x;
+  const float c = kCullMargin / alpha[s];
+  for (int j = wall_off[s] + threadIdx.x; j < wall_off[s + 1]; j += blockDim.x) {
+    const float ax = walls[4 * j], ay = walls[4 * j + 1];
+    const float bx = walls[4 * j + 2], by = walls[4 * j + 3];
+    const float ex = bx - ax, ey = by - ay;
+    WallRec r;
+    r.ax = ax;
+    r.ay = ay;
+    r.ex = ex;
+    r.ey = ey;
+    r.axe = ax * ey - ay * ex;
+    r.pad0 = r.pad1 = r.pad2 = 0.0f;
+    rec[j] = r;
+    const float p0x = fmaf(-c, ex, ax), p0y = fmaf(-c, ey, ay);
+    const float p1x = fmaf(c, ex, bx), p1y = fmaf(c, ey, by);
+    WallBox q;
+    q.xmin = fminf(p0x, p1x);
+    q.xmax = fmaxf(p0x, p1x);
+    q.ymin = fminf(p0y, p1y);
+    q.ymax = fmaxf(p0y, p1y);
+    boxes[j] = q;
+  }
+}
+
+// Receiver of a lane for tiles of tw x (64/tw) receivers on a row-major grid
+// of nx columns (tw = 0 or nx = 0: 64 consecutive receivers).
+__device__ __forceinline__ int batch_rx_of_lane(int tile, int lane, int nx, int tw) {
+  if (nx > 0 && tw > 0) {
+    const int th = kWave / tw;
+    const int tpr = nx / tw;
+    const int ty = tile / tpr;
+    const int tx = tile - ty * tpr;
+    return (ty * th + lane / tw) * nx + tx * tw + (lane % tw);
+  }
+  return tile * kWave + lane;
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
+  extern __shared__ float smem[];
+  __shared__ int item_sh;
+  __shared__ float gsh[kWave];
+  const int ncol_max = 2 + 4 * B.max_walls;
+  float* accs = smem;                        // [NW][ncol_max]
+  float* red = smem + NW * ncol_max;         // [NW][2][64]
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = uniform(threadIdx.x >> 6);
+  const int slot = blockIdx.x * NW + wave;
+  float* cache_c = B.cache_c ? B.cache_c + (size_t)slot * B.cache_cap * kWave : nullptr;
+  int* cache_idx = B.cache_c ? B.cache_idx + (size_t)slot * B.cache_cap : nullptr;
+
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item_sh = atomicAdd(B.counter, 1);
+    __syncthreads();
+    const int it = item_sh;
+    if (it >= B.n_items) break;
+    const int s = B.items[2 * it], tile = B.items[2 * it + 1];
+    const int w0 = B.wall_off[s], W = B.wall_off[s + 1] - w0;
+    const int r0 = B.rx_off[s], R = B.rx_off[s + 1] - r0;
+    const int ncol = 2 + 4 * W;
+    const float alpha = B.alpha[s];
+    SceneView S;
+    S.walls = B.walls + w0;
+    S.boxes = B.boxes + w0;
+    S.n_walls = W;
+    S.alpha = alpha;
+    S.a2 = alpha * kLog2e;
+    S.band_k = 1.0f + 2.0f * kBandMargin / alpha;
+    S.cull_c = kCullMargin / alpha;
+    S.dmin2 = B.dmin2;
+    // number of candidates of this scene
+    int n_cand = 1, term = 0;
+    for (int k = 1; k <= B.max_order; ++k) {
+      term = (k == 1) ? W : term * (W - 1);
+      n_cand += term;
+    }
+    for (int i = threadIdx.x; i < NW * ncol; i += NW * kWave) accs[(i / ncol) * ncol_max + (i % ncol)] = 0.0f;
+
+    const int m = batch_rx_of_lane(tile, lane, B.grid_nx[s], B.tile_w);
+    const bool live = m < R;
+    const float rxx = live ? B.rx[2 * (r0 + m)] : 0.5f;
+    const float rxy = live ? B.rx[2 * (r0 + m) + 1] : 0.5f;
+    const float txx = B.tx[2 * s], txy = B.tx[2 * s + 1];
+
+    // -- forward over this wave's candidates, recording nonzero contributions
+    float sum = 0.0f, comp = 0.0f;
+    int nst = 0;
+    const int stride = NW * B.cchunk;
+    for (int c0 = wave * B.cchunk; c0 < n_cand; c0 += stride) {
+      const int c1 = min(c0 + B.cchunk, n_cand);
+      for (int c = c0; c < c1; ++c) {
+        const Cand cd = decode_candidate(c, W);
+        const float v = candidate_power(S, cd, txx, txy, rxx, rxy, live);
+        kahan_add(sum, comp, v);
+        if (cache_c && ballot(v != 0.0f) != 0) {
+          if (nst < B.cache_cap) {
+            cache_c[(size_t)nst * kWave + lane] = v;
+            if (lane == 0) cache_idx[nst] = c;
+          }
+          ++nst;
+        }
+      }
+    }
+    red[(wave * 2 + 0) * kWave + lane] = sum;
+    red[(wave * 2 + 1) * kWave + lane] = comp;
+    __syncthreads();
+    if (wave == 0) {
+      float sp = 0.0f, cs = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        kahan_add(sp, cs, red[(w * 2 + 0) * kWave + lane] - red[(w * 2 + 1) * kWave + lane]);
+      const float P = sp - cs;
+      float lp = 0.0f, g = 0.0f;
+      if (live) {
+        B.power[r0 + m] = P;
+        if (B.loss_kind == 1) {
+          lp = P;
+          g = 1.0f;
+        } else {
+          lp = logf(P + B.log_eps);
+          g = -1.0f / ((float)R * (P + B.log_eps));
+        }
+      }
+      gsh[lane] = g;
+      const float tot = wave_sum(lp);
+      if (lane == 0) B.loss_part[it] = tot;
+    }
+    __syncthreads();
+
+    // -- adjoint from the recorded contributions (or re-evaluation on overflow)
+    const float g = gsh[lane];
+    float* acc = accs + wave * ncol_max;
+    LaneGrad G{0.0f, 0.0f, 0.0f, 0.0f};
+    if (cache_c && nst <= B.cache_cap) {
+      for (int p = 0; p < nst; ++p) {
+        const int c = cache_idx[p];
+        const float Wl = g * cache_c[(size_t)p * kWave + lane];
+        if (ballot(Wl != 0.0f) == 0) continue;
+        const Cand cd = decode_candidate(c, W);
+        candidate_adjoint_known(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
+      }
+    } else {
+      for (int c0 = wave * B.cchunk; c0 < n_cand; c0 += stride) {
+        const int c1 = min(c0 + B.cchunk, n_cand);
+        for (int c = c0; c < c1; ++c) {
+          const Cand cd = decode_candidate(c, W);
+          candidate_adjoint(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
+        }
+      }
+    }
+    {
+      const float sx = wave_sum(G.tx_x), sy = wave_sum(G.tx_y);
+      if (lane == 0) {
+        acc[0] += sx;
+        acc[1] += sy;
+      }
+    }
+    __syncthreads();
+    float* part = B.grad_part + B.part_off[it];
+    for (int col = threadIdx.x; col < ncol; col += NW * kWave) {
+      float v = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += accs[w * ncol_max + col];
+      part[col] = v;
+    }
+  }
+}
+
+// Per scene: loss and gradients summed over the scene's items in item order.
+__global__ __launch_bounds__(256) void k_batch_reduce(BatchArgs B, float* __restrict__ loss,
+                                                      float* __restrict__ grad_tx,
+                                                      float* __restrict__ grad_walls) {
+  const int s = blockIdx.x;
+  const int i0 = B.scene_items[2 * s], i1 = i0 + B.scene_items[2 * s + 1];
+  const int w0 = B.wall_off[s], W = B.wall_off[s + 1] - w0;
+  const int ncol = 2 + 4 * W;
+  for (int col = threadIdx.x; col < ncol; col += blockDim.x) {
+    double t = 0.0;
+    for (int it = i0; it < i1; ++it) t += (double)B.grad_part[B.part_off[it] + col];
+    if (col < 2) grad_tx[2 * s + col] = (float)t;
+    else grad_walls[4 * (size_t)w0 + (col - 2)] = (float)t;
+  }
+  if (threadIdx.x == 0 && loss) {
+    double t = 0.0;
+    for (int it = i0; it < i1; ++it) t += (double)B.loss_part[it];
+    const int R = B.rx_off[s + 1] - B.rx_off[s];
+    const double scale = B.loss_kind == 1 ? 1.0 : (R > 0 ? -1.0 / (double)R : 0.0);
+    loss[s] = (float)(scale * t);
+  }
+}
+
+size_t batched_lds_bytes(int nw, int max_walls) {
+  return sizeof(float) * ((size_t)nw * (2 + 4 * (size_t)max_walls) + (size_t)nw * 2 * kWave);
+}
+
+template <int NW>
+static hipError_t batched_nw(const BatchArgs& B, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_batched<NW>, dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls), st,
+                     B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float* walls_raw, const float* alpha,
+                          int n_scenes, float* loss, float* grad_tx, float* grad_walls, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_prep, dim3(n_scenes), dim3(128), 0, st, walls_raw, B.wall_off, alpha,
+                     const_cast<WallRec*>(B.walls), const_cast<WallBox*>(B.boxes));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, B.counter);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  switch (nw) {
+    case 4: e = batched_nw<4>(B, n_blocks, st); break;
+    case 8: e = batched_nw<8>(B, n_blocks, st); break;
+    case 16: e = batched_nw<16>(B, n_blocks, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_reduce, dim3(n_scenes), dim3(256), 0, st, B, loss, grad_tx, grad_walls);
+  return hipGetLastError();
+}
+
+int batched_max_blocks_per_cu(int nw, int max_walls) {
+  int nb = 0;
+  const void* fn = nw == 4 ? reinterpret_cast<const void*>(k_batched<4>)
+                 : nw == 8 ? reinterpret_cast<const void*>(k_batched<8>)
+                           : reinterpret_cast<const void*>(k_batched<16>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nw * kWave, batched_lds_bytes(nw, max_walls)) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace drt

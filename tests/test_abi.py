@@ -127,3 +127,20 @@ def test_call_validation_before_launch():
     assert L.drt_set_launch_config(3, 0) == _lib.DRT_EINVAL
     assert L.drt_set_launch_config(0, -1) == _lib.DRT_EINVAL
     assert L.drt_set_launch_config(0, 0) == 0
+
+
+def test_plan_create_validation():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    W = (ctypes.c_int32 * 2)(10, 12)
+    R = (ctypes.c_int32 * 2)(64, 100)
+    bad = (ctypes.c_int32 * 2)(10, -3)
+    assert L.drt_plan_create(None, None, ctypes.byref(h)) == _lib.DRT_EINVAL
+    assert L.drt_plan_create(ctypes.byref(_lib.DrtBatchShape(0, W, R, None, 2)), None, ctypes.byref(h)) == _lib.DRT_EINVAL
+    assert L.drt_plan_create(ctypes.byref(_lib.DrtBatchShape(2, W, R, None, 4)), None, ctypes.byref(h)) == _lib.DRT_EINVAL
+    assert L.drt_plan_create(ctypes.byref(_lib.DrtBatchShape(2, bad, R, None, 2)), None, ctypes.byref(h)) == _lib.DRT_EINVAL
+    assert L.drt_plan_create(ctypes.byref(_lib.DrtBatchShape(2, W, None, None, 2)), None, ctypes.byref(h)) == _lib.DRT_EINVAL
+    assert h.value is None
+    assert L.drt_plan_destroy(None) == 0
+    assert L.drt_batched_forward_backward(None, None, 2, 1e-6, None, None, None, None, None) == _lib.DRT_EINVAL
+    assert L.drt_plan_get_config(None, None) == _lib.DRT_EINVAL

@@ -1,0 +1,139 @@
+"""Batched persistent launch: parity with single-scene launches and the oracle."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tracer as T
+from paper_2401_11882_amd import workloads as WL
+
+import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    from paper_2401_11882_amd import batched, tracer
+    return batched, tracer
+
+
+def _single(tr, s, loss="neg_mean_log"):
+    dev = torch.device("cuda")
+    sc = tr.Scene(torch.tensor(s.walls, device=dev), torch.tensor(s.tx, device=dev), torch.tensor(s.rx, device=dev),
+                  s.max_order, s.alpha, grid_nx=s.grid_n)
+    return [t.clone() for t in tr.forward_backward(sc, loss=loss)[:4]]
+
+
+def _small_mixed():
+    """Uneven small scenes: different wall counts, grid sizes, a ragged receiver list, alphas."""
+    out = []
+    for i, (n_int, n, alpha) in enumerate([(3, 8, 100.0), (7, 16, 30.0), (1, 8, 1000.0), (5, 0, 100.0), (0, 8, 100.0)]):
+        s = WL.scene_random_box(3, n_int, max(n, 1), 2, alpha, seed=100 + i)
+        if n == 0:
+            s.rx = WL.random_points(3, i, 77)
+            s.grid_n = 0
+        out.append(s)
+    return out
+
+
+def test_batched_small_vs_oracle():
+    batched, tr = _mods()
+    scenes = _small_mixed()
+    plan = batched.BatchPlan(scenes, 2)
+    P, L, gtx, gw = [t.cpu().numpy() for t in plan.run()]
+    for s_i, s in enumerate(scenes):
+        rs, ws = plan.scene_slice(s_i)
+        P_o, L_o, gw_o, gt_o, _ = T.forward_backward(s.walls, s.tx, s.rx, 2, s.alpha)
+        _, kap = PU.kappa(s.walls, s.tx, s.rx, 2, s.alpha, P0=P_o)
+        PU.check_power(P[rs], P_o, kap, f"batched scene {s_i}")
+        assert L[s_i] == pytest.approx(L_o, rel=1e-5)
+        PU.check_grads(gtx[s_i], gw[ws], gt_o, gw_o, f"batched scene {s_i}")
+    plan.close()
+
+
+def test_batched_matches_single_scene_launches():
+    batched, tr = _mods()
+    scenes = WL.batch_scenes(12, side_cap=32)
+    plan = batched.BatchPlan(scenes, 2)
+    P, L, gtx, gw = [t.clone() for t in plan.run()]
+    for s_i, s in enumerate(scenes):
+        rs, ws = plan.scene_slice(s_i)
+        P1, L1, g1, w1 = _single(tr, s)
+        torch.testing.assert_close(P[rs], P1, rtol=2e-6, atol=0)
+        torch.testing.assert_close(L[s_i:s_i + 1], L1, rtol=2e-6, atol=0)
+        assert PU.rel_l2(gtx[s_i].cpu().numpy(), g1.cpu().numpy()) < 1e-5
+        assert PU.rel_l2(gw[ws].cpu().numpy(), w1.cpu().numpy()) < 1e-5
+    plan.close()
+
+
+def test_batched_deterministic_and_graph_replay():
+    batched, tr = _mods()
+    scenes = WL.batch_scenes(16, side_cap=16)
+    plan = batched.BatchPlan(scenes, 2)
+    a = [t.clone() for t in plan.run()]
+    b = [t.clone() for t in plan.run()]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            plan.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in plan.out:
+            t.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(plan.out, a):
+            assert torch.equal(x, y), f"replay {rep}"
+        _ = float(plan.out[1].sum())
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    batched, tr = _mods()
+    scenes = WL.batch_scenes(24, side_cap=32)
+    ref_plan = batched.BatchPlan(scenes, 2)
+    ref = [t.clone() for t in ref_plan.run()]
+    ref_plan.close()
+    cache = str(tmp_path / "tune.txt")
+    plan = batched.BatchPlan(scenes, 2)
+    best = plan.autotune(cache_path=cache)
+    out = plan.run()
+    for x, y in zip(out, ref):
+        torch.testing.assert_close(x, y, rtol=1e-5, atol=1e-6 * float(y.abs().max()))
+    plan.close()
+    assert os.path.getsize(cache) > 0
+    plan2 = batched.BatchPlan(scenes, 2, tune_cache=cache)
+    assert plan2.config() == best
+    plan2.close()
+
+
+def test_full_batch_512_sampled():
+    """512 scenes, 8..128 interior segments, 64^2..256^2 receivers, order <= 2, alpha 100:
+    one launch; sampled receivers of sampled scenes vs the oracle, two scenes vs single launches."""
+    batched, tr = _mods()
+    scenes = WL.batch_scenes(512)
+    plan = batched.BatchPlan(scenes, 2)
+    info = plan.info()
+    assert info["items"] == sum((s.n_rx + 63) // 64 for s in scenes)
+    P, L, gtx, gw = [t.cpu() for t in plan.run()]
+    assert torch.isfinite(P).all() and torch.isfinite(gw).all() and torch.isfinite(gtx).all()
+    rng = np.random.default_rng(5)
+    for s_i in rng.choice(512, size=4, replace=False):
+        s = scenes[s_i]
+        rs, ws = plan.scene_slice(s_i)
+        idx = rng.choice(s.n_rx, size=6, replace=False)
+        P_o, kap = PU.kappa(s.walls, s.tx, s.rx[idx], 2, s.alpha)
+        PU.check_power(P[rs].numpy()[idx], P_o, kap, f"scene {s_i}")
+    for s_i in (0, 511):
+        s = scenes[s_i]
+        rs, ws = plan.scene_slice(s_i)
+        P1, L1, g1, w1 = [t.cpu() for t in _single(tr, s)]
+        torch.testing.assert_close(P[rs], P1, rtol=2e-6, atol=0)
+        assert PU.rel_l2(gtx[s_i].numpy(), g1.numpy()) < 1e-5
+        assert PU.rel_l2(gw[ws].numpy(), w1.numpy()) < 1e-5
+    plan.close()
