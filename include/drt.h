@@ -230,7 +230,9 @@ int drt_plan_set_config(drt_plan* plan, const drt_plan_config* cfg);
 int drt_plan_info(const drt_plan* plan, int64_t* n_items, int64_t* path_evals, int32_t* cache_cap);
 
 /* Forward, per-scene loss and adjoint of every scene in one persistent launch.
-   loss_kind: DRT_LOSS_SUM_POWER or DRT_LOSS_NEG_MEAN_LOG_POWER (per scene).
+   loss_kind: DRT_LOSS_SUM_POWER or DRT_LOSS_NEG_MEAN_LOG_POWER (per scene),
+   or DRT_LOSS_NONE for the power maps only (loss and gradient outputs are
+   then ignored and may be NULL).
    power_dev out [sum n_rx]; loss_dev out [n_scenes] or NULL;
    grad_tx_dev out [n_scenes][2]; grad_walls_dev out [sum n_walls][4].
    Enqueues only (no allocation, no memset): graph-capturable.  Calls on the
@@ -246,6 +248,62 @@ int drt_batched_forward_backward(drt_plan* plan, const drt_batch* batch, int32_t
 int drt_batched_autotune(drt_plan* plan, const drt_batch* batch, int32_t loss_kind, float log_eps,
                          float* power_dev, float* loss_dev, float* grad_tx_dev, float* grad_walls_dev,
                          const char* cache_path, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the log smoothed power map
+ *
+ * yhat(tx, rx) ~ log(P(rx; tx) + eps) for one scene: Fourier features
+ * gamma(v) = [sin(2 pi B v), cos(2 pi B v)] of v = (tx, rx) in [0,1]^4 with a
+ * fixed B [64][4] (128 inputs), then 5 ReLU layers of width 256 and a linear
+ * head (296,449 parameters).  Hidden layers run as BF16 MFMA GEMMs with FP32
+ * accumulation; activations are stored in BF16; master weights, biases and
+ * Adam moments are FP32.  Trained by MSE on data the tracer generates
+ * (drt_batched_forward_backward / drt_log_targets) and used to rank
+ * transmitter positions before refinement with the exact tracer.
+ *
+ * Flat FP32 parameter layout (drt_mlp_num_params floats): for each hidden
+ * layer l = 0..4, W_l [in][out] row-major (in = 128 for l = 0, else 256;
+ * out = 256) followed by b_l [256]; then the head w [256] and b [1].
+ * ------------------------------------------------------------------------ */
+
+typedef struct drt_mlp drt_mlp;  /* opaque; owns its device buffers */
+
+/* Number of parameters (296,449). */
+int drt_mlp_num_params(int64_t* n);
+
+/* Creates a network on the current device from host arrays: fourier_B_host
+   [64][4], params_host [drt_mlp_num_params] (flat layout above).  max_batch:
+   rows per training step / inference chunk, a multiple of 64 (<= 2^24);
+   the handle allocates activation buffers for it.  Allocates and
+   synchronises. */
+int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_t max_batch, drt_mlp** out);
+int drt_mlp_destroy(drt_mlp* mlp);
+
+/* Host copies of the FP32 master parameters (synchronising). */
+int drt_mlp_get_params(const drt_mlp* mlp, float* params_host);
+int drt_mlp_set_params(drt_mlp* mlp, const float* params_host);
+
+/* Loss L = (1/n) sum (yhat - y)^2 over rows v_dev [n][4], y_dev [n] and its
+   gradient w.r.t. every parameter into grads_dev [num_params] (or NULL),
+   loss into loss_dev [1] (or NULL).  n: positive multiple of 64, <= max_batch. */
+int drt_mlp_grads(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t n, float* grads_dev,
+                  float* loss_dev, void* stream);
+
+/* drt_mlp_grads followed by one Adam step (beta 0.9 / 0.999, eps 1e-8, torch
+   semantics, step count kept on the device) and the BF16 weight copies. */
+int drt_mlp_train_step(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t n, float lr,
+                       float* loss_dev, void* stream);
+
+/* yhat_dev [n] for inputs v_dev [n][4] (any n >= 0; processed in chunks). */
+int drt_mlp_forward(drt_mlp* mlp, const float* v_dev, int64_t n, float* yhat_dev, void* stream);
+
+/* F_dev[t] = mean over receivers rx_dev [n_rx][2] of yhat(tx_dev[t], rx), for
+   t < n_tx (tx_dev [n_tx][2]).  Needs 0 < n_rx <= max_batch. */
+int drt_mlp_scan(drt_mlp* mlp, const float* tx_dev, int32_t n_tx, const float* rx_dev, int32_t n_rx,
+                 float* F_dev, void* stream);
+
+/* y_dev[i] = log(power_dev[i] + eps), the surrogate's training target. */
+int drt_log_targets(const float* power_dev, int64_t n, float eps, float* y_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -79,6 +79,16 @@ _SIGS = {
                                       c_void_p, c_void_p, c_void_p], c_int32),
     "drt_batched_autotune": ([c_void_p, ctypes.POINTER(DrtBatch), c_int32, c_float, c_void_p, c_void_p,
                               c_void_p, c_void_p, ctypes.c_char_p, c_void_p], c_int32),
+    "drt_mlp_num_params": ([ctypes.POINTER(ctypes.c_int64)], c_int32),
+    "drt_mlp_create": ([c_void_p, c_void_p, c_int32, ctypes.POINTER(c_void_p)], c_int32),
+    "drt_mlp_destroy": ([c_void_p], c_int32),
+    "drt_mlp_get_params": ([c_void_p, c_void_p], c_int32),
+    "drt_mlp_set_params": ([c_void_p, c_void_p], c_int32),
+    "drt_mlp_grads": ([c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p], c_int32),
+    "drt_mlp_train_step": ([c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p, c_void_p], c_int32),
+    "drt_mlp_forward": ([c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p], c_int32),
+    "drt_mlp_scan": ([c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p], c_int32),
+    "drt_log_targets": ([c_void_p, ctypes.c_int64, c_float, c_void_p, c_void_p], c_int32),
 }
 
 _lib = None

@@ -60,7 +60,9 @@ class BatchPlan:
                         self.rx.data_ptr() if self.rx.numel() else None, self.alpha.data_ptr(), self.d_min)
 
     def run(self, loss: str = "neg_mean_log", log_eps: float = DEFAULT_LOG_EPS, stream=None):
-        """(power [sum R], loss [S], grad_tx [S,2], grad_walls [sum W,4]) in the plan's own buffers."""
+        """(power [sum R], loss [S], grad_tx [S,2], grad_walls [sum W,4]) in the plan's own buffers.
+
+        loss='none' computes the power maps only (the other outputs are left as they were)."""
         P, L, gtx, gw = self.out
         b = self._batch()
         check(lib().drt_batched_forward_backward(self._h, ctypes.byref(b), _lib.LOSS[loss], float(log_eps),

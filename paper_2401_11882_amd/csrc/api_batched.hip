@@ -189,8 +189,12 @@ int enqueue(drt_plan* p, const drt_batch* b, int loss_kind, float log_eps, float
 }
 
 int check_outputs(const drt_plan* p, int loss_kind, float log_eps, float* power, float* gtx, float* gw) {
-  if (!(loss_kind == DRT_LOSS_SUM_POWER || loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER))
-    return failf(DRT_EINVAL, "loss_kind=%d: batched calls need SUM_POWER or NEG_MEAN_LOG_POWER", loss_kind);
+  if (loss_kind < DRT_LOSS_NONE || loss_kind > DRT_LOSS_NEG_MEAN_LOG_POWER)
+    return failf(DRT_EINVAL, "loss_kind=%d unknown", loss_kind);
+  if (loss_kind == DRT_LOSS_NONE) {
+    if (p->sum_rx > 0 && !power) return failf(DRT_EINVAL, "power_dev is NULL");
+    return DRT_OK;
+  }
   if (loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER && (!std::isfinite(log_eps) || !(log_eps > 0.0f)))
     return failf(DRT_EINVAL, "log_eps must be finite and > 0");
   if (p->sum_rx > 0 && !power) return failf(DRT_EINVAL, "power_dev is NULL");

@@ -1,0 +1,319 @@
+// C ABI of the learned surrogate: handle with device buffers, training step
+// (forward, MSE, backward, Adam), gradients, inference and tx scan.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/drt.h"
+#include "mlp.h"
+
+extern "C" __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char* msg);
+
+namespace {
+
+int failf(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int failf(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return drt_internal_fail(code, buf);
+}
+
+drt::MlpLayout make_layout() {
+  drt::MlpLayout L{};
+  int off = 0, boff = 0;
+  for (int l = 0; l < drt::kMlpHidden; ++l) {
+    L.fan_in[l] = l == 0 ? drt::kMlpIn : drt::kMlpWidth;
+    L.w_off[l] = off;
+    off += L.fan_in[l] * drt::kMlpWidth;
+    L.b_off[l] = off;
+    off += drt::kMlpWidth;
+    L.bf_off[l] = boff;
+    boff += L.fan_in[l] * drt::kMlpWidth;
+  }
+  L.head_w = off;
+  off += drt::kMlpWidth;
+  L.head_b = off;
+  off += 1;
+  L.n_params = off;
+  L.n_bf = boff;
+  return L;
+}
+
+}  // namespace
+
+struct drt_mlp {
+  int device = 0;
+  int max_batch = 0;
+  int max_slices = 0;
+  drt::MlpLayout L{};
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *Bf = nullptr;
+  int* step = nullptr;
+  __bf16 *wbf = nullptr, *wtbf = nullptr, *X0 = nullptr, *H = nullptr, *dZ0 = nullptr, *dZ1 = nullptr;
+  float *yhat = nullptr, *gvec = nullptr, *loss_part = nullptr, *dw_part = nullptr;
+};
+
+namespace {
+
+void free_mlp(drt_mlp* h) {
+  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->X0, h->H, h->dZ0, h->dZ1,
+                  h->yhat, h->gvec, h->loss_part, h->dw_part};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+}
+
+__bf16* Hl(drt_mlp* h, int l) { return h->H + (size_t)l * h->max_batch * drt::kMlpWidth; }
+
+#define HIPCHK(expr, what)                                                            \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return failf(DRT_EHIP, "%s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+// Hidden layers on n rows whose features are in X0: H_l = relu(X_l W_l + b_l).
+int enqueue_hidden(drt_mlp* h, int n, hipStream_t st) {
+  for (int l = 0; l < drt::kMlpHidden; ++l) {
+    drt::GemmArgs g{};
+    g.A = l == 0 ? h->X0 : Hl(h, l - 1);
+    g.lda = h->L.fan_in[l];
+    g.B = h->wtbf + h->L.bf_off[l];  // W^T [out][in]: B(k=in, n=out) = Wt[n * in + k]
+    g.ldb = h->L.fan_in[l];
+    g.M = n;
+    g.N = drt::kMlpWidth;
+    g.K = h->L.fan_in[l];
+    g.k_split = g.K;
+    g.bias = h->p + h->L.b_off[l];
+    g.relu = 1;
+    g.out_bf16 = Hl(h, l);
+    HIPCHK(drt::launch_gemm(g, false, false, 1, st), "hidden gemm");
+  }
+  return DRT_OK;
+}
+
+// Forward + MSE + backward on rows [0, n) of v/y; gradients into h->g, loss
+// (mean squared error over n) into loss_dev.
+int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss_dev, hipStream_t st) {
+  HIPCHK(drt::launch_features(v, nullptr, nullptr, 1, 0, n, h->Bf, h->X0, st), "features");
+  int rc = enqueue_hidden(h, n, st);
+  if (rc) return rc;
+  const drt::MlpLayout& L = h->L;
+  const int W = drt::kMlpWidth;
+  HIPCHK(drt::launch_head(Hl(h, 4), n, h->p + L.head_w, h->p + L.head_b, y, 1.0f / (float)n, h->yhat, h->loss_part,
+                          h->gvec, h->dZ0, st),
+         "head");
+  HIPCHK(drt::launch_colsum(Hl(h, 4), n, W, h->gvec, h->g + L.head_w, st), "head weight grad");
+  HIPCHK(drt::launch_sum_scalar(h->gvec, n, 1.0, h->g + L.head_b, st), "head bias grad");
+  if (loss_dev) HIPCHK(drt::launch_sum_scalar(h->loss_part, n, 1.0 / (double)n, loss_dev, st), "loss");
+  // split of the batch dimension for the weight gradients
+  int k_split = ((n + h->max_slices - 1) / h->max_slices + 63) / 64 * 64;
+  if (k_split < 64) k_split = 64;
+  const int slices = (n + k_split - 1) / k_split;
+  __bf16* dZ = h->dZ0;
+  __bf16* dZn = h->dZ1;
+  for (int l = drt::kMlpHidden - 1; l >= 0; --l) {
+    const int fi = L.fan_in[l];
+    HIPCHK(drt::launch_colsum(dZ, n, W, nullptr, h->g + L.b_off[l], st), "bias grad");
+    drt::GemmArgs g{};
+    g.A = l == 0 ? h->X0 : Hl(h, l - 1);  // A(m = in, k = row) = X[row * fi + in]
+    g.lda = fi;
+    g.B = dZ;                             // B(k = row, n = out) = dZ[row * 256 + out]
+    g.ldb = W;
+    g.M = fi;
+    g.N = W;
+    g.K = n;
+    g.k_split = k_split;
+    g.out_f32 = h->dw_part;
+    HIPCHK(drt::launch_gemm(g, true, true, slices, st), "weight grad gemm");
+    HIPCHK(drt::launch_sum_slices(h->dw_part, slices, fi * W, h->g + L.w_off[l], st), "weight grad sum");
+    if (l > 0) {
+      drt::GemmArgs d{};
+      d.A = dZ;                            // [n][256]
+      d.lda = W;
+      d.B = h->wbf + L.bf_off[l];          // W [in][out]: B(k = out, n = in) = W[n * 256 + k]
+      d.ldb = W;
+      d.M = n;
+      d.N = fi;
+      d.K = W;
+      d.k_split = W;
+      d.mask = Hl(h, l - 1);               // ReLU derivative of the layer below
+      d.out_bf16 = dZn;
+      HIPCHK(drt::launch_gemm(d, false, false, 1, st), "input grad gemm");
+      std::swap(dZ, dZn);
+    }
+  }
+  return DRT_OK;
+}
+
+int check_rows(const drt_mlp* h, int64_t n) {
+  if (!h) return failf(DRT_EINVAL, "mlp is NULL");
+  if (n <= 0 || n > h->max_batch || n % 64 != 0)
+    return failf(DRT_EINVAL, "rows=%lld must be a positive multiple of 64 and <= max_batch=%d", (long long)n,
+                 h->max_batch);
+  return DRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int drt_mlp_num_params(int64_t* n) {
+  if (!n) return failf(DRT_EINVAL, "n is NULL");
+  *n = make_layout().n_params;
+  return DRT_OK;
+}
+
+int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_t max_batch, drt_mlp** out) {
+  if (!out) return failf(DRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!fourier_B_host || !params_host) return failf(DRT_EINVAL, "NULL host array");
+  if (max_batch <= 0 || max_batch % 64 != 0 || max_batch > (1 << 24))
+    return failf(DRT_EINVAL, "max_batch=%d must be a positive multiple of 64 up to 2^24", max_batch);
+  drt_mlp* h = new (std::nothrow) drt_mlp();
+  if (!h) return failf(DRT_EINVAL, "out of host memory");
+  h->L = make_layout();
+  h->max_batch = max_batch;
+  h->max_slices = 64;
+  const size_t P = h->L.n_params, nb = (size_t)max_batch, W = drt::kMlpWidth;
+  hipError_t e = hipGetDevice(&h->device);
+  auto alloc = [&e](void** ptr, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+  };
+  alloc((void**)&h->p, P * 4);
+  alloc((void**)&h->g, P * 4);
+  alloc((void**)&h->m, P * 4);
+  alloc((void**)&h->v, P * 4);
+  alloc((void**)&h->Bf, drt::kMlpFreq * 4 * 4);
+  alloc((void**)&h->step, 16);
+  alloc((void**)&h->wbf, (size_t)h->L.n_bf * 2);
+  alloc((void**)&h->wtbf, (size_t)h->L.n_bf * 2);
+  alloc((void**)&h->X0, nb * drt::kMlpIn * 2);
+  alloc((void**)&h->H, nb * W * 2 * drt::kMlpHidden);
+  alloc((void**)&h->dZ0, nb * W * 2);
+  alloc((void**)&h->dZ1, nb * W * 2);
+  alloc((void**)&h->yhat, nb * 4);
+  alloc((void**)&h->gvec, nb * 4);
+  alloc((void**)&h->loss_part, nb * 4);
+  alloc((void**)&h->dw_part, (size_t)h->max_slices * W * W * 4);
+  if (e == hipSuccess) e = hipMemcpy(h->p, params_host, P * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->Bf, fourier_B_host, drt::kMlpFreq * 4 * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(h->m, 0, P * 4);
+  if (e == hipSuccess) e = hipMemset(h->v, 0, P * 4);
+  if (e == hipSuccess) e = hipMemset(h->g, 0, P * 4);
+  if (e == hipSuccess) e = hipMemset(h->step, 0, 16);
+  if (e == hipSuccess) e = drt::launch_mlp_copies(h->p, h->L.n_params, h->L, h->wbf, h->wtbf, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_mlp(h);
+    delete h;
+    return failf(DRT_EHIP, "mlp buffers: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return DRT_OK;
+}
+
+int drt_mlp_destroy(drt_mlp* mlp) {
+  if (!mlp) return DRT_OK;
+  (void)hipSetDevice(mlp->device);
+  (void)hipDeviceSynchronize();
+  free_mlp(mlp);
+  delete mlp;
+  return DRT_OK;
+}
+
+int drt_mlp_get_params(const drt_mlp* mlp, float* params_host) {
+  if (!mlp || !params_host) return failf(DRT_EINVAL, "NULL argument");
+  hipError_t e = hipMemcpy(params_host, mlp->p, (size_t)mlp->L.n_params * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return failf(DRT_EHIP, "download: %s", hipGetErrorString(e));
+  return DRT_OK;
+}
+
+int drt_mlp_set_params(drt_mlp* mlp, const float* params_host) {
+  if (!mlp || !params_host) return failf(DRT_EINVAL, "NULL argument");
+  hipError_t e = hipMemcpy(mlp->p, params_host, (size_t)mlp->L.n_params * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = drt::launch_mlp_copies(mlp->p, mlp->L.n_params, mlp->L, mlp->wbf, mlp->wtbf, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return failf(DRT_EHIP, "upload: %s", hipGetErrorString(e));
+  return DRT_OK;
+}
+
+int drt_mlp_grads(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t n, float* grads_dev,
+                  float* loss_dev, void* stream) {
+  int rc = check_rows(mlp, n);
+  if (rc) return rc;
+  if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, st))) return rc;
+  if (grads_dev) HIPCHK(hipMemcpyAsync(grads_dev, mlp->g, (size_t)mlp->L.n_params * 4, hipMemcpyDeviceToDevice, st),
+                        "grad copy");
+  return DRT_OK;
+}
+
+int drt_mlp_train_step(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t n, float lr,
+                       float* loss_dev, void* stream) {
+  int rc = check_rows(mlp, n);
+  if (rc) return rc;
+  if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return failf(DRT_EINVAL, "lr must be finite and > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, st))) return rc;
+  HIPCHK(drt::launch_adam_mlp(mlp->p, mlp->g, mlp->m, mlp->v, mlp->step, mlp->L.n_params, lr, 0.9f, 0.999f, 1e-8f,
+                              mlp->L, mlp->wbf, mlp->wtbf, st),
+         "adam");
+  return DRT_OK;
+}
+
+int drt_mlp_forward(drt_mlp* mlp, const float* v_dev, int64_t n, float* yhat_dev, void* stream) {
+  if (!mlp) return failf(DRT_EINVAL, "mlp is NULL");
+  if (n < 0) return failf(DRT_EINVAL, "n is negative");
+  if (n > 0 && (!v_dev || !yhat_dev)) return failf(DRT_EINVAL, "v_dev / yhat_dev is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int64_t r0 = 0; r0 < n; r0 += mlp->max_batch) {
+    const int rows = (int)std::min<int64_t>(mlp->max_batch, n - r0);
+    HIPCHK(drt::launch_features(v_dev + 4 * r0, nullptr, nullptr, 1, 0, rows, mlp->Bf, mlp->X0, st), "features");
+    int rc = enqueue_hidden(mlp, rows, st);
+    if (rc) return rc;
+    HIPCHK(drt::launch_head(Hl(mlp, 4), rows, mlp->p + mlp->L.head_w, mlp->p + mlp->L.head_b, nullptr, 0.0f,
+                            yhat_dev + r0, nullptr, nullptr, nullptr, st),
+           "head");
+  }
+  return DRT_OK;
+}
+
+int drt_mlp_scan(drt_mlp* mlp, const float* tx_dev, int32_t n_tx, const float* rx_dev, int32_t n_rx,
+                 float* F_dev, void* stream) {
+  if (!mlp) return failf(DRT_EINVAL, "mlp is NULL");
+  if (n_tx < 0 || n_rx <= 0 || n_rx > mlp->max_batch)
+    return failf(DRT_EINVAL, "n_tx=%d n_rx=%d (need 0 < n_rx <= max_batch=%d)", n_tx, n_rx, mlp->max_batch);
+  if (n_tx > 0 && (!tx_dev || !rx_dev || !F_dev)) return failf(DRT_EINVAL, "NULL device array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int per = mlp->max_batch / n_rx;  // transmitters per chunk
+  for (int t0 = 0; t0 < n_tx; t0 += per) {
+    const int nt = std::min(per, n_tx - t0);
+    const int rows = nt * n_rx;
+    HIPCHK(drt::launch_features(nullptr, tx_dev, rx_dev, n_rx, (long long)t0 * n_rx, rows, mlp->Bf, mlp->X0, st),
+           "features");
+    int rc = enqueue_hidden(mlp, rows, st);
+    if (rc) return rc;
+    HIPCHK(drt::launch_head(Hl(mlp, 4), rows, mlp->p + mlp->L.head_w, mlp->p + mlp->L.head_b, nullptr, 0.0f,
+                            mlp->yhat, nullptr, nullptr, nullptr, st),
+           "head");
+    HIPCHK(drt::launch_segment_mean(mlp->yhat, nt, n_rx, F_dev + t0, st), "segment mean");
+  }
+  return DRT_OK;
+}
+
+int drt_log_targets(const float* power_dev, int64_t n, float eps, float* y_dev, void* stream) {
+  if (n < 0) return failf(DRT_EINVAL, "n is negative");
+  if (n > 0 && (!power_dev || !y_dev)) return failf(DRT_EINVAL, "NULL device array");
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return failf(DRT_EINVAL, "eps must be finite and > 0");
+  if (n == 0) return DRT_OK;
+  HIPCHK(drt::launch_log_eps(power_dev, n, eps, y_dev, static_cast<hipStream_t>(stream)), "log targets");
+  return DRT_OK;
+}
+
+}  // extern "C"

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
         const Cand cd = decode_candidate(c, W);
         const float v = candidate_power(S, cd, txx, txy, rxx, rxy, live);
         kahan_add(sum, comp, v);
-        if (cache_c && ballot(v != 0.0f) != 0) {
+        if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
           if (nst < B.cache_cap) {
             cache_c[(size_t)nst * kWave + lane] = v;
             if (lane == 0) cache_idx[nst] = c;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
         if (B.loss_kind == 1) {
           lp = P;
           g = 1.0f;
-        } else {
+        } else if (B.loss_kind == 2) {
           lp = logf(P + B.log_eps);
           g = -1.0f / ((float)R * (P + B.log_eps));
         }
@@ -153,6 +153,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
       const float tot = wave_sum(lp);
       if (lane == 0) B.loss_part[it] = tot;
     }
+    if (B.loss_kind == 0) continue;  // forward only (the loop head synchronises)
     __syncthreads();
 
     // -- adjoint from the recorded contributions (or re-evaluation on overflow)
@@ -243,6 +244,7 @@ hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float*
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  if (B.loss_kind == 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_reduce, dim3(n_scenes), dim3(256), 0, st, B, loss, grad_tx, grad_walls);
   return hipGetLastError();
 }

@@ -1,0 +1,372 @@
+// Learned surrogate of the log smoothed power map: Fourier features of
+// (tx, rx) and a 6-layer ReLU MLP (128 -> 256 x 5 -> 1), trained and evaluated
+// with BF16 MFMA (v_mfma_f32_16x16x32_bf16) and FP32 accumulation.
+//
+// Layouts (row-major): features X0 [n][128] bf16; hidden activations
+// H_l [n][256] bf16; weights of hidden layer l as bf16 in two copies,
+// W [in][out] and W^T [out][in]; master weights, biases, Adam moments FP32 in
+// one flat vector: per hidden layer W_l [in][out] then b_l [out], then the
+// head w5 [256], b5 [1].
+#include "dev.h"
+#include "mlp.h"
+
+namespace drt {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+// ---------------------------------------------------------------------------
+// Fourier features: gamma(v) = [sin(2 pi B v), cos(2 pi B v)], v in R^4.
+// Rows come from v [n][4], or (pairs mode) from tx[row / R], rx[row % R].
+// ---------------------------------------------------------------------------
+__global__ void k_features(const float* __restrict__ v, const float* __restrict__ tx,
+                           const float* __restrict__ rx, int R, long long row0, int n,
+                           const float* __restrict__ Bf, bf16* __restrict__ X0) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)n * 64) return;
+  const int row = (int)(gid >> 6), f = (int)(gid & 63);
+  float x0, x1, x2, x3;
+  if (v) {
+    x0 = v[4 * (size_t)row];
+    x1 = v[4 * (size_t)row + 1];
+    x2 = v[4 * (size_t)row + 2];
+    x3 = v[4 * (size_t)row + 3];
+  } else {
+    const long long g = row0 + row;
+    const int t = (int)(g / R), r = (int)(g % R);
+    x0 = tx[2 * t];
+    x1 = tx[2 * t + 1];
+    x2 = rx[2 * r];
+    x3 = rx[2 * r + 1];
+  }
+  const float tt = Bf[4 * f] * x0 + Bf[4 * f + 1] * x1 + Bf[4 * f + 2] * x2 + Bf[4 * f + 3] * x3;
+  float s, c;
+  sincospif(2.0f * tt, &s, &c);  // sin / cos of 2 pi tt with argument reduction in units of pi
+  X0[(size_t)row * 128 + f] = (bf16)s;
+  X0[(size_t)row * 128 + 64 + f] = (bf16)c;
+}
+
+// ---------------------------------------------------------------------------
+// C[M x N] = A[M x K] . B[K x N], BF16 in, FP32 accumulate.
+//   A(m, k) = A[m * lda + k]          (A_MC = false)
+//           = A[k * lda + m]          (A_MC = true)
+//   B(k, n) = B[n * ldb + k]          (B_NC = false)
+//           = B[k * ldb + n]          (B_NC = true)
+// Tile 64 x 64 x 64 per workgroup of 4 wavefronts (2 x 2, 32 x 32 each, as
+// 2 x 2 MFMA 16x16x32 tiles).  Both operand tiles sit in LDS with k
+// contiguous so every fragment is one 16-byte LDS read.  gridDim.z splits K
+// (k_split per slice); slice z writes out_f32 + z * M * N.
+// Epilogue: + bias[n], ReLU, * (mask[m][n] > 0), then FP32 and/or BF16 out.
+// Requires N % 64 == 0, K % 64 == 0, k_split % 64 == 0, lda / ldb % 8 == 0.
+// ---------------------------------------------------------------------------
+constexpr int GT = 64;          // tile edge
+constexpr int GLD = GT + 8;     // LDS row stride (bf16), 144 bytes
+
+template <bool A_MC, bool B_NC>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) bf16 As[GT * GLD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[GT * GLD];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  const int kb = blockIdx.z * g.k_split;
+  const int ke = min(g.K, kb + g.k_split);
+  const bf16x8 zero8 = {};
+
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int k0 = kb; k0 < ke; k0 += GT) {
+    // stage A tile rows m0..m0+63, k0..k0+63 into As[m][k]
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      const int c = t + rep * 256;
+      if (!A_MC) {
+        const int r = c >> 3, kc = (c & 7) * 8;
+        bf16x8 val = zero8;
+        if (m0 + r < g.M) val = *reinterpret_cast<const bf16x8*>(g.A + (size_t)(m0 + r) * g.lda + k0 + kc);
+        *reinterpret_cast<bf16x8*>(&As[r * GLD + kc]) = val;
+      } else {
+        const int kr = c >> 3, mc = (c & 7) * 8;
+        bf16x8 val = zero8;
+        if (m0 + mc < g.M) val = *reinterpret_cast<const bf16x8*>(g.A + (size_t)(k0 + kr) * g.lda + m0 + mc);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[(mc + j) * GLD + kr] = val[j];
+      }
+    }
+    // stage B tile n0..n0+63, k0..k0+63 into Bs[n][k]
+#pragma unroll
+    for (int rep = 0; rep < 2; ++rep) {
+      const int c = t + rep * 256;
+      if (!B_NC) {
+        const int r = c >> 3, kc = (c & 7) * 8;
+        const bf16x8 val = *reinterpret_cast<const bf16x8*>(g.B + (size_t)(n0 + r) * g.ldb + k0 + kc);
+        *reinterpret_cast<bf16x8*>(&Bs[r * GLD + kc]) = val;
+      } else {
+        const int kr = c >> 3, nc = (c & 7) * 8;
+        const bf16x8 val = *reinterpret_cast<const bf16x8*>(g.B + (size_t)(k0 + kr) * g.ldb + n0 + nc);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[(nc + j) * GLD + kr] = val[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GT; kk += 32) {
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm * 32 + i * 16 + (lane & 15);
+        af[i] = *reinterpret_cast<const bf16x8*>(&As[r * GLD + kk + 8 * (lane >> 4)]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = wn * 32 + j * 16 + (lane & 15);
+        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[r * GLD + kk + 8 * (lane >> 4)]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  float* outf = g.out_f32 ? g.out_f32 + (size_t)blockIdx.z * g.M * g.N : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+      const float bias = g.bias ? g.bias[col] : 0.0f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+        if (row >= g.M) continue;
+        float x = acc[i][j][v] + bias;
+        if (g.relu) x = fmaxf(x, 0.0f);
+        if (g.mask && !((float)g.mask[(size_t)row * g.N + col] > 0.0f)) x = 0.0f;
+        if (outf) outf[(size_t)row * g.N + col] = x;
+        if (g.out_bf16) g.out_bf16[(size_t)row * g.N + col] = (bf16)x;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Head: yhat = H[m] . w + b (FP32).  Training: d = yhat - y, loss_part[m] = d^2,
+// g[m] = 2 d / n_total, dZ[m][i] = bf16(g w[i] (H[m][i] > 0)).
+// One wavefront per row; 4 rows per workgroup.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ H, int n, const float* __restrict__ w,
+                                              const float* __restrict__ b, const float* __restrict__ y,
+                                              float inv_total, float* __restrict__ yhat,
+                                              float* __restrict__ loss_part, float* __restrict__ gout,
+                                              bf16* __restrict__ dZ) {
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= n) return;  // whole wavefront leaves together
+  float h[4], wv[4];
+  float part = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    h[q] = (float)H[(size_t)m * 256 + lane * 4 + q];
+    wv[q] = w[lane * 4 + q];
+    part = fmaf(h[q], wv[q], part);
+  }
+  const float yh = wave_sum(part) + b[0];
+  if (yhat && lane == 0) yhat[m] = yh;
+  if (y) {
+    const float d = yh - y[m];
+    const float gm = 2.0f * d * inv_total;
+    if (lane == 0) {
+      loss_part[m] = d * d;
+      gout[m] = gm;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dZ[(size_t)m * 256 + lane * 4 + q] = (bf16)(h[q] > 0.0f ? gm * wv[q] : 0.0f);
+  }
+}
+
+// out[col] (+)= sum_m X[m][col] * (wt ? wt[m] : 1), FP32, fixed order:
+// 32 columns per workgroup, 32 row groups, partials added in order.
+__global__ __launch_bounds__(1024) void k_colsum(const bf16* __restrict__ X, int M, int N,
+                                                 const float* __restrict__ wt, float* __restrict__ out) {
+  __shared__ float sh[32][33];
+  const int cl = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  const int col = blockIdx.x * 32 + cl;
+  float s = 0.0f;
+  if (col < N)
+    for (int m = rg; m < M; m += 32) s = fmaf((float)X[(size_t)m * N + col], wt ? wt[m] : 1.0f, s);
+  sh[rg][cl] = s;
+  __syncthreads();
+  if (rg == 0 && col < N) {
+    float t = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) t += sh[q][cl];
+    out[col] = t;
+  }
+}
+
+// out[i] = sum_z part[z * n + i] in order.
+__global__ void k_sum_slices(const float* __restrict__ part, int n_slices, int n, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int z = 0; z < n_slices; ++z) s += part[(size_t)z * n + i];
+  out[i] = s;
+}
+
+// scale * sum(x[0..n)) in FP64, fixed tree order; one workgroup of 256.
+__global__ void k_sum_scalar(const float* __restrict__ x, int n, double scale, float* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += (double)x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(scale * sh[0]);
+}
+
+// Segment means: F[t] = mean of yhat[t * R .. t * R + R).  One workgroup per t.
+__global__ void k_segment_mean(const float* __restrict__ yhat, int R, float* __restrict__ F) {
+  __shared__ double sh[256];
+  const float* p = yhat + (size_t)blockIdx.x * R;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < R; i += 256) s += (double)p[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) F[blockIdx.x] = (float)(sh[0] / R);
+}
+
+// Adam on the flat FP32 parameters (torch semantics) with t = step[0] + 1,
+// then BF16 copies W [in][out] and W^T [out][in] of the hidden layers.
+__global__ void k_adam_mlp(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
+                           float* __restrict__ v, const int* __restrict__ step, int n, float lr, float b1,
+                           float b2, float eps, MlpLayout L, bf16* __restrict__ wbf, bf16* __restrict__ wtbf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = step[0] + 1;
+  const float gi = gr[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float bc1 = 1.0f - powf(b1, (float)t);
+  const float bc2 = 1.0f - powf(b2, (float)t);
+  const float pi = p[i] - (lr / bc1) * (mi / (sqrtf(vi) / sqrtf(bc2) + eps));
+  p[i] = pi;
+#pragma unroll
+  for (int l = 0; l < kMlpHidden; ++l) {
+    const int off = L.w_off[l], fi = L.fan_in[l];
+    if (i >= off && i < off + fi * 256) {
+      const int r = (i - off) / 256, c = (i - off) % 256;
+      wbf[L.bf_off[l] + r * 256 + c] = (bf16)pi;
+      wtbf[L.bf_off[l] + c * fi + r] = (bf16)pi;
+    }
+  }
+}
+
+__global__ void k_step_inc(int* step) { step[0] += 1; }
+
+// Same bf16 copies without an update (after loading parameters).
+__global__ void k_mlp_copies(const float* __restrict__ p, int n, MlpLayout L, bf16* __restrict__ wbf,
+                             bf16* __restrict__ wtbf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int l = 0; l < kMlpHidden; ++l) {
+    const int off = L.w_off[l], fi = L.fan_in[l];
+    if (i >= off && i < off + fi * 256) {
+      const int r = (i - off) / 256, c = (i - off) % 256;
+      wbf[L.bf_off[l] + r * 256 + c] = (bf16)p[i];
+      wtbf[L.bf_off[l] + c * fi + r] = (bf16)p[i];
+    }
+  }
+}
+
+// y = log(P + eps)
+__global__ void k_log_eps(const float* __restrict__ P, long long n, float eps, float* __restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = logf(P[i] + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_features(const float* v, const float* tx, const float* rx, int R, long long row0, int n,
+                           const float* Bf, bf16* X0, hipStream_t st) {
+  const long long threads = (long long)n * 64;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, v, tx, rx, R, row0,
+                     n, Bf, X0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmArgs& g, bool a_mc, bool b_nc, int n_slices, hipStream_t st) {
+  const dim3 grid((g.M + GT - 1) / GT, g.N / GT, n_slices);
+  if (!a_mc && !b_nc) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, g);
+  else if (a_mc && b_nc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, g);
+  else if (a_mc) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, g);
+  else hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(const bf16* H, int n, const float* w, const float* b, const float* y, float inv_total,
+                       float* yhat, float* loss_part, float* gout, bf16* dZ, hipStream_t st) {
+  hipLaunchKernelGGL(k_head, dim3((n + 3) / 4), dim3(256), 0, st, H, n, w, b, y, inv_total, yhat, loss_part, gout,
+                     dZ);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const bf16* X, int M, int N, const float* wt, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3((N + 31) / 32), dim3(1024), 0, st, X, M, N, wt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_slices(const float* part, int n_slices, int n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, st, part, n_slices, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_scalar(const float* x, int n, double scale, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(256), 0, st, x, n, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_mean(const float* yhat, int T, int R, float* F, hipStream_t st) {
+  hipLaunchKernelGGL(k_segment_mean, dim3(T), dim3(256), 0, st, yhat, R, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, int* step, int n, float lr, float b1,
+                           float b2, float eps, const MlpLayout& L, bf16* wbf, bf16* wtbf, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam_mlp, dim3((n + 255) / 256), dim3(256), 0, st, p, gr, m, v, step, n, lr, b1, b2, eps, L,
+                     wbf, wtbf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_copies(const float* p, int n, const MlpLayout& L, bf16* wbf, bf16* wtbf, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_copies, dim3((n + 255) / 256), dim3(256), 0, st, p, n, L, wbf, wtbf);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_eps(const float* P, long long n, float eps, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_log_eps, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, n, eps, y);
+  return hipGetLastError();
+}
+
+}  // namespace drt

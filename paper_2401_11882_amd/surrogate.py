@@ -1,0 +1,220 @@
+"""Learned surrogate of the log smoothed power map and surrogate-guided search.
+
+Binding of the drt_mlp_* C ABI plus the orchestration around it:
+
+1. data generation: the exact tracer (batched persistent launch, forward
+   only) evaluates P(rx; tx) for many (tx, rx) pairs of one scene; the target
+   is y = log(P + eps) (drt_log_targets);
+2. training: BF16-MFMA forward/backward and Adam (drt_mlp_train_step) on
+   standardised targets;
+3. coarse search: the mean of yhat over a receiver grid for every
+   transmitter of a grid (drt_mlp_scan), top-k;
+4. refinement: Adam on tx with the exact smoothed tracer (graph-captured
+   forward + adjoint), which also judges the result.
+
+Every number is computed by the library's kernels; this module only moves
+device pointers, shuffles row indices and runs the host-side loop.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+
+import numpy as np
+import torch
+
+from . import _lib
+from . import batched as B
+from . import tracer as tr
+from . import workloads as WL
+from ._lib import check, lib
+
+
+def num_params() -> int:
+    n = ctypes.c_int64()
+    check(lib().drt_mlp_num_params(ctypes.byref(n)))
+    return int(n.value)
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters in the flat layout of include/drt.h (float32)."""
+    layers = WL.mlp_init(seed)
+    parts = []
+    for W, b in layers[:-1]:
+        parts += [W.ravel(), b.ravel()]
+    hw, hb = layers[-1]
+    parts += [hw[:, 0].ravel(), hb.ravel()]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Surrogate:
+    def __init__(self, fourier_B: np.ndarray, params: np.ndarray, max_batch: int = 16384, device="cuda"):
+        self.device = torch.device(device)
+        self.max_batch = int(max_batch)
+        Bh = np.ascontiguousarray(fourier_B, dtype=np.float32)
+        ph = np.ascontiguousarray(params, dtype=np.float32)
+        if ph.size != num_params():
+            raise ValueError(f"params has {ph.size} entries, expected {num_params()}")
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().drt_mlp_create(Bh.ctypes.data_as(ctypes.c_void_p), ph.ctypes.data_as(ctypes.c_void_p),
+                                       self.max_batch, ctypes.byref(h)))
+        self._h = h
+        self.y_mean, self.y_std = 0.0, 1.0
+        self._loss = torch.zeros(1, device=self.device)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(num_params(), dtype=np.float32)
+        check(lib().drt_mlp_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, p: np.ndarray) -> None:
+        ph = np.ascontiguousarray(p, dtype=np.float32)
+        check(lib().drt_mlp_set_params(self._h, ph.ctypes.data_as(ctypes.c_void_p)))
+
+    def grads(self, v: torch.Tensor, y: torch.Tensor):
+        g = torch.empty(num_params(), device=self.device)
+        loss = torch.empty(1, device=self.device)
+        check(lib().drt_mlp_grads(self._h, _p(v), _p(y), v.shape[0], _p(g), _p(loss), tr.stream_handle()))
+        return g, loss
+
+    def train_step(self, v: torch.Tensor, y: torch.Tensor, lr: float) -> torch.Tensor:
+        check(lib().drt_mlp_train_step(self._h, _p(v), _p(y), v.shape[0], float(lr), _p(self._loss),
+                                       tr.stream_handle()))
+        return self._loss
+
+    def forward(self, v: torch.Tensor) -> torch.Tensor:
+        y = torch.empty(v.shape[0], device=self.device)
+        check(lib().drt_mlp_forward(self._h, _p(v), v.shape[0], _p(y), tr.stream_handle()))
+        return y
+
+    def scan(self, tx: torch.Tensor, rx: torch.Tensor) -> torch.Tensor:
+        F = torch.empty(tx.shape[0], device=self.device)
+        check(lib().drt_mlp_scan(self._h, _p(tx), tx.shape[0], _p(rx), rx.shape[0], _p(F), tr.stream_handle()))
+        return F
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().drt_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def log_targets(P: torch.Tensor, eps: float = 1e-6) -> torch.Tensor:
+    y = torch.empty_like(P)
+    check(lib().drt_log_targets(_p(P), P.numel(), float(eps), _p(y), tr.stream_handle()))
+    return y
+
+
+class _Sc:  # minimal scene record for BatchPlan
+    def __init__(self, walls, tx, rx, alpha):
+        self.walls, self.tx, self.rx, self.alpha, self.grid_n = walls, tx, rx, alpha, 0
+
+
+def generate_data(walls: np.ndarray, n_tx: int, n_rx: int, alpha: float, max_order: int, seed: int = 0,
+                  eps: float = 1e-6):
+    """(v [n_tx*n_rx, 4], y [n_tx*n_rx]) on the device: tx ~ U[0,1]^2 and, per tx,
+    n_rx receivers ~ U[0,1]^2; y = log(P + eps) from the exact smoothed tracer."""
+    rng = WL.rng_for(5, 4000 + seed)
+    txs = rng.uniform(0.0, 1.0, (n_tx, 2)).astype(np.float32)
+    rxs = rng.uniform(0.0, 1.0, (n_tx, n_rx, 2)).astype(np.float32)
+    scenes = [_Sc(walls, txs[i], rxs[i], alpha) for i in range(n_tx)]
+    plan = B.BatchPlan(scenes, max_order)
+    P = plan.run(loss="none")[0]
+    y = log_targets(P, eps)
+    v = torch.cat([torch.tensor(np.repeat(txs, n_rx, axis=0), device=plan.device),
+                   plan.rx], dim=1).contiguous()
+    torch.cuda.synchronize()
+    plan.close()
+    return v, y, txs
+
+
+def train(surr: Surrogate, v: torch.Tensor, y: torch.Tensor, epochs: int, batch: int = 16384,
+          lr: float = 1e-3, seed: int = 0, lr_final: float | None = None, log_every: int = 0):
+    """Standardises y, then epochs of shuffled mini-batches; returns per-epoch mean loss."""
+    ym, ys = float(y.mean()), float(y.std())
+    surr.y_mean, surr.y_std = ym, ys
+    yn = ((y - ym) / ys).contiguous()
+    n = v.shape[0] // batch * batch
+    gen = torch.Generator(device=v.device)
+    gen.manual_seed(seed)
+    hist = []
+    steps_total = epochs * (n // batch)
+    k = 0
+    for ep in range(epochs):
+        perm = torch.randperm(v.shape[0], device=v.device, generator=gen)[:n]
+        acc = torch.zeros(1, device=v.device)
+        for s in range(0, n, batch):
+            idx = perm[s:s + batch]
+            vb = v.index_select(0, idx).contiguous()
+            yb = yn.index_select(0, idx).contiguous()
+            lr_k = lr if lr_final is None else lr * (lr_final / lr) ** (k / max(1, steps_total - 1))
+            acc += surr.train_step(vb, yb, lr_k)
+            k += 1
+        hist.append(float(acc) / (n // batch))
+        if log_every and (ep + 1) % log_every == 0:
+            print(f"epoch {ep + 1}: mse {hist[-1]:.4f}", flush=True)
+    return hist
+
+
+def exact_objective(scene: tr.Scene, loss: str = "neg_mean_log") -> float:
+    """F = -L at the scene's current tx (mean log power over its receivers)."""
+    _, L, _ = tr.forward(scene, loss=loss)
+    return -float(L)
+
+
+def refine(walls, rx, tx0, max_order, alpha, steps, lr=1e-2, grid_nx=0, target=None):
+    """Adam on tx with the exact tracer from tx0.  Returns (tx_best, F_best,
+    steps_used); stops early once F >= target (checked every 5 steps)."""
+    from .optimize import optimize_tx
+    best_tx, best_F, used = tx0, None, 0
+    chunk = 5
+    tx = torch.as_tensor(tx0, device=rx.device, dtype=torch.float32)
+    while used < steps:
+        n = min(chunk, steps - used)
+        res = optimize_tx(walls, tx, rx, max_order, alpha, steps=n, lr=lr, grid_nx=grid_nx, use_graph=False)
+        L = res["loss_hist"].cpu().numpy()
+        txh = res["tx_hist"].cpu().numpy()
+        for i in range(n):
+            F = -float(L[i])
+            if best_F is None or F > best_F:
+                best_F, best_tx = F, txh[i]
+        used += n
+        tx = res["tx"]
+        if target is not None and best_F >= target:
+            break
+    return best_tx, best_F, used
+
+
+def search(surr: Surrogate, walls, rx_exact, tx_grid_n: int, rx_scan_n: int, top_k: int, refine_steps: int,
+           max_order: int, alpha: float, grid_nx: int = 0, target=None):
+    """Surrogate scan on a tx grid, top-k, exact refinement.  Returns dict."""
+    dev = rx_exact.device
+    txg = torch.tensor(WL.rx_grid(tx_grid_n), device=dev)
+    rxs = torch.tensor(WL.rx_grid(rx_scan_n), device=dev)
+    t0 = time.perf_counter()
+    Fhat = surr.scan(txg, rxs)
+    order = torch.argsort(Fhat, descending=True)[:top_k].cpu().numpy()
+    torch.cuda.synchronize()
+    t_scan = time.perf_counter() - t0
+    best = (None, -np.inf)
+    tried = 0
+    for i in order:
+        tried += 1
+        tx_b, F_b, _ = refine(walls, rx_exact, txg[i].cpu().numpy(), max_order, alpha, refine_steps,
+                              grid_nx=grid_nx, target=target)
+        if F_b > best[1]:
+            best = (tx_b, F_b)
+        if target is not None and best[1] >= target:
+            break
+    return {"tx": best[0], "F": best[1], "t_scan": t_scan, "t_total": time.perf_counter() - t0,
+            "starts_tried": tried, "Fhat_top": float(Fhat[order[0]])}
