@@ -75,6 +75,65 @@ def cpu_baseline(alpha: float, n_rx: int):
             "sample": f"{n_rx} random receivers of the 256x256 grid (fwd + VJP, FP64, torch CPU), {dt:.1f} s"}
 
 
+def extra_batched(dev):
+    """512 scenes (8..128 interior segments, 64^2..256^2 receivers, order <= 2,
+    alpha 100): forward + per-scene loss + adjoint in one persistent launch."""
+    import torch
+
+    from paper_2401_11882_amd import batched
+    from paper_2401_11882_amd import workloads as WL
+    scenes = WL.batch_scenes(512)
+    plan = batched.BatchPlan(scenes, 2, tune_cache=os.path.join(ROOT, "paper_2401_11882_amd", "tune_cache.txt"))
+    info = plan.info()
+    plan.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        plan.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    out = {"workload": "512 scenes, 8..128 segments + box, 64^2/128^2/256^2 rx, order<=2, alpha=100, fwd+adjoint",
+           "path_evals": info["path_evals"], "ms": round(ms, 3),
+           "value": info["path_evals"] / (ms * 1e-3), "unit": "path-evals/s", "launch": plan.config()}
+    plan.close()
+    return out
+
+
+def extra_order3_loop(dev):
+    """Box + 32 segments, 512^2 receivers, order <= 3: 200 graph-replayed Adam steps."""
+    import torch
+
+    from paper_2401_11882_amd import workloads as WL
+    from paper_2401_11882_amd.optimize import optimize_tx
+    s = WL.scene_32_order3()
+    walls, tx, rx = (torch.tensor(a, device=dev) for a in (s.walls, s.tx, s.rx))
+    optimize_tx(walls, tx, rx, 3, 100.0, steps=2, grid_nx=512)   # warm-up (workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = optimize_tx(walls, tx, rx, 3, 100.0, steps=200, grid_nx=512)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pe = s.n_rx * 45397
+    L = res["loss_hist"].cpu().numpy()
+    return {"workload": "box + 32 segments, 512^2 rx, order<=3 (45397 candidates), alpha=100, 200 Adam steps",
+            "s_total": round(dt, 3), "ms_per_step": round(1e3 * dt / 200, 3),
+            "value": pe * 200 / dt, "unit": "path-evals/s", "loss_first": float(L[0]), "loss_last": float(L[-1])}
+
+
+def extra_surrogate():
+    from paper_2401_11882_amd import surrogate
+    r = surrogate.experiment(seed=0)
+    return {"workload": "64-segment scene, 1e7 tracer samples, 6-layer BF16 MLP, 128^2 tx scan, exact refinement",
+            "speedup_at_1pct": round(r["speedup"], 3), "exact_step_ratio": round(r["exact_step_ratio"], 3),
+            "plain_s": round(r["plain"]["t_total"], 3), "surrogate_s": round(r["surrogate"]["t_total"], 3),
+            "surrogate_reached": r["surrogate"]["reached"], "plain_reached": r["plain"]["reached"],
+            "F_star": r["F_star"], "F_surrogate": r["surrogate"]["F"], "F_plain": r["plain"]["F"],
+            "datagen_s": round(r["datagen_s"], 3), "train_s": round(r["train_s"], 3),
+            "heldout_rmse": round(r["heldout_rmse"], 4), "target_std": round(r["target_std"], 4)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +142,8 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=100.0)
     ap.add_argument("--cpu-sample", type=int, default=768, help="receivers for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, order-3 loop and surrogate measurements")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     args = ap.parse_args()
@@ -179,6 +240,10 @@ def main() -> int:
         "fwd_ms": round(fwd_ms, 4), "bwd_ms": round(bwd_ms, 4),
         "roofline": roofline,
     }
+    if rank == 0 and not args.no_extras:
+        out["extras"] = {"batched_512_scenes": extra_batched(dev), "order3_adam_loop": extra_order3_loop(dev),
+                         "surrogate": extra_surrogate()}
+        out["surrogate_speedup_at_1pct"] = out["extras"]["surrogate"]["speedup_at_1pct"]
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.alpha, args.cpu_sample)
     if rank == 0:

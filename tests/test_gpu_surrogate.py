@@ -131,3 +131,18 @@ def test_training_reduces_loss():
     hist = S.train(net, v, y, epochs=12, batch=8192, lr=2e-3)
     assert hist[-1] < 0.5 * hist[0], hist
     net.close()
+
+
+def test_surrogate_guided_search_gain():
+    """Full study on the 64-segment scene: 1e7 tracer-generated samples, BF16
+    training, then reaching F >= F* + log 0.99 with and without the surrogate."""
+    S = _S()
+    r = S.experiment(seed=0)
+    print({k: r[k] for k in ("datagen_s", "train_s", "heldout_rmse", "F_star", "speedup", "exact_step_ratio")},
+          r["plain"], r["surrogate"])
+    assert r["samples"] == 2442 * 4096
+    assert r["heldout_rmse"] < 0.5 * r["target_std"]
+    assert r["surrogate"]["reached"]
+    # the surrogate path needs fewer exact-tracer steps and less time than the plain one
+    assert r["surrogate"]["exact_steps"] < r["plain"]["exact_steps"]
+    assert r["surrogate"]["t_total"] < r["plain"]["t_total"]
