@@ -19,7 +19,7 @@ namespace drt {
 
 __global__ void k_batch_reset(int* counter) { *counter = 0; }
 
-// Wall records and culling boxes for every wall of every scene (one
+// Wall records and culling data for every wall of every scene (one
 // workgroup per scene, alpha per scene).
 __global__ void k_batch_prep(const float* __restrict__ walls, const int* __restrict__ wall_off,
                              const float* __restrict__ alpha, WallRec* __restrict__ rec,
@@ -27,24 +27,10 @@ __global__ void k_batch_prep(const float* __restrict__ walls, const int* __restr
   const int s = blockIdx.x;
   const float c = kCullMargin / alpha[s];
   for (int j = wall_off[s] + threadIdx.x; j < wall_off[s + 1]; j += blockDim.x) {
-    const float ax = walls[4 * j], ay = walls[4 * j + 1];
-    const float bx = walls[4 * j + 2], by = walls[4 * j + 3];
-    const float ex = bx - ax, ey = by - ay;
     WallRec r;
-    r.ax = ax;
-    r.ay = ay;
-    r.ex = ex;
-    r.ey = ey;
-    r.axe = ax * ey - ay * ex;
-    r.pad0 = r.pad1 = r.pad2 = 0.0f;
-    rec[j] = r;
-    const float p0x = fmaf(-c, ex, ax), p0y = fmaf(-c, ey, ay);
-    const float p1x = fmaf(c, ex, bx), p1y = fmaf(c, ey, by);
     WallBox q;
-    q.xmin = fminf(p0x, p1x);
-    q.xmax = fmaxf(p0x, p1x);
-    q.ymin = fminf(p0y, p1y);
-    q.ymax = fmaxf(p0y, p1y);
+    make_wall(walls[4 * j], walls[4 * j + 1], walls[4 * j + 2], walls[4 * j + 3], c, r, q);
+    rec[j] = r;
     boxes[j] = q;
   }
 }

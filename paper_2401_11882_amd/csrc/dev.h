@@ -10,16 +10,57 @@ constexpr float kLog2e = 1.4426950408889634f;
 // Above this, E / (1 + E) is taken as exactly 1 (it is within 1e-30 of it).
 constexpr float kBig = 1e30f;
 
-// Prepared wall record, 32 bytes: endpoint a, direction e = b - a, a x e.
+// Prepared wall record, 32 bytes: endpoint a, direction e = b - a, a x e,
+// 1 / |e|^2 (0 for a zero-length wall).
 struct WallRec {
-  float ax, ay, ex, ey, axe, pad0, pad1, pad2;
+  float ax, ay, ex, ey, axe, inv_ee, pad1, pad2;
 };
 
-// Axis-aligned box of a wall extended along itself by the culling band:
-// [a - c e, b + c e], c = kCullMargin / alpha.
+// Wall record at a wave-uniform index, read through the scalar data cache
+// (constant address space, SGPR index) instead of 64 identical vector loads.
+__device__ __forceinline__ WallRec load_wall(const WallRec* walls, int j) {
+  typedef __attribute__((address_space(4))) const float* ConstF;
+  const int ju = __builtin_amdgcn_readfirstlane(j);
+  const ConstF p = (ConstF)(walls + ju);
+  WallRec w;
+  w.ax = p[0];
+  w.ay = p[1];
+  w.ex = p[2];
+  w.ey = p[3];
+  w.axe = p[4];
+  w.inv_ee = p[5];
+  w.pad1 = w.pad2 = 0.0f;
+  return w;
+}
+
+// A wall extended along itself by the culling band, [a - c e, b + c e]
+// (c = kCullMargin / alpha), with its normal n = perp(e) and n . p0: the data
+// the culling test needs for one wall.
 struct WallBox {
-  float xmin, xmax, ymin, ymax;
+  float p0x, p0y, p1x, p1y, nx, ny, nd, pad;
 };
+
+// Record and culling data of the wall (a, b).
+__device__ __forceinline__ void make_wall(float ax, float ay, float bx, float by, float c, WallRec& r,
+                                          WallBox& q) {
+  const float ex = bx - ax, ey = by - ay;
+  r.ax = ax;
+  r.ay = ay;
+  r.ex = ex;
+  r.ey = ey;
+  r.axe = ax * ey - ay * ex;
+  const float ee = ex * ex + ey * ey;
+  r.inv_ee = ee > 0.0f ? 1.0f / ee : 0.0f;
+  r.pad1 = r.pad2 = 0.0f;
+  q.p0x = fmaf(-c, ex, ax);
+  q.p0y = fmaf(-c, ey, ay);
+  q.p1x = fmaf(c, ex, bx);
+  q.p1y = fmaf(c, ey, by);
+  q.nx = -ey;
+  q.ny = ex;
+  q.nd = q.nx * q.p0x + q.ny * q.p0y;
+  q.pad = 0.0f;
+}
 
 // Obstruction tests are evaluated only when both parameters lie within
 // kBandMargin / alpha of [0, 1]; the culling boxes use the wider kCullMargin
@@ -74,6 +115,33 @@ __device__ __forceinline__ float wave_max(float x) {
   x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x142, 0xa, 0xf, false));
   x = fmaxf(x, __builtin_amdgcn_update_dpp(I, x, 0x143, 0xc, 0xf, false));
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Four simultaneous maxima over the 64 lanes (a reduce-scatter): after two
+// quad exchanges each lane holds one of the four quantities reduced over its
+// quad (lane % 4 = 0: a, 1: c, 2: b, 3: d); two row rotations reduce over the
+// 16-lane row, two permlane swaps over rows; four readlanes make the results
+// wave-uniform.
+__device__ __forceinline__ void wave_max4(float& a, float& b, float& c, float& d) {
+  const int lane = __lane_id();
+  const bool odd = lane & 1, hi2 = lane & 2;
+  const float s0 = odd ? a : c, s1 = odd ? b : d;   // what the partner lane^1 keeps
+  float o0 = odd ? c : a, o1 = odd ? d : b;
+  o0 = fmaxf(o0, __builtin_amdgcn_update_dpp(s0, s0, 0xb1, 0xf, 0xf, false));  // quad_perm [1,0,3,2]
+  o1 = fmaxf(o1, __builtin_amdgcn_update_dpp(s1, s1, 0xb1, 0xf, 0xf, false));
+  const float s = hi2 ? o0 : o1;                                               // what lane^2 keeps
+  float o = hi2 ? o1 : o0;
+  o = fmaxf(o, __builtin_amdgcn_update_dpp(s, s, 0x4e, 0xf, 0xf, false));      // quad_perm [2,3,0,1]
+  o = fmaxf(o, __builtin_amdgcn_update_dpp(o, o, 0x124, 0xf, 0xf, false));     // row_ror:4
+  o = fmaxf(o, __builtin_amdgcn_update_dpp(o, o, 0x128, 0xf, 0xf, false));     // row_ror:8
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(o), __float_as_uint(o), false, false);
+  o = fmaxf(__uint_as_float(h[0]), __uint_as_float(h[1]));                     // lane ^ 32
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(o), __float_as_uint(o), false, false);
+  o = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));                     // lane ^ 16
+  a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o), 0));
+  c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o), 1));
+  b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o), 2));
+  d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o), 3));
 }
 
 // Candidate index -> (order k, walls s[0..k-1]).  Candidates are ordered by

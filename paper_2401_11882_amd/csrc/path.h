@@ -63,11 +63,10 @@ __device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, f
   bool ok = live;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    const WallRec w = S.walls[P.s[i]];
+    const WallRec w = load_wall(S.walls, P.s[i]);
     const float nx = -w.ey, ny = w.ex;
-    const float nn = nx * nx + ny * ny;
-    ok = ok && (nn > 0.0f);
-    const float h = ((P.Ix[i] - w.ax) * nx + (P.Iy[i] - w.ay) * ny) / (nn > 0.0f ? nn : 1.0f);
+    ok = ok && (w.inv_ee > 0.0f);
+    const float h = ((P.Ix[i] - w.ax) * nx + (P.Iy[i] - w.ay) * ny) * w.inv_ee;
     P.Ix[i + 1] = P.Ix[i] - 2.0f * h * nx;
     P.Iy[i + 1] = P.Iy[i] - 2.0f * h * ny;
   }
@@ -78,7 +77,7 @@ __device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, f
   float F = ok ? 1.0f : 0.0f;
 #pragma unroll
   for (int i = K; i >= 1; --i) {
-    const WallRec w = S.walls[P.s[i - 1]];
+    const WallRec w = load_wall(S.walls, P.s[i - 1]);
     const float dx = P.Ix[i] - P.Xx[i + 1], dy = P.Iy[i] - P.Xy[i + 1];
     const float wx = w.ax - P.Xx[i + 1], wy = w.ay - P.Xy[i + 1];
     const float den = dx * w.ey - dy * w.ex;
@@ -165,51 +164,87 @@ __device__ __forceinline__ ObsVals obstruction_vals(float den, float tn, float u
   return o;
 }
 
-// Wave-uniform box around the band-extended legs [X_l - c D, X_{l+1} + c D]
-// of the live lanes.  A wall whose band-extended box misses it cannot give an
+// Wave-uniform oriented box around the band-extended legs
+// [X_l - c D, X_{l+1} + c D] of the live lanes: axis u along one live lane's
+// leg, v = perp(u), extents from the lanes' projections (grown by a relative
+// 1e-5 against rounding).  A wall whose band-extended segment is separated
+// from it (separating axes u, v and the wall normal) cannot give an
 // unsaturated test on that leg in any lane.
 struct LegBox {
-  float xmin, xmax, ymin, ymax;
+  float ux, uy, umin, umax, vmin, vmax;  // wave-uniform (scalar registers)
+  bool empty;
 };
 
 template <int K>
 __device__ __forceinline__ void leg_boxes(const Path<K>& P, const LegGeom (&L)[K + 1], bool lane_live,
                                           float c, LegBox (&B)[K + 1]) {
   const float I = __builtin_inff();
+  const uint64_t live = ballot(lane_live);
+  const int src = live ? __builtin_ctzll(live) : 0;
 #pragma unroll
   for (int l = 0; l <= K; ++l) {
+    B[l].empty = live == 0;
     const float q0x = fmaf(-c, L[l].Dx, L[l].Xx), q0y = fmaf(-c, L[l].Dy, L[l].Xy);
     const float q1x = fmaf(c, L[l].Dx, P.Xx[l + 1]), q1y = fmaf(c, L[l].Dy, P.Xy[l + 1]);
-    B[l].xmin = wave_min(lane_live ? fminf(q0x, q1x) : I);
-    B[l].xmax = wave_max(lane_live ? fmaxf(q0x, q1x) : -I);
-    B[l].ymin = wave_min(lane_live ? fminf(q0y, q1y) : I);
-    B[l].ymax = wave_max(lane_live ? fmaxf(q0y, q1y) : -I);
+    const float dx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L[l].Dx), src));
+    const float dy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L[l].Dy), src));
+    const float n2 = dx * dx + dy * dy;
+    const float rn = n2 > 0.0f ? rsqrtf(n2) : 0.0f;
+    const float ux = uniformf(n2 > 0.0f ? dx * rn : 1.0f), uy = uniformf(n2 > 0.0f ? dy * rn : 0.0f);
+    const float a0 = ux * q0x + uy * q0y, a1 = ux * q1x + uy * q1y;
+    const float b0 = ux * q0y - uy * q0x, b1 = ux * q1y - uy * q1x;
+    // maxima of -umin, umax, -vmin, vmax (dead lanes contribute -inf)
+    float a = lane_live ? -fminf(a0, a1) : -I, b = lane_live ? fmaxf(a0, a1) : -I;
+    float cc = lane_live ? -fminf(b0, b1) : -I, d = lane_live ? fmaxf(b0, b1) : -I;
+    wave_max4(a, b, cc, d);
+    if (B[l].empty) a = b = cc = d = 0.0f;
+    const float eu = 1e-5f * (1.0f + fmaxf(fabsf(a), fabsf(b)));
+    const float ev = 1e-5f * (1.0f + fmaxf(fabsf(cc), fabsf(d)));
+    B[l].ux = ux;
+    B[l].uy = uy;
+    B[l].umin = uniformf(-a - eu);
+    B[l].umax = uniformf(b + eu);
+    B[l].vmin = uniformf(-cc - ev);
+    B[l].vmax = uniformf(d + ev);
   }
 }
 
-// Calls fn(wall, masks, bit) for every wall whose box overlaps some leg box
-// (walls in increasing order); masks[l] bit `bit` tells whether leg l needs
-// the test (its own end walls are excluded here).  Lane j of the wavefront
-// checks wall b + j of each 64-wall batch.
+// Calls fn(wall, masks, bit) for every wall that is not separated from some
+// leg box (walls in increasing order); masks[l] bit `bit` tells whether leg l
+// needs the test (its own end walls are excluded here).  Lane j of the
+// wavefront checks wall b + j of each 64-wall batch.  Separating axes: u and
+// v (projections of the wall's band-extended segment against the box
+// extents) and the wall normal n (the box's range of n . x - n . p0 by
+// interval arithmetic on the extents, against a relative 1e-5 margin).
 template <int K, class Fn>
 __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P, const LegBox (&B)[K + 1],
                                             Fn&& fn) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int b = 0; b < S.n_walls; b += kWave) {
     const int wj = b + lane;
-    WallBox wb;
-    if (wj < S.n_walls) {
-      wb = S.boxes[wj];
+    const bool valid = wj < S.n_walls;
+    WallBox q;
+    if (valid) {
+      q = S.boxes[wj];
     } else {
-      wb.xmin = wb.ymin = __builtin_inff();
-      wb.xmax = wb.ymax = -__builtin_inff();
+      q.p0x = q.p0y = q.p1x = q.p1y = q.nx = q.ny = q.nd = q.pad = 0.0f;
     }
+    const float en = 1e-5f * (fabsf(q.nx) + fabsf(q.ny) + fabsf(q.nd));
     uint64_t m[K + 1];
     uint64_t uni = 0;
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
-      const bool ov = (wb.xmin <= B[l].xmax) & (wb.xmax >= B[l].xmin) & (wb.ymin <= B[l].ymax) &
-                      (wb.ymax >= B[l].ymin) & (wj != P.lo[l]) & (wj != P.hi[l]);
+      const LegBox& L = B[l];
+      const float a0 = L.ux * q.p0x + L.uy * q.p0y, a1 = L.ux * q.p1x + L.uy * q.p1y;
+      const float b0 = L.ux * q.p0y - L.uy * q.p0x, b1 = L.ux * q.p1y - L.uy * q.p1x;
+      const bool sep_u = (fmaxf(a0, a1) < L.umin) | (fminf(a0, a1) > L.umax);
+      const bool sep_v = (fmaxf(b0, b1) < L.vmin) | (fminf(b0, b1) > L.vmax);
+      // n . (s u + t v) - nd over the box: s in [umin, umax], t in [vmin, vmax]
+      const float nu = q.nx * L.ux + q.ny * L.uy, nv = q.ny * L.ux - q.nx * L.uy;
+      const float s_lo = fminf(nu * L.umin, nu * L.umax) + fminf(nv * L.vmin, nv * L.vmax) - q.nd;
+      const float s_hi = fmaxf(nu * L.umin, nu * L.umax) + fmaxf(nv * L.vmin, nv * L.vmax) - q.nd;
+      const bool sep_n = (s_lo > en) | (s_hi < -en);
+      const bool ov = valid & !L.empty & !sep_u & !sep_v & !sep_n & (wj != P.lo[l]) & (wj != P.hi[l]);
       m[l] = ballot(ov);
       uni |= m[l];
     }
@@ -229,7 +264,7 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
   LegBox B[K + 1];
   leg_boxes<K>(P, L, P.F != 0.0f, S.cull_c, B);
   visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
-    const WallRec w = S.walls[jw];
+    const WallRec w = load_wall(S.walls, jw);
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
       if (((m[l] >> j) & 1ull) == 0) continue;
@@ -303,7 +338,7 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
   LegBox B[K + 1];
   leg_boxes<K>(P, L, act, S.cull_c, B);
   visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
-    const WallRec w = S.walls[jw];
+    const WallRec w = load_wall(S.walls, jw);
     float gax = 0.0f, gay = 0.0f, gex = 0.0f, gey = 0.0f;
     bool any = false;
 #pragma unroll
@@ -365,7 +400,7 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
   // -- interactions i = 1..K: smoothed factors and back-trace, in order
 #pragma unroll
   for (int i = 1; i <= K; ++i) {
-    const WallRec w = S.walls[P.s[i - 1]];
+    const WallRec w = load_wall(S.walls, P.s[i - 1]);
     const float t = P.t[i - 1], u = P.u[i - 1], inv = P.inv[i - 1];
     const float E1 = ex2(-S.a2 * t), E2 = ex2(fmaf(S.a2, t, -S.a2));
     const float E3 = ex2(-S.a2 * u), E4 = ex2(fmaf(S.a2, u, -S.a2));
@@ -414,19 +449,19 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
     GIy[0] = 0.0f;
 #pragma unroll
     for (int i = K; i >= 1; --i) {
-      const WallRec w = S.walls[P.s[i - 1]];
+      const WallRec w = load_wall(S.walls, P.s[i - 1]);
       const float nx = -w.ey, ny = w.ex;
-      const float nn = nx * nx + ny * ny;
+      const float inn = w.inv_ee;
       const float px = P.Ix[i - 1] - w.ax, py = P.Iy[i - 1] - w.ay;
-      const float h = (px * nx + py * ny) / nn;
+      const float h = (px * nx + py * ny) * inn;
       const float Gx = GIx[i], Gy = GIy[i];
       const float Gn = Gx * nx + Gy * ny;
-      const float kk = 2.0f * Gn / nn;
+      const float kk = 2.0f * Gn * inn;
       GIx[i - 1] += Gx - kk * nx;
       GIy[i - 1] += Gy - kk * ny;
       const float gax = kk * nx, gay = kk * ny;
-      const float gnx = -2.0f * (Gn * (px - 2.0f * h * nx) / nn + h * Gx);
-      const float gny = -2.0f * (Gn * (py - 2.0f * h * ny) / nn + h * Gy);
+      const float gnx = -2.0f * (Gn * (px - 2.0f * h * nx) * inn + h * Gx);
+      const float gny = -2.0f * (Gn * (py - 2.0f * h * ny) * inn + h * Gy);
       const float gex = gny, gey = -gnx;
       if (lane == 0) {
         float* p = acc + 2 + 4 * P.s[i - 1];

@@ -207,29 +207,15 @@ __global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const floa
 // Small kernels
 // ---------------------------------------------------------------------------
 
-// Wall records (a, e = b - a, a x e) and culling boxes of [a - c e, b + c e].
+// Wall records and culling data (see make_wall).
 __global__ void k_prep_walls(const float* __restrict__ walls, int n, float c, WallRec* __restrict__ out,
                              WallBox* __restrict__ boxes) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const float ax = walls[4 * j], ay = walls[4 * j + 1];
-  const float bx = walls[4 * j + 2], by = walls[4 * j + 3];
-  const float ex = bx - ax, ey = by - ay;
   WallRec r;
-  r.ax = ax;
-  r.ay = ay;
-  r.ex = ex;
-  r.ey = ey;
-  r.axe = ax * ey - ay * ex;
-  r.pad0 = r.pad1 = r.pad2 = 0.0f;
-  out[j] = r;
-  const float p0x = fmaf(-c, ex, ax), p0y = fmaf(-c, ey, ay);
-  const float p1x = fmaf(c, ex, bx), p1y = fmaf(c, ey, by);
   WallBox q;
-  q.xmin = fminf(p0x, p1x);
-  q.xmax = fmaxf(p0x, p1x);
-  q.ymin = fminf(p0y, p1y);
-  q.ymax = fmaxf(p0y, p1y);
+  make_wall(walls[4 * j], walls[4 * j + 1], walls[4 * j + 2], walls[4 * j + 3], c, r, q);
+  out[j] = r;
   boxes[j] = q;
 }
 
