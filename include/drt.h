@@ -120,10 +120,32 @@ int drt_set_launch_config(int32_t nw, int32_t cchunk);
    the cache.  Default 32 GiB.  Process-wide; affects later size queries. */
 int drt_set_cache_limit(int64_t bytes);
 
+/* Candidate screen on (1, default) or off (0).  With the screen on, each
+   wavefront first tests 64 candidates at a time against the bounding box of
+   its receivers and drops those whose interaction factor is provably
+   exactly 0 at every receiver of the box (a back-trace parameter beyond the
+   range where exp(-alpha x) overflows FP32; Sec. IV-A, Eq. 3-4).  It changes
+   no result beyond the summation order of zero terms; turning it off exists
+   to verify that.  Process-wide. */
+int drt_set_screen(int32_t enabled);
+
 /* Workspace bytes that drt_forward / drt_backward / drt_forward_backward
    need for this scene (depends on n_walls, n_rx and the launch shape).
    Host only; reads no device memory. */
 int drt_workspace_size(const drt_scene* scene, size_t* bytes);
+
+/* Layout of the contribution cache inside a workspace for this scene under
+   the current launch settings (host only; for verification tools).
+   slots      wavefront slots, slot = tile * nw + wave;
+   capacity   entries per slot (0: no cache);
+   off_idx    byte offset of the candidate index lists, int32 [slots][capacity],
+              each in increasing candidate order;
+   off_n      byte offset of the per-slot counts, int32 [slots] (-1: the slot
+              overflowed its capacity).
+   The contents are those of the last drt_forward with a seed or of
+   drt_forward_backward on that workspace. */
+int drt_cache_layout(const drt_scene* scene, int64_t* slots, int64_t* capacity, int64_t* off_idx,
+                     int64_t* off_n);
 
 /* Forward pass (steps 1-3 above, and 4's loss value).
    power_dev   out [n_rx]      P(r).

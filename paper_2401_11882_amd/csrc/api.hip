@@ -33,6 +33,7 @@ int g_nw_override = 0;
 int g_cchunk_override = 0;
 // Largest contribution cache placed in a workspace (bytes); 0 disables it.
 int64_t g_cache_limit = 32LL << 30;
+int g_screen = 1;
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -138,6 +139,7 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.grid_nx = s->rx_grid_nx;
   A.n_cand = (int)count_candidates(s->n_walls, s->max_order);
   A.cchunk = p.cchunk;
+  A.screen = g_screen;
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
   A.band_k = 1.0f + 2.0f * drt::kBandMargin / s->alpha;
@@ -217,6 +219,7 @@ __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char
 }
 
 __attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void) { return g_cache_limit; }
+__attribute__((visibility("hidden"))) int drt_internal_screen(void) { return g_screen; }
 
 int drt_abi_version(void) { return DRT_ABI_VERSION; }
 
@@ -248,6 +251,12 @@ int drt_set_cache_limit(int64_t bytes) {
   return DRT_OK;
 }
 
+int drt_set_screen(int32_t enabled) {
+  if (enabled != 0 && enabled != 1) return fail(DRT_EINVAL, "screen flag %d must be 0 or 1", enabled);
+  g_screen = enabled;
+  return DRT_OK;
+}
+
 int drt_num_candidates(int32_t n_walls, int32_t max_order, int64_t* count) {
   if (!count) return fail(DRT_EINVAL, "count is NULL");
   if (n_walls < 0 || n_walls > DRT_MAX_WALLS || max_order < 0 || max_order > DRT_MAX_ORDER)
@@ -261,6 +270,19 @@ int drt_workspace_size(const drt_scene* scene, size_t* bytes) {
   if (rc) return rc;
   if (!bytes) return fail(DRT_EINVAL, "bytes is NULL");
   *bytes = make_plan(scene).total;
+  return DRT_OK;
+}
+
+int drt_cache_layout(const drt_scene* scene, int64_t* slots, int64_t* capacity, int64_t* off_idx,
+                     int64_t* off_n) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if (!slots || !capacity || !off_idx || !off_n) return fail(DRT_EINVAL, "NULL output pointer");
+  const Plan p = make_plan(scene);
+  *slots = (int64_t)p.n_tiles * p.nw;
+  *capacity = p.cache_cap;
+  *off_idx = (int64_t)p.off_cache_idx;
+  *off_n = (int64_t)p.off_cache_n;
   return DRT_OK;
 }
 

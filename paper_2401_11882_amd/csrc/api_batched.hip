@@ -15,6 +15,7 @@
 
 extern "C" __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char* msg);
 extern "C" __attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void);
+extern "C" __attribute__((visibility("hidden"))) int drt_internal_screen(void);
 
 namespace {
 
@@ -175,6 +176,7 @@ drt::BatchArgs make_args(const drt_plan* p, const drt_batch* b, int loss_kind, f
   B.cache_idx = p->cache_cap > 0 ? p->d_cache_idx : nullptr;
   B.cache_cap = p->cache_cap;
   B.cchunk = p->cfg.cchunk;
+  B.screen = drt_internal_screen();
   B.tile_w = p->cfg.tile_w;
   return B;
 }

@@ -34,6 +34,7 @@ struct BatchArgs {
   int* cache_idx;              // [slots][cache_cap]
   int cache_cap;
   int cchunk;
+  int screen;                  // candidate screen on / off
   int tile_w;                  // receivers per tile row on grid scenes (8, 16, 32)
 };
 

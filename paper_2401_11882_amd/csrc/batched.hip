@@ -14,6 +14,7 @@
 // so results do not depend on which workgroup took which item.
 #include "batched.h"
 #include "path.h"
+#include "screen.h"
 
 namespace drt {
 
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
     S.band_k = 1.0f + 2.0f * kBandMargin / alpha;
     S.cull_c = kCullMargin / alpha;
     S.dmin2 = B.dmin2;
+    S.dead_lim = 128.0f / S.a2 * 1.00001f;
     // number of candidates of this scene
     int n_cand = 1, term = 0;
     for (int k = 1; k <= B.max_order; ++k) {
@@ -99,22 +101,19 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
     // -- forward over this wave's candidates, recording nonzero contributions
     float sum = 0.0f, comp = 0.0f;
     int nst = 0;
-    const int stride = NW * B.cchunk;
-    for (int c0 = wave * B.cchunk; c0 < n_cand; c0 += stride) {
-      const int c1 = min(c0 + B.cchunk, n_cand);
-      for (int c = c0; c < c1; ++c) {
-        const Cand cd = decode_candidate(c, W);
-        const float v = candidate_power(S, cd, txx, txy, rxx, rxy, live);
-        kahan_add(sum, comp, v);
-        if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
-          if (nst < B.cache_cap) {
-            cache_c[(size_t)nst * kWave + lane] = v;
-            if (lane == 0) cache_idx[nst] = c;
-          }
-          ++nst;
-        }
-      }
-    }
+    const RxBox box = rx_box(rxx, rxy, live);
+    for_screened(S.walls, W, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box,
+                 [&](int c, const Cand& cd, const float* Ix, const float* Iy) {
+                   const float v = candidate_power_img(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+                   kahan_add(sum, comp, v);
+                   if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
+                     if (nst < B.cache_cap) {
+                       cache_c[(size_t)nst * kWave + lane] = v;
+                       if (lane == 0) cache_idx[nst] = c;
+                     }
+                     ++nst;
+                   }
+                 });
     red[(wave * 2 + 0) * kWave + lane] = sum;
     red[(wave * 2 + 1) * kWave + lane] = comp;
     __syncthreads();
@@ -155,6 +154,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
         candidate_adjoint_known(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
       }
     } else {
+      const int stride = NW * B.cchunk;
       for (int c0 = wave * B.cchunk; c0 < n_cand; c0 += stride) {
         const int c1 = min(c0 + B.cchunk, n_cand);
         for (int c = c0; c < c1; ++c) {

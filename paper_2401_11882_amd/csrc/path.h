@@ -27,6 +27,7 @@ struct SceneView {
   float band_k;  // 1 + 2 * kBandMargin / alpha
   float cull_c;  // kCullMargin / alpha
   float dmin2;
+  float dead_lim;  // 128 / a2, widened by a relative 1e-5 (see screen.h)
 };
 
 template <int K>
@@ -44,12 +45,10 @@ struct Path {
 // E / (1 + E) = 1 - s, accurate for small E and exactly 1 for huge or infinite E.
 __device__ __forceinline__ float one_minus_s(float E) { return E < kBig ? E * rcp(1.0f + E) : 1.0f; }
 
-// Images, back-trace and (if WANT_F) the interaction factors of candidate cd.
-// With WANT_F, returns false as soon as every lane's factor is exactly 0
-// (then P.F = 0 and the remaining fields are not filled).
-template <int K, bool WANT_F>
-__device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, float txx, float txy,
-                                           float rxx, float rxy, bool live, Path<K>& P) {
+// Wall indices of candidate cd: interaction walls and, per leg, the walls
+// the leg is not tested against (its own ends).
+template <int K>
+__device__ __forceinline__ void path_walls(const Cand& cd, Path<K>& P) {
   const int sv[3] = {cd.s0, cd.s1, cd.s2};
 #pragma unroll
   for (int i = 0; i < Path<K>::KI; ++i) P.s[i] = (i < K) ? sv[i] : -1;
@@ -58,9 +57,13 @@ __device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, f
     P.lo[l] = (l >= 1) ? sv[l - 1] : -1;
     P.hi[l] = (l + 1 <= K) ? sv[l] : -1;
   }
-  P.Ix[0] = txx;
-  P.Iy[0] = txy;
-  bool ok = live;
+}
+
+// Images I_1..I_K of the transmitter (P.Ix[0], P.Iy[0]); false if a wall is
+// degenerate.
+template <int K>
+__device__ __forceinline__ bool path_images(const SceneView& S, Path<K>& P) {
+  bool ok = true;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     const WallRec w = load_wall(S.walls, P.s[i]);
@@ -70,8 +73,16 @@ __device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, f
     P.Ix[i + 1] = P.Ix[i] - 2.0f * h * nx;
     P.Iy[i + 1] = P.Iy[i] - 2.0f * h * ny;
   }
-  P.Xx[0] = txx;
-  P.Xy[0] = txy;
+  return ok;
+}
+
+// Back-trace from the receiver through the images and (if WANT_F) the
+// interaction factors.  With WANT_F, returns false as soon as every lane's
+// factor is exactly 0 (then P.F = 0 and the remaining fields are not filled).
+template <int K, bool WANT_F>
+__device__ __forceinline__ bool back_trace(const SceneView& S, float rxx, float rxy, bool ok, Path<K>& P) {
+  P.Xx[0] = P.Ix[0];
+  P.Xy[0] = P.Iy[0];
   P.Xx[K + 1] = rxx;
   P.Xy[K + 1] = rxy;
   float F = ok ? 1.0f : 0.0f;
@@ -110,6 +121,17 @@ __device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, f
   }
   P.F = F;
   return true;
+}
+
+// Images, back-trace and (if WANT_F) the interaction factors of candidate cd.
+template <int K, bool WANT_F>
+__device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, float txx, float txy,
+                                           float rxx, float rxy, bool live, Path<K>& P) {
+  path_walls<K>(cd, P);
+  P.Ix[0] = txx;
+  P.Iy[0] = txy;
+  const bool ok = path_images<K>(S, P);
+  return back_trace<K, WANT_F>(S, rxx, rxy, live && ok, P);
 }
 
 struct LegGeom {
@@ -293,11 +315,37 @@ __device__ __forceinline__ float path_power(const SceneView& S, const Cand& cd, 
   return V / fmaxf(d2, S.dmin2);
 }
 
+// Same as path_power with the images I_1..I_K given (wave-uniform; the
+// candidate's walls are known to be nondegenerate).
+template <int K>
+__device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& cd, const float* Ix,
+                                                const float* Iy, float txx, float txy, float rxx, float rxy,
+                                                bool live) {
+  Path<K> P;
+  path_walls<K>(cd, P);
+  P.Ix[0] = txx;
+  P.Iy[0] = txy;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    P.Ix[i + 1] = Ix[i];
+    P.Iy[i + 1] = Iy[i];
+  }
+  if (!back_trace<K, true>(S, rxx, rxy, live, P)) return 0.0f;
+  if (ballot(P.F != 0.0f) == 0) return 0.0f;
+  const float V = obstruct_all<K>(S, P, P.F);
+  const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
+  const float d2 = fmaf(ex, ex, ey * ey);
+  return V / fmaxf(d2, S.dmin2);
+}
+
+// Compensated sum; a zero term leaves the state as it is, so which zero
+// contributions are visited does not change the result.
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
   const float y = x - comp;
   const float t = sum + y;
-  comp = (t - sum) - y;
-  sum = t;
+  const float c = (t - sum) - y;
+  sum = x != 0.0f ? t : sum;
+  comp = x != 0.0f ? c : comp;
 }
 
 // Per-wave accumulator layout: [0,1] = d/dtx, [2 + 4j + c] = d/d walls[j][c].
@@ -511,6 +559,17 @@ __device__ __forceinline__ float candidate_power(const SceneView& S, const Cand&
     case 1: return path_power<1>(S, cd, txx, txy, rxx, rxy, live);
     case 2: return path_power<2>(S, cd, txx, txy, rxx, rxy, live);
     default: return path_power<3>(S, cd, txx, txy, rxx, rxy, live);
+  }
+}
+
+__device__ __forceinline__ float candidate_power_img(const SceneView& S, const Cand& cd, const float* Ix,
+                                                     const float* Iy, float txx, float txy, float rxx,
+                                                     float rxy, bool live) {
+  switch (cd.k) {
+    case 0: return path_power_img<0>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    case 1: return path_power_img<1>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    case 2: return path_power_img<2>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    default: return path_power_img<3>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
   }
 }
 

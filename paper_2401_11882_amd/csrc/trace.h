@@ -19,6 +19,7 @@ struct TraceArgs {
   int grid_nx;           // 0 = consecutive receivers per wavefront
   int n_cand;
   int cchunk;            // candidates per chunk handed to one wavefront
+  int screen;            // 1: drop candidates that are exactly 0 over a wavefront's receiver box
   float alpha;
   float a2;              // alpha * log2(e)
   float band_k;          // 1 + 2 * 18 / alpha: unsaturated-test band

@@ -37,6 +37,7 @@
 // candidates are Kahan-compensated; every cross-lane / cross-wave /
 // cross-block sum has a fixed order.
 #include "path.h"
+#include "screen.h"
 #include "trace.h"
 
 namespace drt {
@@ -55,6 +56,7 @@ __device__ __forceinline__ SceneView view_of(const TraceArgs& A) {
   S.band_k = A.band_k;
   S.cull_c = A.cull_c;
   S.dmin2 = A.dmin2;
+  S.dead_lim = 128.0f / A.a2 * 1.00001f;
   return S;
 }
 
@@ -80,22 +82,19 @@ __global__ __launch_bounds__(NW * kWave) void k_forward(TraceArgs A, float* __re
   int nst = 0;
 
   float sum = 0.0f, comp = 0.0f;
-  const int stride = NW * A.cchunk;
-  for (int c0 = wave * A.cchunk; c0 < A.n_cand; c0 += stride) {
-    const int c1 = min(c0 + A.cchunk, A.n_cand);
-    for (int c = c0; c < c1; ++c) {
-      const Cand cd = decode_candidate(c, A.n_walls);
-      const float v = candidate_power(S, cd, txx, txy, rxx, rxy, live);
-      kahan_add(sum, comp, v);
-      if (cache_c && ballot(v != 0.0f) != 0) {
-        if (nst < A.cache_cap) {
-          cache_c[(size_t)nst * kWave + lane] = v;
-          if (lane == 0) cache_idx[nst] = c;
-        }
-        ++nst;
-      }
-    }
-  }
+  const RxBox box = rx_box(rxx, rxy, live);
+  for_screened(S.walls, A.n_walls, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
+               [&](int c, const Cand& cd, const float* Ix, const float* Iy) {
+                 const float v = candidate_power_img(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+                 kahan_add(sum, comp, v);
+                 if (cache_c && ballot(v != 0.0f) != 0) {
+                   if (nst < A.cache_cap) {
+                     cache_c[(size_t)nst * kWave + lane] = v;
+                     if (lane == 0) cache_idx[nst] = c;
+                   }
+                   ++nst;
+                 }
+               });
   if (cache_c && lane == 0) A.cache_n[slot] = nst <= A.cache_cap ? nst : -1;
   red[wave][0][lane] = sum;
   red[wave][1][lane] = comp;

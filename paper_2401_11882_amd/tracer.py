@@ -104,6 +104,26 @@ def set_cache_limit(nbytes: int) -> None:
     check(lib().drt_set_cache_limit(int(nbytes)))
 
 
+def set_screen(enabled: bool) -> None:
+    """Candidate screen on/off (process-wide; on by default)."""
+    check(lib().drt_set_screen(1 if enabled else 0))
+
+
+def cache_lists(scene: Scene) -> list[list[int]]:
+    """Per wavefront slot, the candidates the last seeded forward recorded as
+    nonzero (None for a slot that overflowed); reads the shared workspace."""
+    sc = scene.c_struct()
+    ws, _ = workspace(sc, scene.device)
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    check(lib().drt_cache_layout(ctypes.byref(sc), *[ctypes.byref(x) for x in v]))
+    slots, cap, off_idx, off_n = (int(x.value) for x in v)
+    if cap == 0:
+        return []
+    idx = ws[off_idx:off_idx + 4 * slots * cap].view(torch.int32).view(slots, cap).cpu()
+    cnt = ws[off_n:off_n + 4 * slots].view(torch.int32).cpu()
+    return [None if int(n) < 0 else idx[s, :int(n)].tolist() for s, n in enumerate(cnt)]
+
+
 def forward(scene: Scene, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS,
             want_seed: bool = False, stream=None):
     """P(r) [R]; plus the loss scalar (and dL/dP) when loss != 'none'."""

@@ -93,6 +93,22 @@ def test_batched_deterministic_and_graph_replay():
     plan.close()
 
 
+def test_batched_screen_exact():
+    batched, tr = _mods()
+    scenes = _small_mixed() + WL.batch_scenes(8, side_cap=32)
+    out = {}
+    try:
+        for on in (True, False):
+            tr.set_screen(on)
+            plan = batched.BatchPlan(scenes, 2)
+            out[on] = [t.clone() for t in plan.run()]
+            plan.close()
+    finally:
+        tr.set_screen(True)
+    for x, y in zip(out[True], out[False]):
+        assert torch.equal(x, y)
+
+
 def test_autotune_and_cache(tmp_path):
     batched, tr = _mods()
     scenes = WL.batch_scenes(24, side_cap=32)

@@ -198,6 +198,36 @@ def test_contribution_cache_reuse_and_overflow():
                                atol=1e-6 * float(b[1].abs().max()))
 
 
+@pytest.mark.parametrize("case", ["box64_a10", "box64_a100", "box64_a1000", "order3", "scattered_rx"])
+def test_screen_drops_only_zero_candidates(case):
+    """With and without the candidate screen: the same nonzero candidates per
+    wavefront and bitwise the same power (zero terms do not touch the sums)."""
+    tr = _tr()
+    if case.startswith("box64"):
+        s = WL.scene_64(grid_n=128, alpha=float(case.split("_a")[1]))
+        sc = _scene(s)
+    elif case == "order3":
+        s = WL.scene_32_order3(grid_n=64)
+        sc = _scene(s)
+    else:
+        s = WL.scene_random_box(2, 24, 8, 2, 100.0, seed=5)
+        sc = _scene(s, rx=WL.random_points(2, 5, 3000))
+    res = {}
+    try:
+        for on in (True, False):
+            tr.set_screen(on)
+            P, _, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+            g = tr.backward(sc, seed, reuse_forward=True)
+            res[on] = (P.clone(), tr.cache_lists(sc), [t.clone() for t in g if t is not None])
+    finally:
+        tr.set_screen(True)
+    assert torch.equal(res[True][0], res[False][0])
+    assert all(a is not None for a in res[True][1])
+    assert res[True][1] == res[False][1]
+    for x, y in zip(res[True][2], res[False][2]):
+        assert torch.equal(x, y)
+
+
 def test_deterministic_repeat():
     tr = _tr()
     s = WL.scene_random_box(2, 16, 32, 2, 100.0, seed=4)
