@@ -144,6 +144,27 @@ __device__ __forceinline__ void wave_max4(float& a, float& b, float& c, float& d
   d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o), 3));
 }
 
+// Four simultaneous sums over the 64 lanes, the reduce-scatter of wave_max4
+// with additions (fixed order, so deterministic).  Afterwards lane l holds
+// the total of a, c, b or d for l % 4 = 0, 1, 2, 3.
+__device__ __forceinline__ float wave_sum4(float a, float b, float c, float d) {
+  const int lane = __lane_id();
+  const bool odd = lane & 1, hi2 = lane & 2;
+  const float s0 = odd ? a : c, s1 = odd ? b : d;
+  float o0 = odd ? c : a, o1 = odd ? d : b;
+  o0 += __builtin_amdgcn_update_dpp(s0, s0, 0xb1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+  o1 += __builtin_amdgcn_update_dpp(s1, s1, 0xb1, 0xf, 0xf, false);
+  const float s = hi2 ? o0 : o1;
+  float o = hi2 ? o1 : o0;
+  o += __builtin_amdgcn_update_dpp(s, s, 0x4e, 0xf, 0xf, false);      // quad_perm [2,3,0,1]
+  o += __builtin_amdgcn_update_dpp(o, o, 0x124, 0xf, 0xf, false);     // row_ror:4
+  o += __builtin_amdgcn_update_dpp(o, o, 0x128, 0xf, 0xf, false);     // row_ror:8
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(o), __float_as_uint(o), false, false);
+  o = __uint_as_float(h[0]) + __uint_as_float(h[1]);                   // lane ^ 32
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(o), __float_as_uint(o), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);               // lane ^ 16
+}
+
 // Candidate index -> (order k, walls s[0..k-1]).  Candidates are ordered by
 // order, then lexicographically: the first wall is a base-W digit, each later
 // wall a base-(W-1) digit d mapped to d + (d >= previous wall), which skips a

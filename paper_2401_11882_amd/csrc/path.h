@@ -232,8 +232,9 @@ __device__ __forceinline__ void leg_boxes(const Path<K>& P, const LegGeom (&L)[K
 }
 
 // Calls fn(wall, masks, bit) for every wall that is not separated from some
-// leg box (walls in increasing order); masks[l] bit `bit` tells whether leg l
-// needs the test (its own end walls are excluded here).  Lane j of the
+// leg box (walls in increasing order) until fn returns false; masks[l] bit
+// `bit` tells whether leg l needs the test (its own end walls are excluded
+// here).  Lane j of the
 // wavefront checks wall b + j of each 64-wall batch.  Separating axes: u and
 // v (projections of the wall's band-extended segment against the box
 // extents) and the wall normal n (the box's range of n . x - n . p0 by
@@ -273,7 +274,7 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
     while (uni) {
       const int j = __builtin_ctzll(uni);
       uni &= uni - 1;
-      fn(b + j, m, j);
+      if (!fn(b + j, m, j)) return;
     }
   }
 }
@@ -287,6 +288,7 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
   leg_boxes<K>(P, L, P.F != 0.0f, S.cull_c, B);
   visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
     const WallRec w = load_wall(S.walls, jw);
+    bool upd = false;
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
       if (((m[l] >> j) & 1ull) == 0) continue;
@@ -296,8 +298,11 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
       if (it && ups_in_band(L[l], w, den, kd, un)) {
         const ObsVals o = obstruction_vals(den, tn, un, S.a2);
         V *= o.num * rcp(1.0f + o.num);
+        upd = true;
       }
     }
+    // once every lane's product is exactly 0 no further factor can change it
+    return ballot(upd) == 0 || ballot(V != 0.0f) != 0;
   });
   return V;
 }
@@ -349,16 +354,11 @@ __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
 }
 
 // Per-wave accumulator layout: [0,1] = d/dtx, [2 + 4j + c] = d/d walls[j][c].
+// Lanes 0..3 add the wave totals of (dax, dbx, day, dby) to their entries.
 __device__ __forceinline__ void acc_wall(float* acc, int j, float dax, float day, float dbx, float dby,
                                          int lane) {
-  const float s0 = wave_sum(dax), s1 = wave_sum(day), s2 = wave_sum(dbx), s3 = wave_sum(dby);
-  if (lane == 0) {
-    float* p = acc + 2 + 4 * j;
-    p[0] += s0;
-    p[1] += s1;
-    p[2] += s2;
-    p[3] += s3;
-  }
+  const float s = wave_sum4(dax, day, dbx, dby);
+  if (lane < 4) acc[2 + 4 * j + ((lane & 1) << 1) + ((lane >> 1) & 1)] += s;
 }
 
 struct LaneGrad {
@@ -421,6 +421,7 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
       }
     }
     if (ballot(any) != 0) acc_wall(acc, jw, gax - gex, gay - gey, gex, gey, lane);
+    return true;
   });
 
   // -- gradients of the points X_0..X_{K+1} from the legs
