@@ -72,7 +72,11 @@ typedef enum drt_smoothing {
 typedef enum drt_loss {
   DRT_LOSS_NONE = 0,               /* no loss, no seed */
   DRT_LOSS_SUM_POWER = 1,          /* L = sum_r P(r) */
-  DRT_LOSS_NEG_MEAN_LOG_POWER = 2  /* L = -(1/R) sum_r log(P(r) + log_eps) */
+  DRT_LOSS_NEG_MEAN_LOG_POWER = 2, /* L = -(1/R) sum_r log(P(r) + log_eps) */
+  DRT_LOSS_NEG_MIN_POWER = 3       /* L = -min_r P(r): the objective of Eq. 8 (Sec. VI), to be
+                                      maximised, as a loss; dL/dP = -1 at the lowest receiver
+                                      index attaining the minimum, 0 elsewhere.  Needs n_rx >= 1
+                                      (batched: 1 <= n_rx <= 64 in every scene). */
 } drt_loss;
 
 /* One scene.  All array pointers are device pointers. */
@@ -186,6 +190,24 @@ int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_ep
 int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev,
                 int32_t* step_dev, float lr, float b1, float b2, float eps,
                 float lo, float hi, void* stream);
+
+/* Adam on n_points points at once (2 n_points coordinates), same update and
+   clamp as drt_adam_tx with one shared step counter; one launch.
+   x_dev, m_dev, v_dev [n_points][2] in/out; grad_dev [n_points][2] in.
+   n_points >= 1. */
+int drt_adam_points(int32_t n_points, float* x_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                    int32_t* step_dev, float lr, float b1, float b2, float eps, float lo, float hi,
+                    void* stream);
+
+/* Geometric sharpness schedule of the transmitter optimisation (Sec. VI,
+   Fig. 5: alpha grows geometrically from its first to its last value over
+   the iterations).  Writes alpha_i = a_first (a_last / a_first)^(i/(n_iter-1))
+   with i = min(*step_dev, n_iter - 1) into alpha_dev[0..n), reading the step
+   counter on the device (the one drt_adam_points advances), so a loop of
+   schedule + trace + Adam can be captured once and replayed.
+   n_iter >= 2, 0 < a_first, a_last finite, n >= 1. */
+int drt_alpha_schedule(const int32_t* step_dev, int32_t n_iter, float a_first, float a_last,
+                       float* alpha_dev, int32_t n, void* stream);
 
 /* ------------------------------------------------------------------------
  * Many scenes in one persistent launch

@@ -26,8 +26,8 @@ What it computes, following the paper (arXiv 2401.11882):
   (NOT as one minus).  ``V`` is the product of all factors.
 * Received power (Eq. 7 with the dyadic coefficient set to the identity, an
   incoherent sum): ``P(r) = sum_paths V / max(|r - I_k|^2, d_min^2)``.
-* Objective (Sec. II): ``L = -F``; here ``L_log = -(1/R) sum_r log(P(r)+eps)``
-  or ``L_sum = sum_r P(r)``.
+* Objective (Sec. II): ``L = -F``; here ``L_log = -(1/R) sum_r log(P(r)+eps)``,
+  ``L_sum = sum_r P(r)``, or ``L_min = -min_r P(r)`` (Eq. 8, Sec. VI).
 * Gradients: torch autograd (reverse mode) over the same fp64 expressions, in
   the role the paper gives to automatic differentiation (Sec. I, Sec. II).
 
@@ -251,6 +251,9 @@ def loss_value(P, kind: str, log_eps: float = DEFAULT_LOG_EPS) -> float:
         return float(P.sum())
     if kind == "neg_mean_log":
         return float(-np.mean(np.log(P + log_eps)))
+    if kind == "neg_min":
+        # Eq. 8 (Sec. VI): F = min over receivers, maximised; as a loss, -F
+        return float(-np.min(P))
     raise ValueError(kind)
 
 
@@ -261,6 +264,11 @@ def loss_seed(P, kind: str, log_eps: float = DEFAULT_LOG_EPS) -> np.ndarray:
         return np.ones_like(P)
     if kind == "neg_mean_log":
         return -1.0 / (P.size * (P + log_eps))
+    if kind == "neg_min":
+        # derivative of -min: -1 at the minimiser (the lowest index on a tie)
+        g = np.zeros_like(P)
+        g[int(np.argmin(P))] = -1.0
+        return g
     raise ValueError(kind)
 
 

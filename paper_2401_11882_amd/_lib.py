@@ -21,7 +21,7 @@ c_size_t = ctypes.c_size_t
 DRT_OK, DRT_EINVAL, DRT_EWORKSPACE, DRT_ENOTSUP, DRT_EHIP = 0, -1, -2, -3, -4
 DRT_SIGMOID = 0
 DRT_BWD_REUSE_FORWARD = 1
-LOSS = {"none": 0, "sum": 1, "neg_mean_log": 2}
+LOSS = {"none": 0, "sum": 1, "neg_mean_log": 2, "neg_min": 3}
 
 
 class DrtScene(ctypes.Structure):
@@ -72,6 +72,9 @@ _SIGS = {
                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "drt_adam_tx": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,
                      c_float, c_float, c_float, c_void_p], c_int32),
+    "drt_adam_points": ([c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,
+                         c_float, c_float, c_float, c_void_p], c_int32),
+    "drt_alpha_schedule": ([c_void_p, c_int32, c_float, c_float, c_void_p, c_int32, c_void_p], c_int32),
     "drt_plan_create": ([ctypes.POINTER(DrtBatchShape), ctypes.c_char_p, ctypes.POINTER(c_void_p)], c_int32),
     "drt_plan_destroy": ([c_void_p], c_int32),
     "drt_plan_get_config": ([c_void_p, ctypes.POINTER(DrtPlanConfig)], c_int32),

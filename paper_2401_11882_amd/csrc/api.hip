@@ -164,7 +164,7 @@ int check_ws(const Plan& p, void* ws, size_t ws_bytes) {
 }
 
 int check_loss(int32_t loss_kind, float log_eps) {
-  if (loss_kind < DRT_LOSS_NONE || loss_kind > DRT_LOSS_NEG_MEAN_LOG_POWER)
+  if (loss_kind < DRT_LOSS_NONE || loss_kind > DRT_LOSS_NEG_MIN_POWER)
     return fail(DRT_EINVAL, "loss_kind=%d unknown", loss_kind);
   if (loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER && (!std::isfinite(log_eps) || !(log_eps > 0.0f)))
     return fail(DRT_EINVAL, "log_eps must be finite and > 0");
@@ -180,9 +180,16 @@ int enqueue_forward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, 
                                         reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
   if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
   float* loss_part = reinterpret_cast<float*>(w + p.off_loss);
+  const bool min_loss = loss_kind == DRT_LOSS_NEG_MIN_POWER;
   if (p.n_tiles > 0) {
-    e = drt::launch_forward(A, p.n_tiles, p.nw, power, seed, loss_part, loss_kind, log_eps, st);
+    e = drt::launch_forward(A, p.n_tiles, p.nw, power, min_loss ? nullptr : seed, loss_part,
+                            min_loss ? DRT_LOSS_NONE : loss_kind, log_eps, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
+  }
+  if (min_loss) {
+    e = drt::launch_min_seed(power, s->n_rx, loss, seed, st);
+    if (e != hipSuccess) return hip_fail(e, "min-loss launch");
+    return DRT_OK;
   }
   if (loss_kind != DRT_LOSS_NONE && loss) {
     const double scale = loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER
@@ -293,6 +300,7 @@ int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps, float*
   if ((rc = check_loss(loss_kind, log_eps))) return rc;
   if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
   if (seed_dev && loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "seed_dev needs a loss_kind");
+  if (loss_kind == DRT_LOSS_NEG_MIN_POWER && scene->n_rx < 1) return fail(DRT_EINVAL, "min loss needs n_rx >= 1");
   const Plan p = make_plan(scene);
   if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
   const drt::TraceArgs A = make_args(scene, p, ws_dev);
@@ -329,6 +337,7 @@ int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_ep
   if (rc) return rc;
   if ((rc = check_loss(loss_kind, log_eps))) return rc;
   if (loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "forward_backward needs a loss_kind");
+  if (loss_kind == DRT_LOSS_NEG_MIN_POWER && scene->n_rx < 1) return fail(DRT_EINVAL, "min loss needs n_rx >= 1");
   if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
   if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
   if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
@@ -344,6 +353,25 @@ int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_ep
 
 int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev, int32_t* step_dev,
                 float lr, float b1, float b2, float eps, float lo, float hi, void* stream) {
+  return drt_adam_points(1, tx_dev, grad_dev, m_dev, v_dev, step_dev, lr, b1, b2, eps, lo, hi, stream);
+}
+
+int drt_alpha_schedule(const int32_t* step_dev, int32_t n_iter, float a_first, float a_last, float* alpha_dev,
+                       int32_t n, void* stream) {
+  if (!step_dev || !alpha_dev) return fail(DRT_EINVAL, "NULL pointer argument");
+  if (n_iter < 2) return fail(DRT_EINVAL, "n_iter=%d must be >= 2", n_iter);
+  if (n < 1) return fail(DRT_EINVAL, "n=%d must be >= 1", n);
+  if (!(a_first > 0.0f) || !(a_last > 0.0f) || !std::isfinite(a_first) || !std::isfinite(a_last))
+    return fail(DRT_EINVAL, "a_first / a_last must be finite and > 0");
+  hipError_t e = drt::launch_alpha_schedule(step_dev, n_iter, a_first, a_last, alpha_dev, n,
+                                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "alpha schedule launch");
+  return DRT_OK;
+}
+
+int drt_adam_points(int32_t n_points, float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev,
+                    int32_t* step_dev, float lr, float b1, float b2, float eps, float lo, float hi, void* stream) {
+  if (n_points < 1) return fail(DRT_EINVAL, "n_points=%d must be >= 1", n_points);
   if (!tx_dev || !grad_dev || !m_dev || !v_dev || !step_dev)
     return fail(DRT_EINVAL, "NULL pointer argument");
   if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(DRT_EINVAL, "lr must be finite and > 0");
@@ -351,8 +379,8 @@ int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev
     return fail(DRT_EINVAL, "betas must lie in [0, 1)");
   if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(DRT_EINVAL, "eps must be finite and > 0");
   if (!(lo <= hi)) return fail(DRT_EINVAL, "lo > hi");
-  hipError_t e = drt::launch_adam_tx(tx_dev, grad_dev, m_dev, v_dev, step_dev, lr, b1, b2, eps, lo, hi,
-                                     static_cast<hipStream_t>(stream));
+  hipError_t e = drt::launch_adam_points(2 * n_points, tx_dev, grad_dev, m_dev, v_dev, step_dev, lr, b1, b2, eps,
+                                         lo, hi, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "adam launch");
   return DRT_OK;
 }

@@ -191,8 +191,13 @@ int enqueue(drt_plan* p, const drt_batch* b, int loss_kind, float log_eps, float
 }
 
 int check_outputs(const drt_plan* p, int loss_kind, float log_eps, float* power, float* gtx, float* gw) {
-  if (loss_kind < DRT_LOSS_NONE || loss_kind > DRT_LOSS_NEG_MEAN_LOG_POWER)
+  if (loss_kind < DRT_LOSS_NONE || loss_kind > DRT_LOSS_NEG_MIN_POWER)
     return failf(DRT_EINVAL, "loss_kind=%d unknown", loss_kind);
+  if (loss_kind == DRT_LOSS_NEG_MIN_POWER)
+    for (int s = 0; s < p->n_scenes; ++s) {
+      const int R = p->rx_off[s + 1] - p->rx_off[s];
+      if (R < 1 || R > 64) return failf(DRT_EINVAL, "min loss needs 1..64 receivers per scene (scene %d has %d)", s, R);
+    }
   if (loss_kind == DRT_LOSS_NONE) {
     if (p->sum_rx > 0 && !power) return failf(DRT_EINVAL, "power_dev is NULL");
     return DRT_OK;

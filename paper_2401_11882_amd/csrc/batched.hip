@@ -134,6 +134,14 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
           g = -1.0f / ((float)R * (P + B.log_eps));
         }
       }
+      if (B.loss_kind == 3) {
+        // the scene's only tile: -min P, seeded at the lowest index attaining it
+        const float pm = wave_min(live ? P : __builtin_inff());
+        const uint64_t at = ballot(live && P == pm);
+        const bool first = at != 0 && lane == __builtin_ctzll(at);
+        g = first ? -1.0f : 0.0f;
+        lp = first ? -pm : 0.0f;
+      }
       gsh[lane] = g;
       const float tot = wave_sum(lp);
       if (lane == 0) B.loss_part[it] = tot;
@@ -199,7 +207,7 @@ __global__ __launch_bounds__(256) void k_batch_reduce(BatchArgs B, float* __rest
     double t = 0.0;
     for (int it = i0; it < i1; ++it) t += (double)B.loss_part[it];
     const int R = B.rx_off[s + 1] - B.rx_off[s];
-    const double scale = B.loss_kind == 1 ? 1.0 : (R > 0 ? -1.0 / (double)R : 0.0);
+    const double scale = B.loss_kind == 2 ? (R > 0 ? -1.0 / (double)R : 0.0) : 1.0;
     loss[s] = (float)(scale * t);
   }
 }

@@ -42,7 +42,10 @@ size_t backward_lds_bytes(int nw, int n_walls);
 hipError_t launch_reduce_cols(const float* part, int n_rows, int ncol, float* out_head, int n_head,
                               float* out_tail, hipStream_t st);
 hipError_t launch_reduce_scalar(const float* part, int n, double scale, float* out, hipStream_t st);
-hipError_t launch_adam_tx(float* tx, const float* grad, float* m, float* v, int32_t* step, float lr,
-                          float b1, float b2, float eps, float lo, float hi, hipStream_t st);
+hipError_t launch_adam_points(int n, float* x, const float* grad, float* m, float* v, int32_t* step, float lr,
+                              float b1, float b2, float eps, float lo, float hi, hipStream_t st);
+hipError_t launch_alpha_schedule(const int32_t* step, int n_iter, float a_first, float a_last, float* alpha, int n,
+                                 hipStream_t st);
+hipError_t launch_min_seed(const float* power, int n, float* loss, float* seed, hipStream_t st);
 
 }  // namespace drt

@@ -192,6 +192,30 @@ def adam_tx(tx, grad, m, v, step, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8, lo=1e-3, 
                             stream_handle(stream)))
 
 
+def adam_points(x, grad, m, v, step, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8, lo=1e-3, hi=1.0 - 1e-3,
+                stream=None) -> None:
+    """Adam + clamp on x [n, 2] (all points share the int32 step counter)."""
+    for t, nm in ((x, "x"), (grad, "grad"), (m, "m"), (v, "v")):
+        _dev_f32(t, nm)
+        if t.shape != x.shape:
+            raise ValueError(f"{nm} shape {tuple(t.shape)} differs from x {tuple(x.shape)}")
+    if x.dim() != 2 or x.shape[1] != 2:
+        raise ValueError("x must be [n, 2]")
+    if step.dtype != torch.int32 or step.device.type != "cuda":
+        raise ValueError("step must be an int32 GPU tensor")
+    check(lib().drt_adam_points(int(x.shape[0]), _ptr(x), _ptr(grad), _ptr(m), _ptr(v), _ptr(step), lr, b1, b2,
+                                eps, lo, hi, stream_handle(stream)))
+
+
+def alpha_schedule(step, n_iter: int, a_first: float, a_last: float, out: torch.Tensor, stream=None) -> None:
+    """out[:] = a_first (a_last / a_first)^(min(step, n_iter-1) / (n_iter-1)), step read on the device."""
+    _dev_f32(out, "out")
+    if step.dtype != torch.int32 or step.device.type != "cuda":
+        raise ValueError("step must be an int32 GPU tensor")
+    check(lib().drt_alpha_schedule(_ptr(step), int(n_iter), float(a_first), float(a_last), _ptr(out),
+                                   int(out.numel()), stream_handle(stream)))
+
+
 class SmoothedPower(torch.autograd.Function):
     """P(r) as a differentiable function of (walls, tx, rx); adjoint in HIP."""
 

@@ -138,6 +138,20 @@ def batch_scenes(n_scenes: int = 512, lo: int = 8, hi: int = 128,
     return out
 
 
+def placement_problem(scene: int, n_rx: int, alpha: float = 1.0) -> Scene:
+    """One transmitter-placement problem (Sec. VI): box + 2..5 interior segments
+    of length U(0.2, 0.5), n_rx receivers ~U[0.05, 0.95]^2 and a start
+    position tx ~U[0.05, 0.95]^2; line of sight only (order 0), as in the
+    paper's example.  Receivers are scattered (grid_n = 0)."""
+    rng = rng_for(6, 1000 * int(n_rx) + int(scene))
+    n_int = int(rng.integers(2, 6))
+    segs = random_segments(rng, n_int, 0.2, 0.5)
+    walls = np.concatenate([BOX_WALLS, segs], axis=0)
+    rx = rng.uniform(0.05, 0.95, (n_rx, 2)).astype(np.float32)
+    tx = rng.uniform(0.05, 0.95, 2).astype(np.float32)
+    return Scene(walls, tx, rx, 0, 0, alpha)
+
+
 def random_points(config: int, scene: int, n: int) -> np.ndarray:
     """n points ~U[0,1]^2 as float32 [n, 2] (transmitter starts, sampled receivers)."""
     rng = rng_for(config, 1000 + scene)
