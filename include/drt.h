@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define DRT_ABI_VERSION 1
+#define DRT_ABI_VERSION 2
 #define DRT_MAX_ORDER 3      /* LOS + up to three reflections */
 #define DRT_MAX_WALLS 1024
 
@@ -66,7 +66,9 @@ typedef enum drt_status {
 } drt_status;
 
 typedef enum drt_smoothing {
-  DRT_SIGMOID = 0       /* Eq. 4: 1 / (1 + exp(-alpha x)) */
+  DRT_SIGMOID = 0,      /* Eq. 4: 1 / (1 + exp(-alpha x)) */
+  DRT_HARD_SIGMOID = 1  /* Eq. 5-6: relu6(alpha x + 3) / 6; every factor is exactly 0 or 1
+                           beyond 3 / alpha of its interval's ends, no transcendentals */
 } drt_smoothing;
 
 typedef enum drt_loss {
@@ -241,6 +243,7 @@ typedef struct drt_batch {
   const float* alpha_dev;  /* [n_scenes], each finite and > 0 (not checked
                               on the host: it lives on the device) */
   float d_min;             /* finite, > 0 */
+  int32_t smoothing;       /* drt_smoothing, the same for every scene */
 } drt_batch;
 
 /* Launch shape of a plan.  nw: 4, 8 or 16 wavefronts per workgroup; cchunk:

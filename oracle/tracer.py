@@ -7,8 +7,10 @@ only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 What it computes, following the paper (arXiv 2401.11882):
 
 * Smoothing (Sec. III, Eq. 3 and Eq. 4): a comparison ``x0 > x1`` becomes
-  ``s(x0 - x1; alpha)`` with ``s(x; alpha) = sigmoid(alpha * x)``.  The hard
-  reference uses the unit step of Eq. 1 instead.
+  ``s(x0 - x1; alpha)`` with ``s(x; alpha) = sigmoid(alpha * x)``
+  (mode "sigmoid") or the hard sigmoid of Eq. 5-6,
+  ``relu6(alpha x + 3) / 6`` (mode "hard_sigmoid").  The unsmoothed
+  reference (mode "hard") uses the unit step of Eq. 1 instead.
 * Candidates (Sec. IV): every ordered sequence of walls of length 0..K with no
   wall repeated back to back (full visibility matrix, box walls included).
 * Path in the relaxed scene (Sec. IV and Sec. IV-B): the image method over
@@ -82,6 +84,11 @@ def _log_inside(x, alpha):
 
 def _hard_inside(x):
     return ((x > 0) & (x < 1)).to(DTYPE)
+
+
+def _hs_inside(x, alpha):
+    """hard sigmoid(x) * hard sigmoid(1 - x) (Eq. 5-6): the check 0 < x < 1."""
+    return hard_sigmoid(x, alpha) * hard_sigmoid(1.0 - x, alpha)
 
 
 def _cross(u, v):
@@ -172,6 +179,8 @@ def _group_terms(walls, tx, rxc, seq, alpha, mode, d_min, want_paths=False):
         X[i] = A + t[..., None] * E
         if mode == "sigmoid":
             log_f = log_f + _log_inside(t, alpha) + _log_inside(u, alpha)
+        elif mode == "hard_sigmoid":
+            f_hard = f_hard * _hs_inside(t, alpha) * _hs_inside(u, alpha)
         else:
             f_hard = f_hard * _hard_inside(t) * _hard_inside(u)
         params[i] = (t, u)
@@ -196,6 +205,8 @@ def _group_terms(walls, tx, rxc, seq, alpha, mode, d_min, want_paths=False):
         ups = _cross(w0, e[None, None]) / den_s          # along the leg
         if mode == "sigmoid":
             q = -torch.expm1(_log_inside(tau, alpha) + _log_inside(ups, alpha))
+        elif mode == "hard_sigmoid":
+            q = 1.0 - _hs_inside(tau, alpha) * _hs_inside(ups, alpha)
         else:
             q = 1.0 - _hard_inside(tau) * _hard_inside(ups)
         q = torch.where(use, q, torch.ones_like(q))
@@ -301,18 +312,18 @@ def vjp(walls, tx, rx, max_order: int, alpha: float, g, mode: str = "sigmoid",
 
 
 def forward_backward(walls, tx, rx, max_order, alpha, kind="neg_mean_log",
-                     log_eps=DEFAULT_LOG_EPS, d_min=DEFAULT_DMIN, rx_weight=None):
+                     log_eps=DEFAULT_LOG_EPS, d_min=DEFAULT_DMIN, rx_weight=None, mode="sigmoid"):
     """Power map, loss, and loss gradients w.r.t. walls and tx.
 
     ``rx_weight`` (optional 0/1 mask) restricts the gradient to a receiver
     subset while the loss seed keeps the full-map normalisation.
     """
-    P = power(walls, tx, rx, max_order, alpha, d_min=d_min)
+    P = power(walls, tx, rx, max_order, alpha, mode=mode, d_min=d_min)
     L = loss_value(P, kind, log_eps)
     g = loss_seed(P, kind, log_eps)
     if rx_weight is not None:
         g = g * np.asarray(rx_weight, dtype=np.float64)
-    gw, gt, grx = vjp(walls, tx, rx, max_order, alpha, g, d_min=d_min)
+    gw, gt, grx = vjp(walls, tx, rx, max_order, alpha, g, mode=mode, d_min=d_min)
     return P, L, gw, gt, grx
 
 

@@ -20,6 +20,8 @@ c_size_t = ctypes.c_size_t
 
 DRT_OK, DRT_EINVAL, DRT_EWORKSPACE, DRT_ENOTSUP, DRT_EHIP = 0, -1, -2, -3, -4
 DRT_SIGMOID = 0
+DRT_HARD_SIGMOID = 1
+SMOOTHING = {"sigmoid": DRT_SIGMOID, "hard_sigmoid": DRT_HARD_SIGMOID}
 DRT_BWD_REUSE_FORWARD = 1
 LOSS = {"none": 0, "sum": 1, "neg_mean_log": 2, "neg_min": 3}
 
@@ -40,7 +42,7 @@ class DrtBatchShape(ctypes.Structure):
 
 class DrtBatch(ctypes.Structure):
     _fields_ = [("walls_dev", c_void_p), ("tx_dev", c_void_p), ("rx_dev", c_void_p), ("alpha_dev", c_void_p),
-                ("d_min", c_float)]
+                ("d_min", c_float), ("smoothing", c_int32)]
 
 
 class DrtPlanConfig(ctypes.Structure):

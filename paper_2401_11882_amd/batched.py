@@ -19,7 +19,7 @@ class BatchPlan:
     """
 
     def __init__(self, scenes, max_order: int, device="cuda", d_min: float = DEFAULT_DMIN,
-                 tune_cache: str | None = None):
+                 tune_cache: str | None = None, smoothing: str = "sigmoid"):
         self.device = torch.device(device)
         self.n_scenes = len(scenes)
         self.max_order = int(max_order)
@@ -36,6 +36,7 @@ class BatchPlan:
                                device=self.device).reshape(-1, 2).contiguous()
         self.alpha = torch.tensor(np.array([s.alpha for s in scenes], dtype=np.float32), device=self.device)
         self.d_min = float(d_min)
+        self.smoothing = _lib.SMOOTHING[smoothing]
         shape = DrtBatchShape(self.n_scenes,
                               self.n_walls.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                               self.n_rx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -57,7 +58,8 @@ class BatchPlan:
 
     def _batch(self) -> DrtBatch:
         return DrtBatch(self.walls.data_ptr() if self.walls.numel() else None, self.tx.data_ptr(),
-                        self.rx.data_ptr() if self.rx.numel() else None, self.alpha.data_ptr(), self.d_min)
+                        self.rx.data_ptr() if self.rx.numel() else None, self.alpha.data_ptr(), self.d_min,
+                        self.smoothing)
 
     def run(self, loss: str = "neg_mean_log", log_eps: float = DEFAULT_LOG_EPS, stream=None):
         """(power [sum R], loss [S], grad_tx [S,2], grad_walls [sum W,4]) in the plan's own buffers.

@@ -77,7 +77,8 @@ int check_scene(const drt_scene* s) {
     return fail(DRT_EINVAL, "alpha must be finite and > 0");
   if (!std::isfinite(s->d_min) || !(s->d_min > 0.0f))
     return fail(DRT_EINVAL, "d_min must be finite and > 0");
-  if (s->smoothing != DRT_SIGMOID) return fail(DRT_ENOTSUP, "smoothing=%d not supported", s->smoothing);
+  if (s->smoothing != DRT_SIGMOID && s->smoothing != DRT_HARD_SIGMOID)
+    return fail(DRT_ENOTSUP, "smoothing=%d not supported", s->smoothing);
   if (s->rx_grid_nx != 0) {
     const int nx = s->rx_grid_nx;
     if (nx < 0 || nx % 8 != 0 || s->n_rx % (8 * nx) != 0)
@@ -142,8 +143,10 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.screen = g_screen;
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
-  A.band_k = 1.0f + 2.0f * drt::kBandMargin / s->alpha;
-  A.cull_c = drt::kCullMargin / s->alpha;
+  const bool hard = s->smoothing == DRT_HARD_SIGMOID;
+  A.mode = hard ? 1 : 0;
+  A.band_k = 1.0f + 2.0f * (hard ? drt::kHardBandMargin : drt::kBandMargin) / s->alpha;
+  A.cull_c = (hard ? drt::kHardCullMargin : drt::kCullMargin) / s->alpha;
   A.dmin2 = s->d_min * s->d_min;
   if (p.cache_cap > 0) {
     char* w = static_cast<char*>(ws);
@@ -175,7 +178,7 @@ int check_loss(int32_t loss_kind, float log_eps) {
 int enqueue_forward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A, int32_t loss_kind,
                     float log_eps, float* power, float* loss, float* seed, void* ws, hipStream_t st) {
   char* w = static_cast<char*>(ws);
-  hipError_t e = drt::launch_prep_walls(s->walls_dev, s->n_walls, s->alpha,
+  hipError_t e = drt::launch_prep_walls(s->walls_dev, s->n_walls, A.cull_c,
                                         reinterpret_cast<drt::WallRec*>(w + p.off_walls),
                                         reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
   if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
@@ -322,7 +325,7 @@ int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t fl
   const drt::TraceArgs A = make_args(scene, p, ws_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws_dev);
-  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls, scene->alpha,
+  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls, A.cull_c,
                                         reinterpret_cast<drt::WallRec*>(w + p.off_walls),
                                         reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
   if (e != hipSuccess) return hip_fail(e, "prep_walls launch");

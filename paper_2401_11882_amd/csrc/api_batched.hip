@@ -146,6 +146,8 @@ int check_batch(const drt_plan* p, const drt_batch* b) {
   if (!b->tx_dev || !b->alpha_dev) return failf(DRT_EINVAL, "tx_dev / alpha_dev is NULL");
   if (p->sum_rx > 0 && !b->rx_dev) return failf(DRT_EINVAL, "rx_dev is NULL");
   if (!std::isfinite(b->d_min) || !(b->d_min > 0.0f)) return failf(DRT_EINVAL, "d_min must be finite and > 0");
+  if (b->smoothing != DRT_SIGMOID && b->smoothing != DRT_HARD_SIGMOID)
+    return failf(DRT_ENOTSUP, "smoothing=%d not supported", b->smoothing);
   return DRT_OK;
 }
 
@@ -177,6 +179,7 @@ drt::BatchArgs make_args(const drt_plan* p, const drt_batch* b, int loss_kind, f
   B.cache_cap = p->cache_cap;
   B.cchunk = p->cfg.cchunk;
   B.screen = drt_internal_screen();
+  B.mode = b->smoothing == DRT_HARD_SIGMOID ? 1 : 0;
   B.tile_w = p->cfg.tile_w;
   return B;
 }

@@ -35,6 +35,7 @@ struct BatchArgs {
   int cache_cap;
   int cchunk;
   int screen;                  // candidate screen on / off
+  int mode;                    // 0 sigmoid, 1 hard sigmoid
   int tile_w;                  // receivers per tile row on grid scenes (8, 16, 32)
 };
 

@@ -23,10 +23,10 @@ __global__ void k_batch_reset(int* counter) { *counter = 0; }
 // Wall records and culling data for every wall of every scene (one
 // workgroup per scene, alpha per scene).
 __global__ void k_batch_prep(const float* __restrict__ walls, const int* __restrict__ wall_off,
-                             const float* __restrict__ alpha, WallRec* __restrict__ rec,
+                             const float* __restrict__ alpha, float cull_margin, WallRec* __restrict__ rec,
                              WallBox* __restrict__ boxes) {
   const int s = blockIdx.x;
-  const float c = kCullMargin / alpha[s];
+  const float c = cull_margin / alpha[s];
   for (int j = wall_off[s] + threadIdx.x; j < wall_off[s + 1]; j += blockDim.x) {
     WallRec r;
     WallBox q;
@@ -49,7 +49,7 @@ __device__ __forceinline__ int batch_rx_of_lane(int tile, int lane, int nx, int 
   return tile * kWave + lane;
 }
 
-template <int NW>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
   extern __shared__ float smem[];
   __shared__ int item_sh;
@@ -80,10 +80,13 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
     S.n_walls = W;
     S.alpha = alpha;
     S.a2 = alpha * kLog2e;
-    S.band_k = 1.0f + 2.0f * kBandMargin / alpha;
-    S.cull_c = kCullMargin / alpha;
+    S.band_k = 1.0f + 2.0f * (MODE ? kHardBandMargin : kBandMargin) / alpha;
+    S.cull_c = (MODE ? kHardCullMargin : kCullMargin) / alpha;
     S.dmin2 = B.dmin2;
-    S.dead_lim = 128.0f / S.a2 * 1.00001f;
+    S.a6 = alpha * (1.0f / 6.0f);
+    S.a6h = S.a6 + 0.5f;
+    S.a6m = 0.5f - S.a6;
+    S.dead_lim = (MODE ? kHardBandMargin / alpha : 128.0f / S.a2) * 1.00001f;
     // number of candidates of this scene
     int n_cand = 1, term = 0;
     for (int k = 1; k <= B.max_order; ++k) {
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
     const RxBox box = rx_box(rxx, rxy, live);
     for_screened(S.walls, W, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box,
                  [&](int c, const Cand& cd, const float* Ix, const float* Iy) {
-                   const float v = candidate_power_img(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+                   const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
                    kahan_add(sum, comp, v);
                    if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
                      if (nst < B.cache_cap) {
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
         const float Wl = g * cache_c[(size_t)p * kWave + lane];
         if (ballot(Wl != 0.0f) == 0) continue;
         const Cand cd = decode_candidate(c, W);
-        candidate_adjoint_known(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
+        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
       }
     } else {
       const int stride = NW * B.cchunk;
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
         const int c1 = min(c0 + B.cchunk, n_cand);
         for (int c = c0; c < c1; ++c) {
           const Cand cd = decode_candidate(c, W);
-          candidate_adjoint(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
+          candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
         }
       }
     }
@@ -218,15 +221,20 @@ size_t batched_lds_bytes(int nw, int max_walls) {
 
 template <int NW>
 static hipError_t batched_nw(const BatchArgs& B, int n_blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_batched<NW>, dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls), st,
-                     B);
+  if (B.mode)
+    hipLaunchKernelGGL((k_batched<NW, 1>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls),
+                       st, B);
+  else
+    hipLaunchKernelGGL((k_batched<NW, 0>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls),
+                       st, B);
   return hipGetLastError();
 }
 
 hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float* walls_raw, const float* alpha,
                           int n_scenes, float* loss, float* grad_tx, float* grad_walls, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_prep, dim3(n_scenes), dim3(128), 0, st, walls_raw, B.wall_off, alpha,
-                     const_cast<WallRec*>(B.walls), const_cast<WallBox*>(B.boxes));
+                     B.mode ? kHardCullMargin : kCullMargin, const_cast<WallRec*>(B.walls),
+                     const_cast<WallBox*>(B.boxes));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, B.counter);
@@ -243,15 +251,29 @@ hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float*
   return hipGetLastError();
 }
 
+// Resident workgroups per CU for a launch shape (the smaller of the two
+// smoothing modes, so the persistent grid fits either).
 int batched_max_blocks_per_cu(int nw, int max_walls) {
-  int nb = 0;
-  const void* fn = nw == 4 ? reinterpret_cast<const void*>(k_batched<4>)
-                 : nw == 8 ? reinterpret_cast<const void*>(k_batched<8>)
-                           : reinterpret_cast<const void*>(k_batched<16>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nw * kWave, batched_lds_bytes(nw, max_walls)) !=
-      hipSuccess)
-    return 1;
-  return nb > 0 ? nb : 1;
+  const void* fns[2];
+  if (nw == 4) {
+    fns[0] = reinterpret_cast<const void*>(k_batched<4, 0>);
+    fns[1] = reinterpret_cast<const void*>(k_batched<4, 1>);
+  } else if (nw == 8) {
+    fns[0] = reinterpret_cast<const void*>(k_batched<8, 0>);
+    fns[1] = reinterpret_cast<const void*>(k_batched<8, 1>);
+  } else {
+    fns[0] = reinterpret_cast<const void*>(k_batched<16, 0>);
+    fns[1] = reinterpret_cast<const void*>(k_batched<16, 1>);
+  }
+  int best = 1 << 30;
+  for (const void* fn : fns) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nw * kWave, batched_lds_bytes(nw, max_walls)) !=
+        hipSuccess)
+      return 1;
+    best = nb < best ? nb : best;
+  }
+  return best > 0 ? best : 1;
 }
 
 }  // namespace drt

@@ -67,6 +67,9 @@ __device__ __forceinline__ void make_wall(float ax, float ay, float bx, float by
 // so that a culled test is one the per-lane check would also skip.
 constexpr float kBandMargin = 18.0f;
 constexpr float kCullMargin = 20.0f;
+// Hard sigmoid: hs(x) hs(1 - x) is exactly 0 beyond 3 / alpha outside [0, 1].
+constexpr float kHardBandMargin = 3.0f;
+constexpr float kHardCullMargin = 4.0f;
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }

@@ -27,8 +27,16 @@ struct SceneView {
   float band_k;  // 1 + 2 * kBandMargin / alpha
   float cull_c;  // kCullMargin / alpha
   float dmin2;
-  float dead_lim;  // 128 / a2, widened by a relative 1e-5 (see screen.h)
+  float dead_lim;  // parameter range beyond which a factor is exactly 0 (see screen.h)
+  float a6, a6h, a6m;  // hard sigmoid: alpha / 6, alpha / 6 + 1/2, 1/2 - alpha / 6
 };
+
+// Smoothing of the comparisons (Sec. III-B): sigmoid (Eq. 4) or hard sigmoid
+// (Eq. 5-6, relu6(alpha x + 3) / 6 = clamp(x alpha / 6 + 1/2, 0, 1)).
+constexpr int kSigmoid = 0;
+constexpr int kHardSigmoid = 1;
+
+__device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
 template <int K>
 struct Path {
@@ -79,7 +87,7 @@ __device__ __forceinline__ bool path_images(const SceneView& S, Path<K>& P) {
 // Back-trace from the receiver through the images and (if WANT_F) the
 // interaction factors.  With WANT_F, returns false as soon as every lane's
 // factor is exactly 0 (then P.F = 0 and the remaining fields are not filled).
-template <int K, bool WANT_F>
+template <int K, bool WANT_F, int MODE>
 __device__ __forceinline__ bool back_trace(const SceneView& S, float rxx, float rxy, bool ok, Path<K>& P) {
   P.Xx[0] = P.Ix[0];
   P.Xy[0] = P.Iy[0];
@@ -106,17 +114,27 @@ __device__ __forceinline__ bool back_trace(const SceneView& S, float rxx, float 
     P.wx[i - 1] = wx;
     P.wy[i - 1] = wy;
     if (WANT_F) {
-      // exponents of E = exp(-alpha x) for x = t, 1 - t, u, 1 - u
-      const float z1 = -S.a2 * t, z2 = fmaf(S.a2, t, -S.a2);
-      const float z3 = -S.a2 * u, z4 = fmaf(S.a2, u, -S.a2);
       F = good ? F : 0.0f;
-      const bool zero = (F == 0.0f) | (z1 >= 128.0f) | (z2 >= 128.0f) | (z3 >= 128.0f) | (z4 >= 128.0f);
-      if (ballot(!zero) == 0) {
-        P.F = 0.0f;
-        return false;
+      if constexpr (MODE == kSigmoid) {
+        // exponents of E = exp(-alpha x) for x = t, 1 - t, u, 1 - u
+        const float z1 = -S.a2 * t, z2 = fmaf(S.a2, t, -S.a2);
+        const float z3 = -S.a2 * u, z4 = fmaf(S.a2, u, -S.a2);
+        const bool zero = (F == 0.0f) | (z1 >= 128.0f) | (z2 >= 128.0f) | (z3 >= 128.0f) | (z4 >= 128.0f);
+        if (ballot(!zero) == 0) {
+          P.F = 0.0f;
+          return false;
+        }
+        const float E1 = ex2(z1), E2 = ex2(z2), E3 = ex2(z3), E4 = ex2(z4);
+        F *= rcp(((1.0f + E1) * (1.0f + E2)) * ((1.0f + E3) * (1.0f + E4)));
+      } else {
+        // hs(t) hs(1 - t) hs(u) hs(1 - u): exactly 0 beyond 3 / alpha outside [0, 1]
+        F *= (med01(fmaf(S.a6, t, 0.5f)) * med01(fmaf(-S.a6, t, S.a6h))) *
+             (med01(fmaf(S.a6, u, 0.5f)) * med01(fmaf(-S.a6, u, S.a6h)));
+        if (ballot(F != 0.0f) == 0) {
+          P.F = 0.0f;
+          return false;
+        }
       }
-      const float E1 = ex2(z1), E2 = ex2(z2), E3 = ex2(z3), E4 = ex2(z4);
-      F *= rcp(((1.0f + E1) * (1.0f + E2)) * ((1.0f + E3) * (1.0f + E4)));
     }
   }
   P.F = F;
@@ -124,14 +142,14 @@ __device__ __forceinline__ bool back_trace(const SceneView& S, float rxx, float 
 }
 
 // Images, back-trace and (if WANT_F) the interaction factors of candidate cd.
-template <int K, bool WANT_F>
+template <int K, bool WANT_F, int MODE>
 __device__ __forceinline__ bool setup_path(const SceneView& S, const Cand& cd, float txx, float txy,
                                            float rxx, float rxy, bool live, Path<K>& P) {
   path_walls<K>(cd, P);
   P.Ix[0] = txx;
   P.Iy[0] = txy;
   const bool ok = path_images<K>(S, P);
-  return back_trace<K, WANT_F>(S, rxx, rxy, live && ok, P);
+  return back_trace<K, WANT_F, MODE>(S, rxx, rxy, live && ok, P);
 }
 
 struct LegGeom {
@@ -184,6 +202,41 @@ __device__ __forceinline__ ObsVals obstruction_vals(float den, float tn, float u
   o.nu = fmaf(o.E3, o.E4, o.E3 + o.E4);
   o.num = fmaf(o.nt, o.nu, o.nt + o.nu);
   return o;
+}
+
+struct ObsGeom {
+  float tau, ups, inv;
+};
+
+struct ObsHard {
+  float tau, ups, inv, h1, h2, h3, h4, it, iu, q;
+};
+
+// Hard sigmoid: 1 - in(tau) in(ups) = nt + in(tau) nu with nt = 1 - in(tau) =
+// (1 - h1) + h1 (1 - h2), h1 = hs(tau), h2 = hs(1 - tau) (likewise nu): all
+// terms are nonnegative, so a nearly transparent factor keeps its precision.
+__device__ __forceinline__ ObsHard obstruction_hard(const SceneView& S, float den, float tn, float un) {
+  ObsHard o;
+  o.inv = rcp(den);
+  o.tau = tn * o.inv;
+  o.ups = un * o.inv;
+  o.h1 = med01(fmaf(S.a6, o.tau, 0.5f));
+  o.h2 = med01(fmaf(-S.a6, o.tau, S.a6h));
+  o.h3 = med01(fmaf(S.a6, o.ups, 0.5f));
+  o.h4 = med01(fmaf(-S.a6, o.ups, S.a6h));
+  const float d1 = med01(fmaf(-S.a6, o.tau, 0.5f)), d2 = med01(fmaf(S.a6, o.tau, S.a6m));
+  const float d3 = med01(fmaf(-S.a6, o.ups, 0.5f)), d4 = med01(fmaf(S.a6, o.ups, S.a6m));
+  const float nt = fmaf(o.h1, d2, d1), nu = fmaf(o.h3, d4, d3);
+  o.it = o.h1 * o.h2;
+  o.iu = o.h3 * o.h4;
+  o.q = fmaf(o.it, nu, nt);
+  return o;
+}
+
+// d hs(x) hs(1 - x) / dx divided by alpha / 6: h2 where hs(x) is on its ramp,
+// minus h1 where hs(1 - x) is (0 on the flat parts; the kinks take 0).
+__device__ __forceinline__ float hard_ramp(float h1, float h2) {
+  return ((h1 > 0.0f) & (h1 < 1.0f) ? h2 : 0.0f) - ((h2 > 0.0f) & (h2 < 1.0f) ? h1 : 0.0f);
 }
 
 // Wave-uniform oriented box around the band-extended legs
@@ -280,7 +333,7 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
 }
 
 // V times every obstruction factor of the path.
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>& P, float V) {
   LegGeom L[K + 1];
   leg_geoms<K>(P, L);
@@ -296,8 +349,12 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
       const bool it = tau_in_band(L[l], w, S.band_k, den, tn, kd);
       if (ballot(it) == 0) continue;
       if (it && ups_in_band(L[l], w, den, kd, un)) {
-        const ObsVals o = obstruction_vals(den, tn, un, S.a2);
-        V *= o.num * rcp(1.0f + o.num);
+        if constexpr (MODE == kSigmoid) {
+          const ObsVals o = obstruction_vals(den, tn, un, S.a2);
+          V *= o.num * rcp(1.0f + o.num);
+        } else {
+          V *= obstruction_hard(S, den, tn, un).q;
+        }
         upd = true;
       }
     }
@@ -308,13 +365,13 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
 }
 
 // Contribution c = V / max(|r - I_K|^2, d_min^2) of candidate cd at this lane.
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ float path_power(const SceneView& S, const Cand& cd, float txx, float txy,
                                             float rxx, float rxy, bool live) {
   Path<K> P;
-  if (!setup_path<K, true>(S, cd, txx, txy, rxx, rxy, live, P)) return 0.0f;
+  if (!setup_path<K, true, MODE>(S, cd, txx, txy, rxx, rxy, live, P)) return 0.0f;
   if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all<K>(S, P, P.F);
+  const float V = obstruct_all<K, MODE>(S, P, P.F);
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
   const float d2 = fmaf(ex, ex, ey * ey);
   return V / fmaxf(d2, S.dmin2);
@@ -322,7 +379,7 @@ __device__ __forceinline__ float path_power(const SceneView& S, const Cand& cd, 
 
 // Same as path_power with the images I_1..I_K given (wave-uniform; the
 // candidate's walls are known to be nondegenerate).
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                 const float* Iy, float txx, float txy, float rxx, float rxy,
                                                 bool live) {
@@ -335,9 +392,9 @@ __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& 
     P.Ix[i + 1] = Ix[i];
     P.Iy[i + 1] = Iy[i];
   }
-  if (!back_trace<K, true>(S, rxx, rxy, live, P)) return 0.0f;
+  if (!back_trace<K, true, MODE>(S, rxx, rxy, live, P)) return 0.0f;
   if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all<K>(S, P, P.F);
+  const float V = obstruct_all<K, MODE>(S, P, P.F);
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
   const float d2 = fmaf(ex, ex, ey * ey);
   return V / fmaxf(d2, S.dmin2);
@@ -368,7 +425,7 @@ struct LaneGrad {
 // Reverse sweep of one path given Wl = g(r) * c (= dL/dlog V at this lane).
 // Adds wall and transmitter gradients to the wave's accumulator and per-lane
 // transmitter / receiver gradients to G.
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path<K>& P, float Wl,
                                                   float rxx, float rxy, float* acc, int lane,
                                                   LaneGrad& G) {
@@ -396,11 +453,23 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
       const bool it = tau_in_band(L[l], w, S.band_k, den, tn, kd) && act;
       if (ballot(it) == 0) continue;
       if (it && ups_in_band(L[l], w, den, kd, un)) {
-        const ObsVals o = obstruction_vals(den, tn, un, S.a2);
-        const float Ab = 1.0f + o.nt, Bb = 1.0f + o.nu;
-        const float coef = nalpha * Wl * rcp(o.num * Ab * Bb);
-        const float gt = coef * (o.E1 - o.E2) * Bb;
-        const float gu = coef * (o.E3 - o.E4) * Ab;
+        // gt, gu = Wl dlog q / dtau, Wl dlog q / dups
+        float gt, gu;
+        ObsGeom o;
+        if constexpr (MODE == kSigmoid) {
+          const ObsVals v = obstruction_vals(den, tn, un, S.a2);
+          const float Ab = 1.0f + v.nt, Bb = 1.0f + v.nu;
+          const float coef = nalpha * Wl * rcp(v.num * Ab * Bb);
+          gt = coef * (v.E1 - v.E2) * Bb;
+          gu = coef * (v.E3 - v.E4) * Ab;
+          o = ObsGeom{v.tau, v.ups, v.inv};
+        } else {
+          const ObsHard v = obstruction_hard(S, den, tn, un);
+          const float coef = v.q > 0.0f ? -S.a6 * Wl * rcp(v.q) : 0.0f;
+          gt = coef * v.iu * hard_ramp(v.h1, v.h2);
+          gu = coef * v.it * hard_ramp(v.h3, v.h4);
+          o = ObsGeom{v.tau, v.ups, v.inv};
+        }
         const float w0x = w.ax - L[l].Xx, w0y = w.ay - L[l].Xy;
         const float s = fmaf(gt, o.tau, gu * o.ups);
         const float gw0x = o.inv * fmaf(gt, L[l].Dy, gu * w.ey);
@@ -451,11 +520,22 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
   for (int i = 1; i <= K; ++i) {
     const WallRec w = load_wall(S.walls, P.s[i - 1]);
     const float t = P.t[i - 1], u = P.u[i - 1], inv = P.inv[i - 1];
-    const float E1 = ex2(-S.a2 * t), E2 = ex2(fmaf(S.a2, t, -S.a2));
-    const float E3 = ex2(-S.a2 * u), E4 = ex2(fmaf(S.a2, u, -S.a2));
-    const float aw = S.alpha * Wl;
-    const float gti = aw * (one_minus_s(E1) - one_minus_s(E2));
-    const float gu = aw * (one_minus_s(E3) - one_minus_s(E4));
+    // gti, gu = Wl dlog f_i / dt, Wl dlog f_i / du
+    float gti, gu;
+    if constexpr (MODE == kSigmoid) {
+      const float E1 = ex2(-S.a2 * t), E2 = ex2(fmaf(S.a2, t, -S.a2));
+      const float E3 = ex2(-S.a2 * u), E4 = ex2(fmaf(S.a2, u, -S.a2));
+      const float aw = S.alpha * Wl;
+      gti = aw * (one_minus_s(E1) - one_minus_s(E2));
+      gu = aw * (one_minus_s(E3) - one_minus_s(E4));
+    } else {
+      // d log hs(x) / dx = (alpha / 6) / hs(x) on the ramp, 0 on the flat parts
+      const float h1 = med01(fmaf(S.a6, t, 0.5f)), h2 = med01(fmaf(-S.a6, t, S.a6h));
+      const float h3 = med01(fmaf(S.a6, u, 0.5f)), h4 = med01(fmaf(-S.a6, u, S.a6h));
+      const float aw = S.a6 * Wl;
+      gti = aw * (((h1 > 0.0f) & (h1 < 1.0f) ? rcp(h1) : 0.0f) - ((h2 > 0.0f) & (h2 < 1.0f) ? rcp(h2) : 0.0f));
+      gu = aw * (((h3 > 0.0f) & (h3 < 1.0f) ? rcp(h3) : 0.0f) - ((h4 > 0.0f) & (h4 < 1.0f) ? rcp(h4) : 0.0f));
+    }
     // X_i = a + t e
     const float gt = gti + gXx[i] * w.ex + gXy[i] * w.ey;
     float gax = gXx[i], gay = gXy[i];
@@ -528,71 +608,75 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
 }
 
 // Adjoint of one candidate, re-evaluating its forward value first.
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
                                              float rxx, float rxy, bool live, float g, float* acc,
                                              int lane, LaneGrad& G) {
   Path<K> P;
-  if (!setup_path<K, true>(S, cd, txx, txy, rxx, rxy, live, P)) return;
+  if (!setup_path<K, true, MODE>(S, cd, txx, txy, rxx, rxy, live, P)) return;
   if (ballot(P.F != 0.0f && g != 0.0f) == 0) return;
-  const float V = obstruct_all<K>(S, P, P.F);
+  const float V = obstruct_all<K, MODE>(S, P, P.F);
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
   const float d2 = fmaf(ex, ex, ey * ey);
   const float Wl = g * (V / fmaxf(d2, S.dmin2));
   if (ballot(Wl != 0.0f) == 0) return;
-  path_adjoint_core<K>(S, P, Wl, rxx, rxy, acc, lane, G);
+  path_adjoint_core<K, MODE>(S, P, Wl, rxx, rxy, acc, lane, G);
 }
 
 // Adjoint of one candidate whose contribution c is already known.
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint_known(const SceneView& S, const Cand& cd, float txx,
                                                    float txy, float rxx, float rxy, bool live, float Wl,
                                                    float* acc, int lane, LaneGrad& G) {
   Path<K> P;
-  setup_path<K, false>(S, cd, txx, txy, rxx, rxy, live, P);
-  path_adjoint_core<K>(S, P, Wl, rxx, rxy, acc, lane, G);
+  setup_path<K, false, MODE>(S, cd, txx, txy, rxx, rxy, live, P);
+  path_adjoint_core<K, MODE>(S, P, Wl, rxx, rxy, acc, lane, G);
 }
 
+template <int MODE>
 __device__ __forceinline__ float candidate_power(const SceneView& S, const Cand& cd, float txx, float txy,
                                                  float rxx, float rxy, bool live) {
   switch (cd.k) {
-    case 0: return path_power<0>(S, cd, txx, txy, rxx, rxy, live);
-    case 1: return path_power<1>(S, cd, txx, txy, rxx, rxy, live);
-    case 2: return path_power<2>(S, cd, txx, txy, rxx, rxy, live);
-    default: return path_power<3>(S, cd, txx, txy, rxx, rxy, live);
+    case 0: return path_power<0, MODE>(S, cd, txx, txy, rxx, rxy, live);
+    case 1: return path_power<1, MODE>(S, cd, txx, txy, rxx, rxy, live);
+    case 2: return path_power<2, MODE>(S, cd, txx, txy, rxx, rxy, live);
+    default: return path_power<3, MODE>(S, cd, txx, txy, rxx, rxy, live);
   }
 }
 
+template <int MODE>
 __device__ __forceinline__ float candidate_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                      const float* Iy, float txx, float txy, float rxx,
                                                      float rxy, bool live) {
   switch (cd.k) {
-    case 0: return path_power_img<0>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
-    case 1: return path_power_img<1>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
-    case 2: return path_power_img<2>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
-    default: return path_power_img<3>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    case 0: return path_power_img<0, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    case 1: return path_power_img<1, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    case 2: return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    default: return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
   }
 }
 
+template <int MODE>
 __device__ __forceinline__ void candidate_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
                                                   float rxx, float rxy, bool live, float g, float* acc,
                                                   int lane, LaneGrad& G) {
   switch (cd.k) {
-    case 0: path_adjoint<0>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
-    case 1: path_adjoint<1>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
-    case 2: path_adjoint<2>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
-    default: path_adjoint<3>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    case 0: path_adjoint<0, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    case 1: path_adjoint<1, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    case 2: path_adjoint<2, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    default: path_adjoint<3, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
   }
 }
 
+template <int MODE>
 __device__ __forceinline__ void candidate_adjoint_known(const SceneView& S, const Cand& cd, float txx,
                                                         float txy, float rxx, float rxy, bool live,
                                                         float Wl, float* acc, int lane, LaneGrad& G) {
   switch (cd.k) {
-    case 0: path_adjoint_known<0>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
-    case 1: path_adjoint_known<1>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
-    case 2: path_adjoint_known<2>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
-    default: path_adjoint_known<3>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    case 0: path_adjoint_known<0, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    case 1: path_adjoint_known<1, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    case 2: path_adjoint_known<2, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    default: path_adjoint_known<3, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
   }
 }
 

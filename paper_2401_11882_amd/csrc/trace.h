@@ -20,6 +20,7 @@ struct TraceArgs {
   int n_cand;
   int cchunk;            // candidates per chunk handed to one wavefront
   int screen;            // 1: drop candidates that are exactly 0 over a wavefront's receiver box
+  int mode;              // 0 sigmoid, 1 hard sigmoid
   float alpha;
   float a2;              // alpha * log2(e)
   float band_k;          // 1 + 2 * 18 / alpha: unsaturated-test band
@@ -32,7 +33,7 @@ struct TraceArgs {
   int cache_cap;
 };
 
-hipError_t launch_prep_walls(const float* walls, int n, float alpha, WallRec* out, WallBox* boxes,
+hipError_t launch_prep_walls(const float* walls, int n, float cull_c, WallRec* out, WallBox* boxes,
                              hipStream_t st);
 hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power, float* seed,
                           float* loss_part, int loss_kind, float log_eps, hipStream_t st);

@@ -56,11 +56,14 @@ __device__ __forceinline__ SceneView view_of(const TraceArgs& A) {
   S.band_k = A.band_k;
   S.cull_c = A.cull_c;
   S.dmin2 = A.dmin2;
-  S.dead_lim = 128.0f / A.a2 * 1.00001f;
+  S.a6 = A.alpha * (1.0f / 6.0f);
+  S.a6h = S.a6 + 0.5f;
+  S.a6m = 0.5f - S.a6;
+  S.dead_lim = (A.mode ? kHardBandMargin / A.alpha : 128.0f / A.a2) * 1.00001f;
   return S;
 }
 
-template <int NW>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) void k_forward(TraceArgs A, float* __restrict__ power,
                                                         float* __restrict__ seed,
                                                         float* __restrict__ loss_part, int loss_kind,
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(NW * kWave) void k_forward(TraceArgs A, float* __re
   const RxBox box = rx_box(rxx, rxy, live);
   for_screened(S.walls, A.n_walls, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
                [&](int c, const Cand& cd, const float* Ix, const float* Iy) {
-                 const float v = candidate_power_img(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+                 const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
                  kahan_add(sum, comp, v);
                  if (cache_c && ballot(v != 0.0f) != 0) {
                    if (nst < A.cache_cap) {
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(NW * kWave) void k_forward(TraceArgs A, float* __re
 // Adjoint kernel
 // ---------------------------------------------------------------------------
 
-template <int NW>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const float* __restrict__ gP,
                                                          float* __restrict__ part,
                                                          float* __restrict__ grad_rx, int reuse) {
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const floa
         const float Wl = g * cache_c[(size_t)p * kWave + lane];
         if (ballot(Wl != 0.0f) == 0) continue;
         const Cand cd = decode_candidate(c, A.n_walls);
-        candidate_adjoint_known(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
+        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
       }
     } else {
       const int stride = NW * A.cchunk;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const floa
         const int c1 = min(c0 + A.cchunk, A.n_cand);
         for (int c = c0; c < c1; ++c) {
           const Cand cd = decode_candidate(c, A.n_walls);
-          candidate_adjoint(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
+          candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
         }
       }
     }
@@ -262,19 +265,23 @@ __global__ void k_reduce_scalar(const float* __restrict__ part, int n, double sc
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_prep_walls(const float* walls, int n, float alpha, WallRec* out, WallBox* boxes,
+hipError_t launch_prep_walls(const float* walls, int n, float cull_c, WallRec* out, WallBox* boxes,
                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep_walls, dim3((n + 255) / 256), dim3(256), 0, st, walls, n, kCullMargin / alpha,
-                     out, boxes);
+  hipLaunchKernelGGL(k_prep_walls, dim3((n + 255) / 256), dim3(256), 0, st, walls, n, cull_c, out,
+                     boxes);
   return hipGetLastError();
 }
 
 template <int NW>
 static hipError_t fwd_nw(const TraceArgs& A, int n_tiles, float* power, float* seed, float* loss_part,
                          int loss_kind, float log_eps, hipStream_t st) {
-  hipLaunchKernelGGL(k_forward<NW>, dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
-                     loss_kind, log_eps);
+  if (A.mode)
+    hipLaunchKernelGGL((k_forward<NW, 1>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
+                       loss_kind, log_eps);
+  else
+    hipLaunchKernelGGL((k_forward<NW, 0>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
+                       loss_kind, log_eps);
   return hipGetLastError();
 }
 
@@ -297,8 +304,12 @@ template <int NW>
 static hipError_t bwd_nw(const TraceArgs& A, int n_tiles, const float* gP, float* part, float* grad_rx,
                          int reuse, hipStream_t st) {
   const size_t lds = backward_lds_bytes(NW, A.n_walls);
-  hipLaunchKernelGGL(k_backward<NW>, dim3(n_tiles), dim3(NW * kWave), lds, st, A, gP, part, grad_rx,
-                     reuse);
+  if (A.mode)
+    hipLaunchKernelGGL((k_backward<NW, 1>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, gP, part, grad_rx,
+                       reuse);
+  else
+    hipLaunchKernelGGL((k_backward<NW, 0>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, gP, part, grad_rx,
+                       reuse);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ class Scene:
     """Device-resident scene description (walls [W,4], tx [2], rx [R,2])."""
 
     def __init__(self, walls, tx, rx, max_order: int, alpha: float, d_min: float = DEFAULT_DMIN,
-                 grid_nx: int = 0):
+                 grid_nx: int = 0, smoothing: str = "sigmoid"):
         self.walls = _dev_f32(walls, "walls", (4,)) if walls.numel() else walls
         self.tx = _dev_f32(tx, "tx")
         if self.tx.numel() != 2:
@@ -58,6 +58,7 @@ class Scene:
         self.alpha = float(alpha)
         self.d_min = float(d_min)
         self.grid_nx = int(grid_nx)
+        self.smoothing = _lib.SMOOTHING[smoothing]
         self.device = dev
 
     @property
@@ -73,7 +74,7 @@ class Scene:
             walls_dev=self.walls.data_ptr() if self.n_walls else None, n_walls=self.n_walls,
             tx_dev=self.tx.data_ptr(),
             rx_dev=self.rx.data_ptr() if self.n_rx else None, n_rx=self.n_rx, rx_grid_nx=self.grid_nx,
-            max_order=self.max_order, alpha=self.alpha, smoothing=_lib.DRT_SIGMOID, d_min=self.d_min)
+            max_order=self.max_order, alpha=self.alpha, smoothing=self.smoothing, d_min=self.d_min)
 
 
 _WS: dict = {}

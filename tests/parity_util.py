@@ -33,13 +33,13 @@ def perturb(x: np.ndarray, rng, ulps: int = 4) -> np.ndarray:
     return (x.astype(np.float64) + sign * step).astype(np.float32)
 
 
-def kappa(walls, tx, rx, K, alpha, runs: int = 4, seed: int = 0, P0=None):
+def kappa(walls, tx, rx, K, alpha, runs: int = 4, seed: int = 0, P0=None, mode="sigmoid"):
     rng = np.random.default_rng(seed)
     if P0 is None:
-        P0 = T.power(walls, tx, rx, K, alpha)
+        P0 = T.power(walls, tx, rx, K, alpha, mode=mode)
     kap = np.zeros_like(P0)
     for _ in range(runs):
-        P = T.power(perturb(walls, rng), perturb(tx, rng), perturb(rx, rng), K, alpha)
+        P = T.power(perturb(walls, rng), perturb(tx, rng), perturb(rx, rng), K, alpha, mode=mode)
         kap = np.maximum(kap, np.abs(P - P0))
     return P0, kap
 

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol():
 
 def test_version_and_status_strings():
     L = _lib.lib()
-    assert L.drt_abi_version() == 1
+    assert L.drt_abi_version() == 2
     for code in (0, -1, -2, -3, -4):
         assert L.drt_status_string(code)
     assert L.drt_status_string(-99) == b"unknown status"
@@ -84,7 +84,7 @@ def test_workspace_size_host_only():
     ("n_rx", -5, _lib.DRT_EINVAL),
     ("rx_grid_nx", 12, _lib.DRT_EINVAL),
     ("rx_grid_nx", 48, _lib.DRT_EINVAL),
-    ("smoothing", 1, _lib.DRT_ENOTSUP),
+    ("smoothing", 2, _lib.DRT_ENOTSUP),
     ("walls_dev", None, _lib.DRT_EINVAL),
     ("tx_dev", None, _lib.DRT_EINVAL),
     ("rx_dev", None, _lib.DRT_EINVAL),
@@ -123,6 +123,16 @@ def test_call_validation_before_launch():
     assert L.drt_adam_tx(BOGUS, BOGUS, BOGUS, BOGUS, BOGUS, 1e-2, 1.0, 0.999, 1e-8, 0.0, 1.0, None) == _lib.DRT_EINVAL
     assert L.drt_adam_tx(BOGUS, BOGUS, BOGUS, BOGUS, None, 1e-2, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == _lib.DRT_EINVAL
     assert L.drt_adam_tx(BOGUS, BOGUS, BOGUS, BOGUS, BOGUS, 1e-2, 0.9, 0.999, 1e-8, 1.0, 0.0, None) == _lib.DRT_EINVAL
+    assert L.drt_adam_points(0, BOGUS, BOGUS, BOGUS, BOGUS, BOGUS, 1e-2, 0.9, 0.999, 1e-8, 0.0, 1.0, None) == _lib.DRT_EINVAL
+    # schedule arguments
+    assert L.drt_alpha_schedule(BOGUS, 1, 1.0, 100.0, BOGUS, 4, None) == _lib.DRT_EINVAL
+    assert L.drt_alpha_schedule(BOGUS, 100, 0.0, 100.0, BOGUS, 4, None) == _lib.DRT_EINVAL
+    assert L.drt_alpha_schedule(BOGUS, 100, 1.0, 100.0, BOGUS, 0, None) == _lib.DRT_EINVAL
+    assert L.drt_alpha_schedule(None, 100, 1.0, 100.0, BOGUS, 4, None) == _lib.DRT_EINVAL
+    # the min loss needs a receiver; an unknown smoothing is not supported
+    empty = _scene(n_rx=0, rx_dev=None, rx_grid_nx=0)
+    assert L.drt_forward(ctypes.byref(empty), 3, 1e-6, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt_set_screen(2) == _lib.DRT_EINVAL
     # launch config knob
     assert L.drt_set_launch_config(3, 0) == _lib.DRT_EINVAL
     assert L.drt_set_launch_config(0, -1) == _lib.DRT_EINVAL

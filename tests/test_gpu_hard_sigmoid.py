@@ -1,0 +1,130 @@
+"""Hard-sigmoid smoothing (Eq. 5-6) in the HIP kernels against the FP64 reference."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tracer as T
+from paper_2401_11882_amd import workloads as WL
+
+import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+HS = "hard_sigmoid"
+
+
+def _tr():
+    from paper_2401_11882_amd import tracer
+    return tracer
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _scene(s, alpha=None, rx=None, grid=True):
+    tr = _tr()
+    rx_np = s.rx if rx is None else rx
+    return tr.Scene(_dev(s.walls), _dev(s.tx), _dev(rx_np), s.max_order, s.alpha if alpha is None else alpha,
+                    grid_nx=(s.grid_n if (grid and rx is None) else 0), smoothing=HS)
+
+
+def test_closed_forms():
+    tr = _tr()
+    a = 0.5 + 1.0 / 50.0
+    walls = np.array([[0.5, a, 0.5, a + 1.0], [0.5, -2.0, 0.5, -1.0]], np.float32)
+    rx = np.array([[0.8, 0.5], [0.8, -1.5]], np.float32)
+    sc = tr.Scene(_dev(walls), _dev([0.2, 0.5]), _dev(rx), 0, 50.0, smoothing=HS)
+    P, _, _ = tr.forward(sc)
+    P = P.cpu().numpy()
+    assert P[0] == pytest.approx((2.0 / 3.0) / 0.36, rel=2e-6)
+    P_o = T.power(walls, np.array([0.2, 0.5]), rx, 0, 50.0, mode=HS)
+    assert P[1] == pytest.approx(P_o[1], rel=2e-6)
+    walls = np.array([[0.5, 0.0, 0.5, 1.0]], np.float32)
+    sc = tr.Scene(_dev(walls), _dev([0.2, 0.5]), _dev([[0.8, 0.5]]), 0, 50.0, smoothing=HS)
+    assert float(tr.forward(sc)[0][0]) == 0.0
+
+
+@pytest.mark.parametrize("K", [0, 1, 2, 3])
+@pytest.mark.parametrize("alpha", [10.0, 50.0])
+def test_small_scenes_all_orders(K, alpha):
+    tr = _tr()
+    s = WL.scene_random_box(2, 5 if K < 3 else 3, 16, K, alpha, seed=30 + K)
+    sc = _scene(s)
+    P, L, gtx, gw, _ = tr.forward_backward(sc, loss="neg_mean_log")
+    P_o, L_o, gw_o, gt_o, _ = T.forward_backward(s.walls, s.tx, s.rx, K, alpha, mode=HS)
+    _, kap = PU.kappa(s.walls, s.tx, s.rx, K, alpha, P0=P_o, mode=HS)
+    PU.check_power(P.cpu().numpy(), P_o, kap, f"hard sigmoid K={K}")
+    # the mean of logs can nearly cancel: compare on the scale of its terms
+    assert float(L) == pytest.approx(L_o, rel=1e-5, abs=1e-5 * float(np.mean(np.abs(np.log(P_o + 1e-6)))))
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, f"hard sigmoid K={K}")
+
+
+@pytest.mark.parametrize("alpha", [50.0, 100.0])
+def test_scene64_full_size_sampled(alpha):
+    """Box + 64 segments, 256 x 256 receivers, order <= 2, in the bench's launch
+    shape; sampled receivers against the reference, gradients over a sampled
+    receiver subset."""
+    tr = _tr()
+    s = WL.scene_64(alpha=alpha)
+    sc = _scene(s)
+    P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    idx = np.unique(np.concatenate([np.random.default_rng(2).choice(s.n_rx, 62, replace=False), [0, s.n_rx - 1]]))
+    P_o, kap = PU.kappa(s.walls, s.tx, s.rx[idx], 2, alpha, mode=HS)
+    PU.check_power(P.cpu().numpy()[idx], P_o, kap, "scene64 hard")
+    w = np.zeros(s.n_rx, np.float32)
+    w[idx[:24]] = 1.0
+    g = seed * _dev(w)
+    gtx, gw, _ = tr.backward(sc, g)
+    gw_o, gt_o, _ = T.vjp(s.walls, s.tx, s.rx[idx[:24]], 2, alpha, seed.cpu().numpy()[idx[:24]], mode=HS)
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, "scene64 hard")
+
+
+def test_screen_exact():
+    tr = _tr()
+    s = WL.scene_64(grid_n=128, alpha=50.0)
+    sc = _scene(s)
+    res = {}
+    try:
+        for on in (True, False):
+            tr.set_screen(on)
+            P, _, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+            g = tr.backward(sc, seed, reuse_forward=True)
+            res[on] = (P.clone(), tr.cache_lists(sc), [t.clone() for t in g if t is not None])
+    finally:
+        tr.set_screen(True)
+    assert torch.equal(res[True][0], res[False][0])
+    assert res[True][1] == res[False][1]
+    for x, y in zip(res[True][2], res[False][2]):
+        assert torch.equal(x, y)
+
+
+def test_cache_reuse_matches_reevaluation():
+    tr = _tr()
+    s = WL.scene_random_box(2, 12, 16, 2, 50.0, seed=8)
+    sc = _scene(s)
+    P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    a = tr.backward(sc, seed, want_rx=True, reuse_forward=True)
+    b = tr.backward(sc, seed, want_rx=True)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x.cpu().numpy(), y.cpu().numpy(), rtol=1e-6, atol=1e-6 * float(y.abs().max()))
+
+
+def test_batched_matches_single():
+    from paper_2401_11882_amd import batched
+    tr = _tr()
+    scenes = WL.batch_scenes(10, side_cap=32, alpha=50.0)
+    plan = batched.BatchPlan(scenes, 2, smoothing=HS)
+    P, L, gtx, gw = [t.clone() for t in plan.run()]
+    for k, s in enumerate(scenes):
+        rs, ws = plan.scene_slice(k)
+        P1, L1, g1, w1, _ = tr.forward_backward(_scene(s), loss="neg_mean_log")
+        torch.testing.assert_close(P[rs], P1, rtol=2e-6, atol=0)
+        assert float(L[k]) == pytest.approx(float(L1), rel=2e-6)
+        assert PU.rel_l2(gtx[k].cpu().numpy(), g1.cpu().numpy()) < 1e-5
+        assert PU.rel_l2(gw[ws].cpu().numpy(), w1.cpu().numpy()) < 1e-5
+    plan.close()
+    s = scenes[3]
+    P_o = T.power(s.walls, s.tx, s.rx[::37], 2, 50.0, mode=HS)
+    _, kap = PU.kappa(s.walls, s.tx, s.rx[::37], 2, 50.0, P0=P_o, mode=HS)
+    rs, _ = plan.scene_slice(3)
+    PU.check_power(P[rs].cpu().numpy()[::37], P_o, kap, "batched hard")
