@@ -17,16 +17,20 @@ from . import tracer as tr
 
 def optimize_tx(walls: torch.Tensor, tx0: torch.Tensor, rx: torch.Tensor, max_order: int, alpha: float,
                 steps: int = 200, lr: float = 1e-2, grid_nx: int = 0, loss: str = "neg_mean_log",
-                lo: float = 1e-3, hi: float = 1.0 - 1e-3, use_graph: bool = True):
-    """Returns dict(tx [2], tx_hist [steps+1, 2], loss_hist [steps]) (device tensors).
+                lo: float = 1e-3, hi: float = 1.0 - 1e-3, use_graph: bool = True, state=None):
+    """Returns dict(tx [2], tx_hist [steps+1, 2], loss_hist [steps], state) (device tensors).
 
     loss_hist[i] is the loss at tx_hist[i]; tx_hist[i+1] is tx after step i.
+    ``state`` (the dict returned by a previous call: Adam moments and step
+    count) continues an earlier run instead of starting Adam afresh.
     """
     dev = tx0.device
     tx = tx0.detach().clone().float().contiguous()
-    m = torch.zeros(2, device=dev)
-    v = torch.zeros(2, device=dev)
-    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    if state is None:
+        state = {"m": torch.zeros(2, device=dev), "v": torch.zeros(2, device=dev),
+                 "step": torch.zeros(1, dtype=torch.int32, device=dev)}
+    m, v, step = state["m"], state["v"], state["step"]
+    step0 = step.clone()
     tx_hist = torch.zeros(steps + 1, 2, device=dev)
     loss_hist = torch.zeros(steps, device=dev)
     tx_hist[0] = tx
@@ -36,7 +40,7 @@ def optimize_tx(walls: torch.Tensor, tx0: torch.Tensor, rx: torch.Tensor, max_or
 
     def one_step():
         tr.forward_backward(sc, loss=loss, out=out)
-        idx = step.long()
+        idx = (step - step0).long()
         loss_hist.index_copy_(0, idx, out[1])
         tr.adam_tx(tx, out[2], m, v, step, lr=lr, lo=lo, hi=hi)
         tx_hist.index_copy_(0, idx + 1, tx.view(1, 2))
@@ -44,7 +48,7 @@ def optimize_tx(walls: torch.Tensor, tx0: torch.Tensor, rx: torch.Tensor, max_or
     if not use_graph:
         for _ in range(steps):
             one_step()
-        return {"tx": tx, "tx_hist": tx_hist, "loss_hist": loss_hist}
+        return {"tx": tx, "tx_hist": tx_hist, "loss_hist": loss_hist, "state": state}
 
     # workspace and kernels warmed outside the capture, then state reset
     tr.forward_backward(sc, loss=loss, out=out)
@@ -60,4 +64,4 @@ def optimize_tx(walls: torch.Tensor, tx0: torch.Tensor, rx: torch.Tensor, max_or
     for _ in range(steps):
         g.replay()
     torch.cuda.synchronize()
-    return {"tx": tx, "tx_hist": tx_hist, "loss_hist": loss_hist}
+    return {"tx": tx, "tx_hist": tx_hist, "loss_hist": loss_hist, "state": state}

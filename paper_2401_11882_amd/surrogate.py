@@ -208,16 +208,24 @@ def plain_search(walls, rx, starts, max_order, alpha, steps, grid_nx=0, target=N
             "exact_steps": used_total}
 
 
-def refine(walls, rx, tx0, max_order, alpha, steps, lr=1e-2, grid_nx=0, target=None):
-    """Adam on tx with the exact tracer from tx0.  Returns (tx_best, F_best,
-    steps_used); stops early once F >= target (checked every 5 steps)."""
+def refine(walls, rx, tx0, max_order, alpha, steps, lr=1e-2, lr_final=1e-4, grid_nx=0, target=None):
+    """Adam on tx with the exact tracer from tx0, the step size decaying
+    geometrically from lr to lr_final (the objective is sharp near its maxima
+    at large alpha, so a constant step keeps circling them).  Returns
+    (tx_best, F_best, steps_used); stops early once F >= target (checked
+    every 5 steps)."""
     from .optimize import optimize_tx
     best_tx, best_F, used = tx0, None, 0
     chunk = 5
+    n_chunks = max(1, (steps + chunk - 1) // chunk)
     tx = torch.as_tensor(tx0, device=rx.device, dtype=torch.float32)
+    state = None
     while used < steps:
         n = min(chunk, steps - used)
-        res = optimize_tx(walls, tx, rx, max_order, alpha, steps=n, lr=lr, grid_nx=grid_nx, use_graph=False)
+        lr_c = lr * (lr_final / lr) ** ((used // chunk) / max(1, n_chunks - 1))
+        res = optimize_tx(walls, tx, rx, max_order, alpha, steps=n, lr=lr_c, grid_nx=grid_nx, use_graph=False,
+                          state=state)
+        state = res["state"]
         L = res["loss_hist"].cpu().numpy()
         txh = res["tx_hist"].cpu().numpy()
         for i in range(n):
@@ -275,11 +283,14 @@ def search(surr: Surrogate, walls, rx_exact, tx_grid_n: int, rx_scan_n: int, top
 
 
 def experiment(seed: int = 0, n_tx: int = 2442, n_rx: int = 4096, epochs: int = 20, holdout_tx: int = 122,
-               n_starts: int = 16, verbose: bool = False):
+               n_starts: int = 48, plain_seeds: int = 3, verbose: bool = False):
     """The surrogate study on the 64-segment scene (alpha 100, order <= 2, 256^2
     receivers): data generation, training, held-out error, F* by the exhaustive
-    reference, then time to reach F >= F* + log 0.99 with plain exact-tracer
-    Adam from seeded random starts vs. the surrogate scan + exact refinement."""
+    reference, then the time to reach F >= F* + log 0.99 with plain exact-tracer
+    Adam from seeded random starts (``plain_seeds`` independent start sets of up
+    to ``n_starts`` each) versus the surrogate scan + exact refinement.  A plain
+    run that does not reach the target counts with its whole time, so the
+    reported speedup is then a lower bound."""
     dev = torch.device("cuda")
     s = WL.scene_64()
     walls = torch.tensor(s.walls, device=dev)
@@ -306,14 +317,21 @@ def experiment(seed: int = 0, n_tx: int = 2442, n_rx: int = 4096, epochs: int = 
     Fs, txs = reference_optimum(s.walls, walls, rx, s.max_order, s.alpha, s.grid_n)
     target = Fs + float(np.log(0.99))
     out.update({"F_star": Fs, "tx_star": [float(x) for x in txs], "target": target})
-    starts = WL.random_points(5, seed, n_starts)
-    plain = plain_search(walls, rx, starts, s.max_order, s.alpha, 100, grid_nx=s.grid_n, target=target)
     sur = search(net, walls, rx, 128, 64, 8, 50, s.max_order, s.alpha, grid_nx=s.grid_n, target=target)
     net.close()
-    for k, d in (("plain", plain), ("surrogate", sur)):
-        out[k] = {kk: (float(vv) if np.isscalar(vv) else [float(x) for x in vv]) for kk, vv in d.items()}
-    out["plain"]["reached"] = bool(plain["F"] >= target)
+    plains = []
+    for k in range(plain_seeds):
+        starts = WL.random_points(5, 100 * seed + k, n_starts)
+        p = plain_search(walls, rx, starts, s.max_order, s.alpha, 50, grid_nx=s.grid_n, target=target)
+        p["reached"] = bool(p["F"] >= target)
+        plains.append(p)
+    out["surrogate"] = {kk: (float(vv) if np.isscalar(vv) else [float(x) for x in vv]) for kk, vv in sur.items()}
     out["surrogate"]["reached"] = bool(sur["F"] >= target)
-    out["speedup"] = plain["t_total"] / sur["t_total"]
-    out["exact_step_ratio"] = plain["exact_steps"] / max(1, sur["exact_steps"])
+    out["plain"] = [{kk: (vv if isinstance(vv, bool) else float(vv) if np.isscalar(vv) else [float(x) for x in vv])
+                     for kk, vv in p.items()} for p in plains]
+    t_plain = float(np.median([p["t_total"] for p in plains]))
+    out["plain_reached"] = sum(p["reached"] for p in plains)
+    out["speedup"] = t_plain / sur["t_total"]
+    out["speedup_is_lower_bound"] = out["plain_reached"] < (plain_seeds + 1) // 2
+    out["exact_step_ratio"] = float(np.median([p["exact_steps"] for p in plains])) / max(1, sur["exact_steps"])
     return out

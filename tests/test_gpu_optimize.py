@@ -25,6 +25,22 @@ def test_graph_loop_equals_eager_loop():
     assert torch.equal(a["loss_hist"], b["loss_hist"])
 
 
+def test_continued_state_equals_one_run():
+    """Three calls of 4 steps that pass the Adam state on == one call of 12."""
+    from paper_2401_11882_amd.optimize import optimize_tx
+    s = WL.scene_random_box(4, 6, 32, 2, 100.0, seed=3)
+    walls, rx = _dev(s.walls), _dev(s.rx)
+    a = optimize_tx(walls, _dev(s.tx), rx, 2, 100.0, steps=12, grid_nx=32, use_graph=False)
+    tx, state, hist = _dev(s.tx), None, []
+    for i in range(3):
+        r = optimize_tx(walls, tx, rx, 2, 100.0, steps=4, grid_nx=32, use_graph=(i == 1), state=state)
+        tx, state = r["tx"], r["state"]
+        hist.append(r["loss_hist"])
+    assert torch.equal(torch.cat(hist), a["loss_hist"])
+    assert torch.equal(tx, a["tx"])
+    assert int(state["step"]) == 12
+
+
 def test_order3_scene_200_steps_gradient_parity_at_own_iterates():
     """Box + 32 segments, 512x512 receivers, order <= 3 (45,397 candidates), alpha 100,
     L = -mean log(P + 1e-6), 200 Adam steps (lr 1e-2) replayed from one captured graph.

@@ -144,5 +144,5 @@ def test_surrogate_guided_search_gain():
     assert r["heldout_rmse"] < 0.5 * r["target_std"]
     assert r["surrogate"]["reached"]
     # the surrogate path needs fewer exact-tracer steps and less time than the plain one
-    assert r["surrogate"]["exact_steps"] < r["plain"]["exact_steps"]
-    assert r["surrogate"]["t_total"] < r["plain"]["t_total"]
+    assert r["exact_step_ratio"] > 1.0
+    assert r["speedup"] > 1.0
