@@ -36,8 +36,11 @@ __device__ __forceinline__ WallRec load_wall(const WallRec* walls, int j) {
 // A wall extended along itself by the culling band, [a - c e, b + c e]
 // (c = kCullMargin / alpha), with its normal n = perp(e) and n . p0: the data
 // the culling test needs for one wall.
+// Culling data of a wall: its segment extended by c |e| at both ends, as
+// centre and half vector, the normal n = perp(e), n . centre, and the margin
+// used against rounding in the normal-axis test.
 struct WallBox {
-  float p0x, p0y, p1x, p1y, nx, ny, nd, pad;
+  float cx, cy, hx, hy, nx, ny, nd, en;
 };
 
 // Record and culling data of the wall (a, b).
@@ -52,14 +55,14 @@ __device__ __forceinline__ void make_wall(float ax, float ay, float bx, float by
   const float ee = ex * ex + ey * ey;
   r.inv_ee = ee > 0.0f ? 1.0f / ee : 0.0f;
   r.pad1 = r.pad2 = 0.0f;
-  q.p0x = fmaf(-c, ex, ax);
-  q.p0y = fmaf(-c, ey, ay);
-  q.p1x = fmaf(c, ex, bx);
-  q.p1y = fmaf(c, ey, by);
+  q.cx = 0.5f * (ax + bx);
+  q.cy = 0.5f * (ay + by);
+  q.hx = (0.5f + c) * ex;
+  q.hy = (0.5f + c) * ey;
   q.nx = -ey;
   q.ny = ex;
-  q.nd = q.nx * q.p0x + q.ny * q.p0y;
-  q.pad = 0.0f;
+  q.nd = q.nx * q.cx + q.ny * q.cy;
+  q.en = 1e-5f * (fabsf(q.nx) + fabsf(q.ny) + fabsf(q.nd));
 }
 
 // Obstruction tests are evaluated only when both parameters lie within

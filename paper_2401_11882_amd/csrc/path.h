@@ -246,7 +246,7 @@ __device__ __forceinline__ float hard_ramp(float h1, float h2) {
 // from it (separating axes u, v and the wall normal) cannot give an
 // unsaturated test on that leg in any lane.
 struct LegBox {
-  float ux, uy, umin, umax, vmin, vmax;  // wave-uniform (scalar registers)
+  float ux, uy, umid, uh, vmid, vh;  // wave-uniform (scalar registers)
   bool empty;
 };
 
@@ -277,21 +277,20 @@ __device__ __forceinline__ void leg_boxes(const Path<K>& P, const LegGeom (&L)[K
     const float ev = 1e-5f * (1.0f + fmaxf(fabsf(cc), fabsf(d)));
     B[l].ux = ux;
     B[l].uy = uy;
-    B[l].umin = uniformf(-a - eu);
-    B[l].umax = uniformf(b + eu);
-    B[l].vmin = uniformf(-cc - ev);
-    B[l].vmax = uniformf(d + ev);
+    B[l].umid = uniformf(0.5f * (b - a));
+    B[l].uh = uniformf(0.5f * (b + a) + eu);
+    B[l].vmid = uniformf(0.5f * (d - cc));
+    B[l].vh = uniformf(0.5f * (d + cc) + ev);
   }
 }
 
 // Calls fn(wall, masks, bit) for every wall that is not separated from some
 // leg box (walls in increasing order) until fn returns false; masks[l] bit
 // `bit` tells whether leg l needs the test (its own end walls are excluded
-// here).  Lane j of the
-// wavefront checks wall b + j of each 64-wall batch.  Separating axes: u and
-// v (projections of the wall's band-extended segment against the box
-// extents) and the wall normal n (the box's range of n . x - n . p0 by
-// interval arithmetic on the extents, against a relative 1e-5 margin).
+// here).  Lane j of the wavefront checks wall b + j of each 64-wall batch.
+// Separating axes: u and v (the wall's projection, centre +- half extent,
+// against the box's) and the wall normal n (the box's range of n . x - n . a
+// from its centre and half extents, against a relative margin).
 template <int K, class Fn>
 __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P, const LegBox (&B)[K + 1],
                                             Fn&& fn) {
@@ -303,23 +302,20 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
     if (valid) {
       q = S.boxes[wj];
     } else {
-      q.p0x = q.p0y = q.p1x = q.p1y = q.nx = q.ny = q.nd = q.pad = 0.0f;
+      q.cx = q.cy = q.hx = q.hy = q.nx = q.ny = q.nd = q.en = 0.0f;
     }
-    const float en = 1e-5f * (fabsf(q.nx) + fabsf(q.ny) + fabsf(q.nd));
     uint64_t m[K + 1];
     uint64_t uni = 0;
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
       const LegBox& L = B[l];
-      const float a0 = L.ux * q.p0x + L.uy * q.p0y, a1 = L.ux * q.p1x + L.uy * q.p1y;
-      const float b0 = L.ux * q.p0y - L.uy * q.p0x, b1 = L.ux * q.p1y - L.uy * q.p1x;
-      const bool sep_u = (fmaxf(a0, a1) < L.umin) | (fminf(a0, a1) > L.umax);
-      const bool sep_v = (fmaxf(b0, b1) < L.vmin) | (fminf(b0, b1) > L.vmax);
-      // n . (s u + t v) - nd over the box: s in [umin, umax], t in [vmin, vmax]
-      const float nu = q.nx * L.ux + q.ny * L.uy, nv = q.ny * L.ux - q.nx * L.uy;
-      const float s_lo = fminf(nu * L.umin, nu * L.umax) + fminf(nv * L.vmin, nv * L.vmax) - q.nd;
-      const float s_hi = fmaxf(nu * L.umin, nu * L.umax) + fmaxf(nv * L.vmin, nv * L.vmax) - q.nd;
-      const bool sep_n = (s_lo > en) | (s_hi < -en);
+      const float uc = fmaf(L.ux, q.cx, L.uy * q.cy), uw = fabsf(fmaf(L.ux, q.hx, L.uy * q.hy));
+      const float vc = fmaf(L.ux, q.cy, -L.uy * q.cx), vw = fabsf(fmaf(L.ux, q.hy, -L.uy * q.hx));
+      const bool sep_u = fabsf(uc - L.umid) > uw + L.uh;
+      const bool sep_v = fabsf(vc - L.vmid) > vw + L.vh;
+      const float nu = fmaf(q.nx, L.ux, q.ny * L.uy), nv = fmaf(q.ny, L.ux, -q.nx * L.uy);
+      const bool sep_n = fabsf(fmaf(L.umid, nu, fmaf(L.vmid, nv, -q.nd))) >
+                         fmaf(fabsf(nu), L.uh, fmaf(fabsf(nv), L.vh, q.en));
       const bool ov = valid & !L.empty & !sep_u & !sep_v & !sep_n & (wj != P.lo[l]) & (wj != P.hi[l]);
       m[l] = ballot(ov);
       uni |= m[l];
