@@ -53,13 +53,17 @@ struct Plan {
   int cchunk;
   int ncol;       // 2 + 4 W
   int cache_cap;  // 0 = no contribution cache
-  size_t off_walls, off_boxes, off_loss, off_seed, off_grad, off_cache_c, off_cache_idx, off_cache_n, total;
+  size_t off_walls, off_boxes, off_loss, off_seed, off_grad, off_cache_c, off_cache_idx, off_cache_n, off_cache_box,
+      total;
+  int box_stride;  // floats of leg boxes per cache entry: 6 (max_order + 1)
 };
 
-int pick_nw(int n_tiles, int n_walls) {
+int pick_nw(int n_tiles, int n_walls, int max_order) {
   int nw = g_nw_override;
   if (nw == 0) nw = n_tiles < 512 ? 16 : (n_tiles < 2048 ? 8 : 4);
-  while (nw > 2 && drt::backward_lds_bytes(nw, n_walls) > 48 * 1024) nw >>= 1;
+  while (nw > 2 && (drt::backward_lds_bytes(nw, n_walls) > 48 * 1024 ||
+                    drt::forward_lds_bytes(nw, max_order) > 48 * 1024))
+    nw >>= 1;
   return nw;
 }
 
@@ -92,7 +96,7 @@ int check_scene(const drt_scene* s) {
 Plan make_plan(const drt_scene* s) {
   Plan p{};
   p.n_tiles = (s->n_rx + drt::kWave - 1) / drt::kWave;
-  p.nw = pick_nw(p.n_tiles, s->n_walls);
+  p.nw = pick_nw(p.n_tiles, s->n_walls, s->max_order);
   p.cchunk = g_cchunk_override > 0 ? g_cchunk_override : 1;
   p.ncol = 2 + 4 * s->n_walls;
   size_t off = 0;
@@ -110,7 +114,8 @@ Plan make_plan(const drt_scene* s) {
   const int64_t n_cand = count_candidates(s->n_walls, s->max_order);
   const int64_t per_wave = (n_cand + (int64_t)p.nw * p.cchunk - 1) / ((int64_t)p.nw * p.cchunk) * p.cchunk;
   const int64_t slots = (int64_t)p.n_tiles * p.nw;
-  const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int);
+  p.box_stride = 6 * (s->max_order + 1);
+  const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int) + (int64_t)p.box_stride * sizeof(float);
   int64_t cap = per_wave;
   if (slots > 0 && g_cache_limit > 0) {
     const int64_t fit = (g_cache_limit - slots * (int64_t)sizeof(int)) / (slots * entry);
@@ -125,6 +130,8 @@ Plan make_plan(const drt_scene* s) {
   off = align_up(off + sizeof(int) * (size_t)slots * p.cache_cap);
   p.off_cache_n = off;
   off = align_up(off + sizeof(int) * (size_t)(p.cache_cap > 0 ? slots : 0));
+  p.off_cache_box = off;
+  off = align_up(off + sizeof(float) * (size_t)slots * p.cache_cap * p.box_stride);
   p.total = off;
   return p;
 }
@@ -145,6 +152,7 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.a2 = s->alpha * drt::kLog2e;
   const bool hard = s->smoothing == DRT_HARD_SIGMOID;
   A.mode = hard ? 1 : 0;
+  A.max_order = s->max_order;
   A.band_k = 1.0f + 2.0f * (hard ? drt::kHardBandMargin : drt::kBandMargin) / s->alpha;
   A.cull_c = (hard ? drt::kHardCullMargin : drt::kCullMargin) / s->alpha;
   A.dmin2 = s->d_min * s->d_min;
@@ -153,7 +161,9 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
     A.cache_c = reinterpret_cast<float*>(w + p.off_cache_c);
     A.cache_idx = reinterpret_cast<int*>(w + p.off_cache_idx);
     A.cache_n = reinterpret_cast<int*>(w + p.off_cache_n);
+    A.cache_box = reinterpret_cast<float*>(w + p.off_cache_box);
     A.cache_cap = p.cache_cap;
+    A.box_stride = p.box_stride;
   }
   return A;
 }

@@ -101,7 +101,7 @@ int apply_config(drt_plan* p, const drt_plan_config& c) {
   if (!(c.nw == 4 || c.nw == 8 || c.nw == 16)) return failf(DRT_EINVAL, "nw=%d must be 4, 8 or 16", c.nw);
   if (c.cchunk < 1 || c.cchunk > 64) return failf(DRT_EINVAL, "cchunk=%d outside [1, 64]", c.cchunk);
   if (!(c.tile_w == 8 || c.tile_w == 16 || c.tile_w == 32)) return failf(DRT_EINVAL, "tile_w=%d must be 8, 16 or 32", c.tile_w);
-  const int maxb = drt::batched_max_blocks_per_cu(c.nw, p->max_walls);
+  const int maxb = drt::batched_max_blocks_per_cu(c.nw, p->max_walls, p->max_order);
   const int bpc = c.blocks_per_cu <= 0 ? maxb : std::min(c.blocks_per_cu, maxb);
   const int blocks = bpc * p->n_cu;
   // contribution cache: one region per wavefront slot of the persistent grid
@@ -180,6 +180,7 @@ drt::BatchArgs make_args(const drt_plan* p, const drt_batch* b, int loss_kind, f
   B.cchunk = p->cfg.cchunk;
   B.screen = drt_internal_screen();
   B.mode = b->smoothing == DRT_HARD_SIGMOID ? 1 : 0;
+  B.box_lds = drt::batched_box_lds(p->cfg.nw, p->max_walls, p->max_order) ? 1 : 0;
   B.tile_w = p->cfg.tile_w;
   return B;
 }
@@ -425,7 +426,7 @@ int drt_batched_autotune(drt_plan* plan, const drt_batch* batch, int32_t loss_ki
   for (int nw : nws)
     for (int cc : chunks)
       for (int tw : tiles) {
-        const int maxb = drt::batched_max_blocks_per_cu(nw, plan->max_walls);
+        const int maxb = drt::batched_max_blocks_per_cu(nw, plan->max_walls, plan->max_order);
         for (int bpc = 1; bpc <= maxb; bpc *= 2) {
           drt_plan_config c{nw, cc, bpc, tw};
           if (run_rc != DRT_OK || apply_config(plan, c) != DRT_OK) continue;

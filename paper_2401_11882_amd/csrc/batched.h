@@ -36,12 +36,14 @@ struct BatchArgs {
   int cchunk;
   int screen;                  // candidate screen on / off
   int mode;                    // 0 sigmoid, 1 hard sigmoid
+  int box_lds;                 // 1: screened candidates' leg boxes kept in LDS
   int tile_w;                  // receivers per tile row on grid scenes (8, 16, 32)
 };
 
 hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float* walls_raw, const float* alpha,
                           int n_scenes, float* loss, float* grad_tx, float* grad_walls, hipStream_t st);
-size_t batched_lds_bytes(int nw, int max_walls);
-int batched_max_blocks_per_cu(int nw, int max_walls);
+size_t batched_lds_bytes(int nw, int max_walls, int max_order);
+bool batched_box_lds(int nw, int max_walls, int max_order);
+int batched_max_blocks_per_cu(int nw, int max_walls, int max_order);
 
 }  // namespace drt

@@ -59,6 +59,8 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
   float* red = smem + NW * ncol_max;         // [NW][2][64]
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x >> 6);
+  // [NW][6 (max_order + 1)][64] leg boxes of screened candidates, when they fit
+  float* boxes = B.box_lds ? red + NW * 2 * kWave + wave * 6 * (B.max_order + 1) * kWave : nullptr;
   const int slot = blockIdx.x * NW + wave;
   float* cache_c = B.cache_c ? B.cache_c + (size_t)slot * B.cache_cap * kWave : nullptr;
   int* cache_idx = B.cache_c ? B.cache_idx + (size_t)slot * B.cache_cap : nullptr;
@@ -105,9 +107,9 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
     float sum = 0.0f, comp = 0.0f;
     int nst = 0;
     const RxBox box = rx_box(rxx, rxy, live);
-    for_screened(S.walls, W, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box,
-                 [&](int c, const Cand& cd, const float* Ix, const float* Iy) {
-                   const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    for_screened(S.walls, W, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box, S.cull_c,
+                    boxes, [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
+                   const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
                    kahan_add(sum, comp, v);
                    if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
                      if (nst < B.cache_cap) {
@@ -215,17 +217,28 @@ __global__ __launch_bounds__(256) void k_batch_reduce(BatchArgs B, float* __rest
   }
 }
 
-size_t batched_lds_bytes(int nw, int max_walls) {
+static size_t batched_base_lds(int nw, int max_walls) {
   return sizeof(float) * ((size_t)nw * (2 + 4 * (size_t)max_walls) + (size_t)nw * 2 * kWave);
+}
+
+// The leg boxes of screened candidates go to LDS when the workgroup's total
+// stays within 64 KiB; otherwise the boxes are formed from the lanes' legs.
+bool batched_box_lds(int nw, int max_walls, int max_order) {
+  return batched_base_lds(nw, max_walls) + sizeof(float) * (size_t)nw * 6 * (max_order + 1) * kWave <= 65536;
+}
+
+size_t batched_lds_bytes(int nw, int max_walls, int max_order) {
+  return batched_base_lds(nw, max_walls) +
+         (batched_box_lds(nw, max_walls, max_order) ? sizeof(float) * (size_t)nw * 6 * (max_order + 1) * kWave : 0);
 }
 
 template <int NW>
 static hipError_t batched_nw(const BatchArgs& B, int n_blocks, hipStream_t st) {
   if (B.mode)
-    hipLaunchKernelGGL((k_batched<NW, 1>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls),
+    hipLaunchKernelGGL((k_batched<NW, 1>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls, B.max_order),
                        st, B);
   else
-    hipLaunchKernelGGL((k_batched<NW, 0>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls),
+    hipLaunchKernelGGL((k_batched<NW, 0>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls, B.max_order),
                        st, B);
   return hipGetLastError();
 }
@@ -253,7 +266,7 @@ hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float*
 
 // Resident workgroups per CU for a launch shape (the smaller of the two
 // smoothing modes, so the persistent grid fits either).
-int batched_max_blocks_per_cu(int nw, int max_walls) {
+int batched_max_blocks_per_cu(int nw, int max_walls, int max_order) {
   const void* fns[2];
   if (nw == 4) {
     fns[0] = reinterpret_cast<const void*>(k_batched<4, 0>);
@@ -268,7 +281,7 @@ int batched_max_blocks_per_cu(int nw, int max_walls) {
   int best = 1 << 30;
   for (const void* fn : fns) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nw * kWave, batched_lds_bytes(nw, max_walls)) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nw * kWave, batched_lds_bytes(nw, max_walls, max_order)) !=
         hipSuccess)
       return 1;
     best = nb < best ? nb : best;

@@ -329,12 +329,30 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
 }
 
 // V times every obstruction factor of the path.
+// With `boxes` (leg boxes stored by the candidate screen, fields of leg l at
+// boxes[(6 l + f) * 64 + j]) the culling boxes are read from there; without,
+// they are formed from the live lanes' legs.
 template <int K, int MODE>
-__device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>& P, float V) {
+__device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>& P, float V,
+                                              const float* boxes = nullptr, int j = 0) {
   LegGeom L[K + 1];
   leg_geoms<K>(P, L);
   LegBox B[K + 1];
-  leg_boxes<K>(P, L, P.F != 0.0f, S.cull_c, B);
+  if (boxes) {
+#pragma unroll
+    for (int l = 0; l <= K; ++l) {
+      const float* b = boxes + 6 * l * kWave + j;  // same address in every lane: to scalar registers
+      B[l].ux = uniformf(b[0]);
+      B[l].uy = uniformf(b[kWave]);
+      B[l].umid = uniformf(b[2 * kWave]);
+      B[l].uh = uniformf(b[3 * kWave]);
+      B[l].vmid = uniformf(b[4 * kWave]);
+      B[l].vh = uniformf(b[5 * kWave]);
+      B[l].empty = false;
+    }
+  } else {
+    leg_boxes<K>(P, L, P.F != 0.0f, S.cull_c, B);
+  }
   visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
     const WallRec w = load_wall(S.walls, jw);
     bool upd = false;
@@ -378,7 +396,7 @@ __device__ __forceinline__ float path_power(const SceneView& S, const Cand& cd, 
 template <int K, int MODE>
 __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                 const float* Iy, float txx, float txy, float rxx, float rxy,
-                                                bool live) {
+                                                bool live, const float* boxes, int j) {
   Path<K> P;
   path_walls<K>(cd, P);
   P.Ix[0] = txx;
@@ -390,7 +408,7 @@ __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& 
   }
   if (!back_trace<K, true, MODE>(S, rxx, rxy, live, P)) return 0.0f;
   if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all<K, MODE>(S, P, P.F);
+  const float V = obstruct_all<K, MODE>(S, P, P.F, boxes, j);
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
   const float d2 = fmaf(ex, ex, ey * ey);
   return V / fmaxf(d2, S.dmin2);
@@ -421,10 +439,28 @@ struct LaneGrad {
 // Reverse sweep of one path given Wl = g(r) * c (= dL/dlog V at this lane).
 // Adds wall and transmitter gradients to the wave's accumulator and per-lane
 // transmitter / receiver gradients to G.
+// Leg boxes recorded by the forward (fields of leg l at gbox[6 l + f], the
+// same address in every lane), read through the scalar data cache.
+template <int K>
+__device__ __forceinline__ void load_leg_boxes(const float* gbox, LegBox (&B)[K + 1]) {
+  typedef __attribute__((address_space(4))) const float* ConstF;
+  const ConstF p = (ConstF)gbox;
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    B[l].ux = p[6 * l];
+    B[l].uy = p[6 * l + 1];
+    B[l].umid = p[6 * l + 2];
+    B[l].uh = p[6 * l + 3];
+    B[l].vmid = p[6 * l + 4];
+    B[l].vh = p[6 * l + 5];
+    B[l].empty = false;
+  }
+}
+
 template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path<K>& P, float Wl,
                                                   float rxx, float rxy, float* acc, int lane,
-                                                  LaneGrad& G) {
+                                                  LaneGrad& G, const float* gbox = nullptr) {
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
   const float d2 = fmaf(ex, ex, ey * ey);
 
@@ -437,7 +473,8 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
   const bool act = Wl != 0.0f;
   const float nalpha = -S.alpha;
   LegBox B[K + 1];
-  leg_boxes<K>(P, L, act, S.cull_c, B);
+  if (gbox) load_leg_boxes<K>(gbox, B);
+  else leg_boxes<K>(P, L, act, S.cull_c, B);
   visit_walls<K>(S, P, B, [&](int jw, const uint64_t* m, int j) {
     const WallRec w = load_wall(S.walls, jw);
     float gax = 0.0f, gay = 0.0f, gex = 0.0f, gey = 0.0f;
@@ -623,10 +660,10 @@ __device__ __forceinline__ void path_adjoint(const SceneView& S, const Cand& cd,
 template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint_known(const SceneView& S, const Cand& cd, float txx,
                                                    float txy, float rxx, float rxy, bool live, float Wl,
-                                                   float* acc, int lane, LaneGrad& G) {
+                                                   float* acc, int lane, LaneGrad& G, const float* gbox) {
   Path<K> P;
   setup_path<K, false, MODE>(S, cd, txx, txy, rxx, rxy, live, P);
-  path_adjoint_core<K, MODE>(S, P, Wl, rxx, rxy, acc, lane, G);
+  path_adjoint_core<K, MODE>(S, P, Wl, rxx, rxy, acc, lane, G, gbox);
 }
 
 template <int MODE>
@@ -643,12 +680,12 @@ __device__ __forceinline__ float candidate_power(const SceneView& S, const Cand&
 template <int MODE>
 __device__ __forceinline__ float candidate_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                      const float* Iy, float txx, float txy, float rxx,
-                                                     float rxy, bool live) {
+                                                     float rxy, bool live, const float* boxes, int j) {
   switch (cd.k) {
-    case 0: return path_power_img<0, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
-    case 1: return path_power_img<1, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
-    case 2: return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
-    default: return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+    case 0: return path_power_img<0, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
+    case 1: return path_power_img<1, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
+    case 2: return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
+    default: return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
   }
 }
 
@@ -667,12 +704,13 @@ __device__ __forceinline__ void candidate_adjoint(const SceneView& S, const Cand
 template <int MODE>
 __device__ __forceinline__ void candidate_adjoint_known(const SceneView& S, const Cand& cd, float txx,
                                                         float txy, float rxx, float rxy, bool live,
-                                                        float Wl, float* acc, int lane, LaneGrad& G) {
+                                                        float Wl, float* acc, int lane, LaneGrad& G,
+                                                        const float* gbox = nullptr) {
   switch (cd.k) {
-    case 0: path_adjoint_known<0, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
-    case 1: path_adjoint_known<1, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
-    case 2: path_adjoint_known<2, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
-    default: path_adjoint_known<3, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G); break;
+    case 0: path_adjoint_known<0, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
+    case 1: path_adjoint_known<1, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
+    case 2: path_adjoint_known<2, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
+    default: path_adjoint_known<3, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
   }
 }
 

@@ -101,16 +101,64 @@ __device__ __forceinline__ bool step_ranges(const WallRec& w, float Ix, float Iy
   return pos | neg;
 }
 
+// Box, in the frame of its own axis, around every leg from a point of the
+// segment [A0, A1] to a point of the convex hull of B[0..3], extended by c of
+// its length at both ends: the extended ends (1 + c) a - c b and
+// (1 + c) b - c a are affine in (a, b), so their extremes along an axis come
+// from the extremes of the two point sets.  Axis: from the middle of A to the
+// middle of B.  Grown by a relative 1e-5 against rounding.  Stored as the
+// fields ux, uy, umid, uh, vmid, vh at out[f * 64].
+__device__ __forceinline__ void store_leg_box(float a0x, float a0y, float a1x, float a1y, const float (&bx)[4],
+                                              const float (&by)[4], float c, float* out) {
+  const float dx = 0.25f * ((bx[0] + bx[1]) + (bx[2] + bx[3])) - 0.5f * (a0x + a1x);
+  const float dy = 0.25f * ((by[0] + by[1]) + (by[2] + by[3])) - 0.5f * (a0y + a1y);
+  const float n2 = dx * dx + dy * dy;
+  const float rn = n2 > 0.0f ? rsqrtf(n2) : 0.0f;
+  const float ux = n2 > 0.0f ? dx * rn : 1.0f, uy = n2 > 0.0f ? dy * rn : 0.0f;
+  const float pa0 = fmaf(ux, a0x, uy * a0y), pa1 = fmaf(ux, a1x, uy * a1y);
+  const float qa0 = fmaf(ux, a0y, -uy * a0x), qa1 = fmaf(ux, a1y, -uy * a1x);
+  float pbl = fmaf(ux, bx[0], uy * by[0]), pbh = pbl;
+  float qbl = fmaf(ux, by[0], -uy * bx[0]), qbh = qbl;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    const float p = fmaf(ux, bx[j], uy * by[j]), q = fmaf(ux, by[j], -uy * bx[j]);
+    pbl = fminf(pbl, p);
+    pbh = fmaxf(pbh, p);
+    qbl = fminf(qbl, q);
+    qbh = fmaxf(qbh, q);
+  }
+  const float pal = fminf(pa0, pa1), pah = fmaxf(pa0, pa1), qal = fminf(qa0, qa1), qah = fmaxf(qa0, qa1);
+  const float c1 = 1.0f + c;
+  const float umin = fminf(fmaf(c1, pal, -c * pbh), fmaf(c1, pbl, -c * pah));
+  const float umax = fmaxf(fmaf(c1, pah, -c * pbl), fmaf(c1, pbh, -c * pal));
+  const float vmin = fminf(fmaf(c1, qal, -c * qbh), fmaf(c1, qbl, -c * qah));
+  const float vmax = fmaxf(fmaf(c1, qah, -c * qbl), fmaf(c1, qbh, -c * qal));
+  out[0] = ux;
+  out[kWave] = uy;
+  out[2 * kWave] = 0.5f * (umin + umax);
+  out[3 * kWave] = 0.5f * (umax - umin) + 1e-5f * (1.0f + fmaxf(fabsf(umin), fabsf(umax)));
+  out[4 * kWave] = 0.5f * (vmin + vmax);
+  out[5 * kWave] = 0.5f * (vmax - vmin) + 1e-5f * (1.0f + fmaxf(fabsf(vmin), fabsf(vmax)));
+}
+
 // Screen of candidate cd (order <= 3) for the receivers in box B.  Fills the
 // images I_1..I_K (Ix[i-1], Iy[i-1]) with the same arithmetic as the
 // per-receiver setup.  Returns false only if every receiver in the box has a
-// zero interaction factor.
+// zero interaction factor.  With `out`, stores the culling box of every leg
+// l = 0..K (fields at out[(6 l + f) * 64]): X_0 = tx, X_{K+1} in the box,
+// and X_i on the part of its wall where it can lie at a receiver of the box
+// with a nonzero factor (the whole range -L..1+L wherever the screen cannot
+// tell, or when `test` is off).
 __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim, bool test, const Cand& cd,
                                                  float txx, float txy, const RxBox& B, float (&Ix)[3],
-                                                 float (&Iy)[3]) {
+                                                 float (&Iy)[3], float c, float* out) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) Ix[i] = Iy[i] = 0.0f;
-  if (cd.k == 0) return true;
+  const float cbx[4] = {B.x0, B.x1, B.x0, B.x1}, cby[4] = {B.y0, B.y0, B.y1, B.y1};
+  if (cd.k == 0) {
+    if (out) store_leg_box(txx, txy, txx, txy, cbx, cby, c, out);
+    return true;
+  }
   const int sv[3] = {cd.s0, cd.s1, cd.s2};
   WallRec w[3];
   float cx = txx, cy = txy;
@@ -131,42 +179,60 @@ __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim
     }
   }
   if (!ok) return false;
-  if (!test) return true;
   const float lo = -lim, hi = 1.0f + lim;
-  // last interaction: the four corners of the receiver box
-  float tlo, thi, ulo, uhi;
-  {
-    const WallRec& wl = cd.k == 1 ? w[0] : (cd.k == 2 ? w[1] : w[2]);
-    const float Lx = cd.k == 1 ? Ix[0] : (cd.k == 2 ? Ix[1] : Ix[2]);
-    const float Ly = cd.k == 1 ? Iy[0] : (cd.k == 2 ? Iy[1] : Iy[2]);
-    const float px[4] = {B.x0, B.x1, B.x0, B.x1}, py[4] = {B.y0, B.y0, B.y1, B.y1};
-    if (!step_ranges<4>(wl, Lx, Ly, px, py, tlo, thi, ulo, uhi)) return true;
-    if (thi < lo || tlo > hi || uhi < lo || ulo > hi) return false;
-  }
-  // earlier interactions: the two ends of the reachable part of the next wall
+  bool known = test;
+  // ends of the range of X_{i+1} (the box corners for i = K)
+  float nx4[4], ny4[4];
 #pragma unroll
-  for (int i = 2; i >= 1; --i) {
-    if (i >= cd.k) continue;
-    const WallRec& wn = w[i];       // wall of interaction i + 1 (holds X_{i+1})
-    const WallRec& wi = w[i - 1];   // wall of interaction i
-    const float t0 = fmaxf(tlo, lo), t1 = fminf(thi, hi);
-    const float px[2] = {fmaf(t0, wn.ex, wn.ax), fmaf(t1, wn.ex, wn.ax)};
-    const float py[2] = {fmaf(t0, wn.ey, wn.ay), fmaf(t1, wn.ey, wn.ay)};
-    if (!step_ranges<2>(wi, Ix[i - 1], Iy[i - 1], px, py, tlo, thi, ulo, uhi)) return true;
-    if (thi < lo || tlo > hi || uhi < lo || ulo > hi) return false;
+  for (int q = 0; q < 4; ++q) {
+    nx4[q] = cbx[q];
+    ny4[q] = cby[q];
   }
+  // interactions K..1, backwards
+#pragma unroll
+  for (int i = 3; i >= 1; --i) {
+    if (i > cd.k) continue;
+    const WallRec& wi = w[i - 1];
+    float t0 = lo, t1 = hi;
+    if (known) {
+      float tlo, thi, ulo, uhi;
+      bool sgn;
+      if (i == cd.k) {
+        sgn = step_ranges<4>(wi, Ix[i - 1], Iy[i - 1], nx4, ny4, tlo, thi, ulo, uhi);
+      } else {
+        const float px[2] = {nx4[0], nx4[1]}, py[2] = {ny4[0], ny4[1]};
+        sgn = step_ranges<2>(wi, Ix[i - 1], Iy[i - 1], px, py, tlo, thi, ulo, uhi);
+      }
+      if (sgn) {
+        if (thi < lo || tlo > hi || uhi < lo || ulo > hi) return false;
+        t0 = fmaxf(tlo, lo);
+        t1 = fminf(thi, hi);
+      } else {
+        known = false;
+      }
+    }
+    const float x0 = fmaf(t0, wi.ex, wi.ax), y0 = fmaf(t0, wi.ey, wi.ay);
+    const float x1 = fmaf(t1, wi.ex, wi.ax), y1 = fmaf(t1, wi.ey, wi.ay);
+    if (out) store_leg_box(x0, y0, x1, y1, nx4, ny4, c, out + 6 * i * kWave);   // leg i: X_i -> X_{i+1}
+    nx4[0] = nx4[2] = x0;
+    ny4[0] = ny4[2] = y0;
+    nx4[1] = nx4[3] = x1;
+    ny4[1] = ny4[3] = y1;
+  }
+  if (out) store_leg_box(txx, txy, txx, txy, nx4, ny4, c, out);                  // leg 0: tx -> X_1
   return true;
 }
 
-// Calls fn(c, cd, Ix, Iy) (wave-uniform arguments: index, decoded walls,
-// images I_1..I_K) for every candidate of this
+// Calls fn(c, cd, Ix, Iy, j) (wave-uniform arguments: index, decoded walls,
+// images I_1..I_K, the lane that screened it) for every candidate of this
 // wavefront's share that survives the screen, in increasing candidate order.
 // The share: chunks of `cchunk` consecutive candidates, chunk q going to
-// wavefront q mod nw.
+// wavefront q mod nw.  With `boxes` (this wavefront's LDS area of
+// 6 (K + 1) x 64 floats), every candidate's leg boxes are stored there.
 template <class Fn>
 __device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, int n_cand, float lim,
                                              bool test, int wave, int nw, int cchunk, float txx, float txy,
-                                             const RxBox& B, Fn&& fn) {
+                                             const RxBox& B, float cull_c, float* boxes, Fn&& fn) {
   if (B.empty) return;
   const int lane = __lane_id();
   for (int p0 = 0;; p0 += kWave) {
@@ -180,7 +246,7 @@ __device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, 
     bool keep = false;
     if (c < n_cand) {
       cd = decode_candidate(c, n_walls);
-      keep = screen_candidate(walls, lim, test, cd, txx, txy, B, Ix, Iy);
+      keep = screen_candidate(walls, lim, test, cd, txx, txy, B, Ix, Iy, cull_c, boxes ? boxes + lane : nullptr);
     }
     uint64_t m = ballot(keep);
     while (m) {
@@ -198,7 +264,7 @@ __device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, 
         jx[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Ix[i]), j));
         jy[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Iy[i]), j));
       }
-      fn(cu, u, jx, jy);
+      fn(cu, u, jx, jy, j);
     }
   }
 }

@@ -21,6 +21,7 @@ struct TraceArgs {
   int cchunk;            // candidates per chunk handed to one wavefront
   int screen;            // 1: drop candidates that are exactly 0 over a wavefront's receiver box
   int mode;              // 0 sigmoid, 1 hard sigmoid
+  int max_order;
   float alpha;
   float a2;              // alpha * log2(e)
   float band_k;          // 1 + 2 * 18 / alpha: unsaturated-test band
@@ -31,6 +32,8 @@ struct TraceArgs {
   int* cache_idx;    // [slots][cache_cap] candidate index of each entry
   int* cache_n;      // [slots] entries, or -1 when the list overflowed
   int cache_cap;
+  float* cache_box;  // [slots][cache_cap][box_stride] culling boxes of each entry's legs
+  int box_stride;
 };
 
 hipError_t launch_prep_walls(const float* walls, int n, float cull_c, WallRec* out, WallBox* boxes,
@@ -40,6 +43,7 @@ hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power,
 hipError_t launch_backward(const TraceArgs& A, int n_tiles, int nw, const float* gP, float* part,
                            float* grad_rx, int reuse, hipStream_t st);
 size_t backward_lds_bytes(int nw, int n_walls);
+size_t forward_lds_bytes(int nw, int max_order);
 hipError_t launch_reduce_cols(const float* part, int n_rows, int ncol, float* out_head, int n_head,
                               float* out_tail, hipStream_t st);
 hipError_t launch_reduce_scalar(const float* part, int n, double scale, float* out, hipStream_t st);

@@ -64,11 +64,12 @@ __device__ __forceinline__ SceneView view_of(const TraceArgs& A) {
 }
 
 template <int NW, int MODE>
-__global__ __launch_bounds__(NW * kWave) void k_forward(TraceArgs A, float* __restrict__ power,
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_forward(TraceArgs A, float* __restrict__ power,
                                                         float* __restrict__ seed,
                                                         float* __restrict__ loss_part, int loss_kind,
                                                         float log_eps) {
   __shared__ float red[NW][2][kWave];
+  extern __shared__ float fwd_boxes[];  // [NW][6 (max_order + 1)][64] leg boxes of screened candidates
   const SceneView S = view_of(A);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x >> 6);
@@ -86,14 +87,17 @@ __global__ __launch_bounds__(NW * kWave) void k_forward(TraceArgs A, float* __re
 
   float sum = 0.0f, comp = 0.0f;
   const RxBox box = rx_box(rxx, rxy, live);
+  float* boxes = fwd_boxes + wave * 6 * (A.max_order + 1) * kWave;
   for_screened(S.walls, A.n_walls, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
-               [&](int c, const Cand& cd, const float* Ix, const float* Iy) {
-                 const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live);
+                  S.cull_c, boxes, [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
+                 const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
                  kahan_add(sum, comp, v);
                  if (cache_c && ballot(v != 0.0f) != 0) {
                    if (nst < A.cache_cap) {
                      cache_c[(size_t)nst * kWave + lane] = v;
                      if (lane == 0) cache_idx[nst] = c;
+                     if (lane < A.box_stride)
+                       A.cache_box[((size_t)slot * A.cache_cap + nst) * A.box_stride + lane] = boxes[lane * kWave + j];
                    }
                    ++nst;
                  }
@@ -164,7 +168,8 @@ __global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const floa
         const float Wl = g * cache_c[(size_t)p * kWave + lane];
         if (ballot(Wl != 0.0f) == 0) continue;
         const Cand cd = decode_candidate(c, A.n_walls);
-        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
+        const float* gbox = A.cache_box + ((size_t)slot * A.cache_cap + p) * A.box_stride;
+        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
       }
     } else {
       const int stride = NW * A.cchunk;
@@ -276,11 +281,12 @@ hipError_t launch_prep_walls(const float* walls, int n, float cull_c, WallRec* o
 template <int NW>
 static hipError_t fwd_nw(const TraceArgs& A, int n_tiles, float* power, float* seed, float* loss_part,
                          int loss_kind, float log_eps, hipStream_t st) {
+  const size_t lds = forward_lds_bytes(NW, A.max_order) - sizeof(float) * NW * 2 * kWave;  // minus static
   if (A.mode)
-    hipLaunchKernelGGL((k_forward<NW, 1>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
+    hipLaunchKernelGGL((k_forward<NW, 1>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, power, seed, loss_part,
                        loss_kind, log_eps);
   else
-    hipLaunchKernelGGL((k_forward<NW, 0>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
+    hipLaunchKernelGGL((k_forward<NW, 0>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, power, seed, loss_part,
                        loss_kind, log_eps);
   return hipGetLastError();
 }
@@ -294,6 +300,10 @@ hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power,
     case 16: return fwd_nw<16>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+size_t forward_lds_bytes(int nw, int max_order) {
+  return sizeof(float) * ((size_t)nw * 6 * (max_order + 1) * kWave + (size_t)nw * 2 * kWave);
 }
 
 size_t backward_lds_bytes(int nw, int n_walls) {
