@@ -70,7 +70,7 @@ struct drt_plan {
   long long* d_part_off = nullptr;
   drt::WallRec* d_rec = nullptr;
   drt::WallBox* d_boxes = nullptr;
-  float *d_loss_part = nullptr, *d_grad_part = nullptr, *d_cache_c = nullptr;
+  float *d_loss_part = nullptr, *d_grad_part = nullptr, *d_cache_c = nullptr, *d_cache_box = nullptr;
   size_t cache_bytes = 0;
 };
 
@@ -79,7 +79,7 @@ namespace {
 void free_plan(drt_plan* p) {
   void* bufs[] = {p->d_wall_off, p->d_rx_off, p->d_grid_nx, p->d_items, p->d_scene_items, p->d_counter,
                   p->d_cache_idx, p->d_part_off, p->d_rec, p->d_boxes, p->d_loss_part, p->d_grad_part,
-                  p->d_cache_c};
+                  p->d_cache_c, p->d_cache_box};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -107,26 +107,32 @@ int apply_config(drt_plan* p, const drt_plan_config& c) {
   // contribution cache: one region per wavefront slot of the persistent grid
   const int64_t per_wave = (p->max_cand + (int64_t)c.nw * c.cchunk - 1) / ((int64_t)c.nw * c.cchunk) * c.cchunk;
   const int64_t slots = (int64_t)blocks * c.nw;
-  const int64_t entry = 64 * (int64_t)sizeof(float) + (int64_t)sizeof(int);
+  const int box_stride = 6 * (p->max_order + 1);
+  const int64_t entry = 64 * (int64_t)sizeof(float) + (int64_t)sizeof(int) + (int64_t)box_stride * sizeof(float);
   int64_t cap = per_wave;
   if (p->cache_limit <= 0) cap = 0;
   else cap = std::min<int64_t>(cap, p->cache_limit / (slots * entry));
   const size_t need_c = (size_t)slots * (size_t)cap * 64 * sizeof(float);
   const size_t need_i = (size_t)slots * (size_t)cap * sizeof(int);
+  const size_t need_b = (size_t)slots * (size_t)cap * box_stride * sizeof(float);
   hipError_t e = hipSetDevice(p->device);
   if (e != hipSuccess) return failf(DRT_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
-  if (need_c + need_i > p->cache_bytes) {
+  if (need_c + need_i + need_b > p->cache_bytes) {
     if (p->d_cache_c) (void)hipFree(p->d_cache_c);
     if (p->d_cache_idx) (void)hipFree(p->d_cache_idx);
+    if (p->d_cache_box) (void)hipFree(p->d_cache_box);
     p->d_cache_c = nullptr;
     p->d_cache_idx = nullptr;
+    p->d_cache_box = nullptr;
     p->cache_bytes = 0;
     if (cap > 0) {
       p->d_cache_c = dev_alloc<float>(need_c / sizeof(float), e);
       if (e != hipSuccess) return failf(DRT_EHIP, "cache allocation (%zu bytes): %s", need_c, hipGetErrorString(e));
       p->d_cache_idx = dev_alloc<int>(need_i / sizeof(int), e);
       if (e != hipSuccess) return failf(DRT_EHIP, "cache index allocation: %s", hipGetErrorString(e));
-      p->cache_bytes = need_c + need_i;
+      p->d_cache_box = dev_alloc<float>(need_b / sizeof(float), e);
+      if (e != hipSuccess) return failf(DRT_EHIP, "cache box allocation: %s", hipGetErrorString(e));
+      p->cache_bytes = need_c + need_i + need_b;
     }
   }
   const std::vector<int> g = grid_for_tile(p, c.tile_w);
@@ -176,6 +182,8 @@ drt::BatchArgs make_args(const drt_plan* p, const drt_batch* b, int loss_kind, f
   B.grad_part = p->d_grad_part;
   B.cache_c = p->cache_cap > 0 ? p->d_cache_c : nullptr;
   B.cache_idx = p->cache_cap > 0 ? p->d_cache_idx : nullptr;
+  B.cache_box = p->cache_cap > 0 ? p->d_cache_box : nullptr;
+  B.box_stride = 6 * (p->max_order + 1);
   B.cache_cap = p->cache_cap;
   B.cchunk = p->cfg.cchunk;
   B.screen = drt_internal_screen();

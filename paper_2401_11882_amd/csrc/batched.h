@@ -32,6 +32,8 @@ struct BatchArgs {
   float* grad_part;            // [sum over items of 2 + 4 W]
   float* cache_c;              // [slots][cache_cap][64] (NULL = no cache)
   int* cache_idx;              // [slots][cache_cap]
+  float* cache_box;            // [slots][cache_cap][box_stride] leg boxes of each entry
+  int box_stride;
   int cache_cap;
   int cchunk;
   int screen;                  // candidate screen on / off

@@ -115,6 +115,8 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
                      if (nst < B.cache_cap) {
                        cache_c[(size_t)nst * kWave + lane] = v;
                        if (lane == 0) cache_idx[nst] = c;
+                       if (boxes && lane < B.box_stride)
+                         B.cache_box[((size_t)slot * B.cache_cap + nst) * B.box_stride + lane] = boxes[lane * kWave + j];
                      }
                      ++nst;
                    }
@@ -164,7 +166,8 @@ __global__ __launch_bounds__(NW * kWave) void k_batched(BatchArgs B) {
         const float Wl = g * cache_c[(size_t)p * kWave + lane];
         if (ballot(Wl != 0.0f) == 0) continue;
         const Cand cd = decode_candidate(c, W);
-        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G);
+        const float* gbox = boxes ? B.cache_box + ((size_t)slot * B.cache_cap + p) * B.box_stride : nullptr;
+        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
       }
     } else {
       const int stride = NW * B.cchunk;

@@ -440,19 +440,19 @@ struct LaneGrad {
 // Adds wall and transmitter gradients to the wave's accumulator and per-lane
 // transmitter / receiver gradients to G.
 // Leg boxes recorded by the forward (fields of leg l at gbox[6 l + f], the
-// same address in every lane), read through the scalar data cache.
+// same address in every lane).  Vector loads, not the scalar data cache: in
+// the batched kernel the same wavefront wrote these entries earlier in the
+// launch, and only vector memory keeps that order.
 template <int K>
 __device__ __forceinline__ void load_leg_boxes(const float* gbox, LegBox (&B)[K + 1]) {
-  typedef __attribute__((address_space(4))) const float* ConstF;
-  const ConstF p = (ConstF)gbox;
 #pragma unroll
   for (int l = 0; l <= K; ++l) {
-    B[l].ux = p[6 * l];
-    B[l].uy = p[6 * l + 1];
-    B[l].umid = p[6 * l + 2];
-    B[l].uh = p[6 * l + 3];
-    B[l].vmid = p[6 * l + 4];
-    B[l].vh = p[6 * l + 5];
+    B[l].ux = uniformf(gbox[6 * l]);
+    B[l].uy = uniformf(gbox[6 * l + 1]);
+    B[l].umid = uniformf(gbox[6 * l + 2]);
+    B[l].uh = uniformf(gbox[6 * l + 3]);
+    B[l].vmid = uniformf(gbox[6 * l + 4]);
+    B[l].vh = uniformf(gbox[6 * l + 5]);
     B[l].empty = false;
   }
 }
