@@ -435,7 +435,8 @@ int drt_batched_autotune(drt_plan* plan, const drt_batch* batch, int32_t loss_ki
     for (int cc : chunks)
       for (int tw : tiles) {
         const int maxb = drt::batched_max_blocks_per_cu(nw, plan->max_walls, plan->max_order);
-        for (int bpc = 1; bpc <= maxb; bpc *= 2) {
+        // powers of two below the resident maximum, and the maximum itself
+        for (int bpc = 1; bpc <= maxb; bpc = (bpc < maxb && 2 * bpc > maxb) ? maxb : 2 * bpc) {
           drt_plan_config c{nw, cc, bpc, tw};
           if (run_rc != DRT_OK || apply_config(plan, c) != DRT_OK) continue;
           float ms = 1e30f;

@@ -93,6 +93,27 @@ def test_batched_deterministic_and_graph_replay():
     plan.close()
 
 
+@pytest.mark.parametrize("nw", [4, 8, 16])
+def test_every_launch_shape_agrees_when_workgroups_take_several_items(nw):
+    """One workgroup per CU, more items than workgroups: each wavefront slot is
+    reused for several items, and its recorded contributions and leg boxes
+    must be the current item's.  Repeated runs are bitwise equal and match
+    the default launch shape."""
+    batched, tr = _mods()
+    scenes = WL.batch_scenes(24, side_cap=32)
+    plan = batched.BatchPlan(scenes, 2)
+    ref = [t.clone() for t in plan.run()]
+    for cc, tw in ((1, 8), (4, 16)):
+        plan.set_config(nw=nw, cchunk=cc, blocks_per_cu=1, tile_w=tw)
+        a = [t.clone() for t in plan.run()]
+        b = [t.clone() for t in plan.run()]
+        for x, y, z in zip(a, b, ref):
+            assert torch.equal(x, y)
+            torch.testing.assert_close(x, z, rtol=1e-5, atol=1e-6 * float(z.abs().max()))
+    assert plan.info()["items"] > 256
+    plan.close()
+
+
 def test_batched_screen_exact():
     batched, tr = _mods()
     scenes = _small_mixed() + WL.batch_scenes(8, side_cap=32)
