@@ -14,7 +14,8 @@
  *      = X_{i+1} + u_i (I_i - X_{i+1});
  *   2. the continuous validity of Sec. IV-A, with every comparison
  *      x0 > x1 replaced by s(x0 - x1; alpha), s = sigmoid(alpha x)
- *      (Eq. 3, Eq. 4), AND as a product and NOT as 1 - s:
+ *      (Eq. 3, Eq. 4) or the hard sigmoid relu6(alpha x + 3) / 6 (Eq. 5-6),
+ *      AND as a product and NOT as 1 - s:
  *        V = prod_i in(t_i) in(u_i) * prod_{legs l} prod_{walls j not at
  *            the leg's ends} (1 - in(tau_lj) in(upsilon_lj)),
  *        in(x) = s(x) s(1 - x);
@@ -28,8 +29,10 @@
  *
  * Conventions shared by every entry point
  *   - Pointers named *_dev are DEVICE pointers, owned by the caller; the
- *     library never allocates, frees or retains them.  Pointers to drt_*
- *     structs are HOST pointers read during the call only.
+ *     library never frees or retains them.  Only drt_plan_create,
+ *     drt_plan_set_config, drt_batched_autotune and drt_mlp_create allocate
+ *     device memory, which their handle owns.  Pointers to drt_* structs are
+ *     HOST pointers read during the call only.
  *   - Layouts: walls float32 [n_walls][4] = (ax, ay, bx, by); tx float32 [2];
  *     rx float32 [n_rx][2]; grad_walls float32 [n_walls][4] in the same
  *     order; power / grad_power float32 [n_rx].
