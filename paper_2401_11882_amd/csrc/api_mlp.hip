@@ -55,14 +55,14 @@ struct drt_mlp {
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *Bf = nullptr;
   int* step = nullptr;
   __bf16 *wbf = nullptr, *wtbf = nullptr, *X0 = nullptr, *H = nullptr, *dZ0 = nullptr, *dZ1 = nullptr;
-  float *yhat = nullptr, *gvec = nullptr, *loss_part = nullptr, *dw_part = nullptr;
+  float *yhat = nullptr, *gvec = nullptr, *loss_part = nullptr, *dw_part = nullptr, *col_part = nullptr;
 };
 
 namespace {
 
 void free_mlp(drt_mlp* h) {
   void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->X0, h->H, h->dZ0, h->dZ1,
-                  h->yhat, h->gvec, h->loss_part, h->dw_part};
+                  h->yhat, h->gvec, h->loss_part, h->dw_part, h->col_part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -106,7 +106,7 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss
   HIPCHK(drt::launch_head(Hl(h, 4), n, h->p + L.head_w, h->p + L.head_b, y, 1.0f / (float)n, h->yhat, h->loss_part,
                           h->gvec, h->dZ0, st),
          "head");
-  HIPCHK(drt::launch_colsum(Hl(h, 4), n, W, h->gvec, h->g + L.head_w, st), "head weight grad");
+  HIPCHK(drt::launch_colsum(Hl(h, 4), n, W, h->gvec, h->col_part, h->g + L.head_w, st), "head weight grad");
   HIPCHK(drt::launch_sum_scalar(h->gvec, n, 1.0, h->g + L.head_b, st), "head bias grad");
   if (loss_dev) HIPCHK(drt::launch_sum_scalar(h->loss_part, n, 1.0 / (double)n, loss_dev, st), "loss");
   // split of the batch dimension for the weight gradients
@@ -117,7 +117,7 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss
   __bf16* dZn = h->dZ1;
   for (int l = drt::kMlpHidden - 1; l >= 0; --l) {
     const int fi = L.fan_in[l];
-    HIPCHK(drt::launch_colsum(dZ, n, W, nullptr, h->g + L.b_off[l], st), "bias grad");
+    HIPCHK(drt::launch_colsum(dZ, n, W, nullptr, h->col_part, h->g + L.b_off[l], st), "bias grad");
     drt::GemmArgs g{};
     g.A = l == 0 ? h->X0 : Hl(h, l - 1);  // A(m = in, k = row) = X[row * fi + in]
     g.lda = fi;
@@ -199,6 +199,7 @@ int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_
   alloc((void**)&h->gvec, nb * 4);
   alloc((void**)&h->loss_part, nb * 4);
   alloc((void**)&h->dw_part, (size_t)h->max_slices * W * W * 4);
+  alloc((void**)&h->col_part, (size_t)drt::colsum_chunks(max_batch) * W * 4);
   if (e == hipSuccess) e = hipMemcpy(h->p, params_host, P * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->Bf, fourier_B_host, drt::kMlpFreq * 4 * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(h->m, 0, P * 4);

@@ -39,7 +39,10 @@ hipError_t launch_features(const float* v, const float* tx, const float* rx, int
 hipError_t launch_gemm(const GemmArgs& g, bool a_mc, bool b_nc, int n_slices, hipStream_t st);
 hipError_t launch_head(const __bf16* H, int n, const float* w, const float* b, const float* y, float inv_total,
                        float* yhat, float* loss_part, float* gout, __bf16* dZ, hipStream_t st);
-hipError_t launch_colsum(const __bf16* X, int M, int N, const float* wt, float* out, hipStream_t st);
+// out[col] = sum_m X[m][col] * (wt ? wt[m] : 1) through per-chunk partials
+// (part: colsum_chunks(M) x N floats), fixed order.
+int colsum_chunks(int M);
+hipError_t launch_colsum(const __bf16* X, int M, int N, const float* wt, float* part, float* out, hipStream_t st);
 hipError_t launch_sum_slices(const float* part, int n_slices, int n, float* out, hipStream_t st);
 hipError_t launch_sum_scalar(const float* x, int n, double scale, float* out, hipStream_t st);
 hipError_t launch_segment_mean(const float* yhat, int T, int R, float* F, hipStream_t st);

@@ -191,22 +191,58 @@ __global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ H, int n,
   }
 }
 
-// out[col] (+)= sum_m X[m][col] * (wt ? wt[m] : 1), FP32, fixed order:
-// 32 columns per workgroup, 32 row groups, partials added in order.
-__global__ __launch_bounds__(1024) void k_colsum(const bf16* __restrict__ X, int M, int N,
-                                                 const float* __restrict__ wt, float* __restrict__ out) {
-  __shared__ float sh[32][33];
-  const int cl = threadIdx.x & 31, rg = threadIdx.x >> 5;
-  const int col = blockIdx.x * 32 + cl;
-  float s = 0.0f;
-  if (col < N)
-    for (int m = rg; m < M; m += 32) s = fmaf((float)X[(size_t)m * N + col], wt ? wt[m] : 1.0f, s);
-  sh[rg][cl] = s;
+// part[chunk][col] = sum over the chunk's kColChunk rows m of
+// X[m][col] * (wt ? wt[m] : 1); one workgroup per (chunk, 256 columns).
+// Thread (row lane r, column group g) reads 8 columns at once (16 bytes) of
+// rows r, r + 8, ... in order; the 8 row lanes are then added in order
+// through LDS (fixed order overall, with k_colsum_fold).  N % 8 == 0.
+constexpr int kColChunk = 128;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const bf16* __restrict__ X, int M, int N,
+                                                     const float* __restrict__ wt, float* __restrict__ part) {
+  __shared__ float sh[8][256];
+  const int cg = threadIdx.x & 31, rl = threadIdx.x >> 5;
+  const int col0 = blockIdx.y * 256 + cg * 8;
+  const int m0 = blockIdx.x * kColChunk, m1 = min(M, m0 + kColChunk);
+  float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (col0 < N) {
+    for (int m = m0 + rl; m < m1; m += 8) {
+      const uint4 raw = *reinterpret_cast<const uint4*>(X + (size_t)m * N + col0);
+      const bf16* x = reinterpret_cast<const bf16*>(&raw);
+      const float w = wt ? wt[m] : 1.0f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] = fmaf((float)x[k], w, s[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[rl][cg * 8 + k] = s[k];
   __syncthreads();
-  if (rg == 0 && col < N) {
+  const int col = blockIdx.y * 256 + threadIdx.x;
+  if (col < N) {
     float t = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) t += sh[q][cl];
+    for (int r = 0; r < 8; ++r) t += sh[r][threadIdx.x];
+    part[(size_t)blockIdx.x * N + col] = t;
+  }
+}
+
+// out[col] = sum over chunks of part[chunk][col]: 32 columns per workgroup,
+// 8 threads per column each adding every 8th chunk in order, then the 8
+// partials in order.
+__global__ __launch_bounds__(256) void k_colsum_fold(const float* __restrict__ part, int chunks, int N,
+                                                     float* __restrict__ out) {
+  __shared__ float sh[8][32];
+  const int c = threadIdx.x & 31, q = threadIdx.x >> 5;
+  const int col = blockIdx.x * 32 + c;
+  float s = 0.0f;
+  if (col < N)
+    for (int z = q; z < chunks; z += 8) s += part[(size_t)z * N + col];
+  sh[q][c] = s;
+  __syncthreads();
+  if (q == 0 && col < N) {
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += sh[k][c];
     out[col] = t;
   }
 }
@@ -220,14 +256,15 @@ __global__ void k_sum_slices(const float* __restrict__ part, int n_slices, int n
   out[i] = s;
 }
 
-// scale * sum(x[0..n)) in FP64, fixed tree order; one workgroup of 256.
-__global__ void k_sum_scalar(const float* __restrict__ x, int n, double scale, float* __restrict__ out) {
-  __shared__ double sh[256];
+// scale * sum(x[0..n)) in FP64, fixed tree order; one workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_sum_scalar(const float* __restrict__ x, int n, double scale,
+                                                     float* __restrict__ out) {
+  __shared__ double sh[1024];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += (double)x[i];
+  for (int i = threadIdx.x; i < n; i += 1024) s += (double)x[i];
   sh[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
@@ -329,8 +366,16 @@ hipError_t launch_head(const bf16* H, int n, const float* w, const float* b, con
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const bf16* X, int M, int N, const float* wt, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_colsum, dim3((N + 31) / 32), dim3(1024), 0, st, X, M, N, wt, out);
+int colsum_chunks(int M) { return (M + kColChunk - 1) / kColChunk; }
+
+hipError_t launch_colsum(const bf16* X, int M, int N, const float* wt, float* part, float* out, hipStream_t st) {
+  const int chunks = colsum_chunks(M);
+  if (chunks <= 0 || N <= 0) return hipSuccess;
+  if (N % 8 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_colsum_part, dim3(chunks, (N + 255) / 256), dim3(256), 0, st, X, M, N, wt, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_fold, dim3((N + 31) / 32), dim3(256), 0, st, part, chunks, N, out);
   return hipGetLastError();
 }
 
@@ -340,7 +385,7 @@ hipError_t launch_sum_slices(const float* part, int n_slices, int n, float* out,
 }
 
 hipError_t launch_sum_scalar(const float* x, int n, double scale, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(256), 0, st, x, n, scale, out);
+  hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(1024), 0, st, x, n, scale, out);
   return hipGetLastError();
 }
 
