@@ -263,7 +263,10 @@ typedef struct drt_plan drt_plan;  /* opaque; owns its device buffers */
    current device (allocates and synchronises; not for graph capture).  If
    tune_cache_path names a file with a line for this device and batch shape,
    its launch shape is used, otherwise a default.  *out must be released with
-   drt_plan_destroy. */
+   drt_plan_destroy.  Each workgroup keeps per-wavefront gradient
+   accumulators for the largest scene's walls in 64 KiB of LDS, so a batch
+   whose largest scene has more than 991 walls is rejected (DRT_EINVAL); a
+   launch shape that does not fit is rejected by drt_plan_set_config. */
 int drt_plan_create(const drt_batch_shape* shape, const char* tune_cache_path, drt_plan** out);
 
 /* Waits for the device, frees the plan's buffers.  NULL is a no-op. */

@@ -76,6 +76,9 @@ struct drt_plan {
 
 namespace {
 
+// Largest workgroup LDS footprint the batched kernel is launched with.
+constexpr size_t kMaxBatchedLds = 64 * 1024;
+
 void free_plan(drt_plan* p) {
   void* bufs[] = {p->d_wall_off, p->d_rx_off, p->d_grid_nx, p->d_items, p->d_scene_items, p->d_counter,
                   p->d_cache_idx, p->d_part_off, p->d_rec, p->d_boxes, p->d_loss_part, p->d_grad_part,
@@ -101,6 +104,9 @@ int apply_config(drt_plan* p, const drt_plan_config& c) {
   if (!(c.nw == 4 || c.nw == 8 || c.nw == 16)) return failf(DRT_EINVAL, "nw=%d must be 4, 8 or 16", c.nw);
   if (c.cchunk < 1 || c.cchunk > 64) return failf(DRT_EINVAL, "cchunk=%d outside [1, 64]", c.cchunk);
   if (!(c.tile_w == 8 || c.tile_w == 16 || c.tile_w == 32)) return failf(DRT_EINVAL, "tile_w=%d must be 8, 16 or 32", c.tile_w);
+  if (drt::batched_lds_bytes(c.nw, p->max_walls, p->max_order) > kMaxBatchedLds)
+    return failf(DRT_EINVAL, "nw=%d needs %zu bytes of LDS for %d walls (limit %zu)", c.nw,
+                 drt::batched_lds_bytes(c.nw, p->max_walls, p->max_order), p->max_walls, kMaxBatchedLds);
   const int maxb = drt::batched_max_blocks_per_cu(c.nw, p->max_walls, p->max_order);
   const int bpc = c.blocks_per_cu <= 0 ? maxb : std::min(c.blocks_per_cu, maxb);
   const int blocks = bpc * p->n_cu;
@@ -358,7 +364,9 @@ int drt_plan_create(const drt_batch_shape* shape, const char* tune_cache_path, d
     delete p;
     return failf(DRT_EHIP, "plan buffers: %s", hipGetErrorString(e));
   }
+  // default shape: 8 wavefronts, fewer when the wall accumulators do not fit
   drt_plan_config c{8, 1, 0, 8};
+  while (c.nw > 4 && drt::batched_lds_bytes(c.nw, p->max_walls, p->max_order) > kMaxBatchedLds) c.nw >>= 1;
   read_tuned(tune_cache_path, p->signature, &c);
   int rc = apply_config(p, c);
   if (rc != DRT_OK) {

@@ -152,6 +152,94 @@ def placement_problem(scene: int, n_rx: int, alpha: float = 1.0) -> Scene:
     return Scene(walls, tx, rx, 0, 0, alpha)
 
 
+# --- 3D scenes: parallelogram panels [P][9] = corner a, adjacent corners b, c ---
+
+ROOM_PANELS = np.array(
+    [[0, 0, 0, 1, 0, 0, 0, 1, 0],    # floor z = 0
+     [0, 0, 1, 0, 1, 1, 1, 0, 1],    # ceiling z = 1
+     [0, 0, 0, 0, 1, 0, 0, 0, 1],    # x = 0
+     [1, 0, 0, 1, 0, 1, 1, 1, 0],    # x = 1
+     [0, 0, 0, 0, 0, 1, 1, 0, 0],    # y = 0
+     [0, 1, 0, 1, 1, 0, 0, 1, 1]],   # y = 1
+    dtype=np.float32)
+
+
+@dataclasses.dataclass
+class Scene3D:
+    panels: np.ndarray     # float32 [P, 9]
+    tx: np.ndarray         # float32 [3]
+    rx: np.ndarray         # float32 [R, 3]
+    grid_n: int            # receivers form a grid_n x grid_n grid at one height (0 if not)
+    max_order: int
+    alpha: float
+
+    @property
+    def n_panels(self) -> int:
+        return int(self.panels.shape[0])
+
+    @property
+    def n_rx(self) -> int:
+        return int(self.rx.shape[0])
+
+
+def random_panels(rng: np.random.Generator, n: int, len_lo: float = 0.05, len_hi: float = 0.3) -> np.ndarray:
+    """n rectangles: centre ~U[0,1]^3, normal uniform on the sphere, side lengths
+    ~U(len_lo, len_hi), in-plane angle ~U[0, 2 pi); float32 [n, 9]."""
+    out = np.empty((n, 9), dtype=np.float64)
+    for s in range(n):
+        c = rng.uniform(0.0, 1.0, 3)
+        nrm = rng.normal(0.0, 1.0, 3)
+        nrm /= np.linalg.norm(nrm)
+        l1, l2 = rng.uniform(len_lo, len_hi, 2)
+        th = rng.uniform(0.0, 2.0 * np.pi)
+        ref = np.array([1.0, 0.0, 0.0]) if abs(nrm[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        t1 = np.cross(nrm, ref)
+        t1 /= np.linalg.norm(t1)
+        t2 = np.cross(nrm, t1)
+        u = np.cos(th) * t1 + np.sin(th) * t2
+        v = np.cross(nrm, u)
+        e1, e2 = l1 * u, l2 * v
+        a = c - 0.5 * (e1 + e2)
+        out[s] = np.concatenate([a, a + e1, a + e2])
+    return out.astype(np.float32)
+
+
+def rx_plane(n: int, z: float) -> np.ndarray:
+    """Cell centres of an n x n grid of [0,1]^2 at height z, float32 [n*n, 3], m = j*n + i."""
+    xy = rx_grid(n).astype(np.float64)
+    return np.concatenate([xy, np.full((xy.shape[0], 1), z)], axis=1).astype(np.float32)
+
+
+def scene3d_room(config: int, n_panels: int, grid_n: int, max_order: int, alpha: float, seed: int = 0,
+                 z: float = 0.5) -> Scene3D:
+    """Unit-cube room (6 panels) + n random rectangles; tx ~U[0.1, 0.9]^3;
+    receivers on an n x n grid at height z."""
+    rng = rng_for(config, seed)
+    tx = rng.uniform(0.1, 0.9, 3)
+    panels = np.concatenate([ROOM_PANELS, random_panels(rng, n_panels)], axis=0)
+    return Scene3D(panels, tx.astype(np.float32), rx_plane(grid_n, z), grid_n, max_order, alpha)
+
+
+def scene3d_32(seed: int = 0, grid_n: int = 256, alpha: float = 100.0) -> Scene3D:
+    """Room + 32 rectangles, 256 x 256 receivers at mid-height, order <= 2 (1,445 panel sequences)."""
+    return scene3d_room(8, 32, grid_n, 2, alpha, seed)
+
+
+def extrude(s: Scene, height: float = 1.0) -> Scene3D:
+    """The 2D scene as vertical panels of the given height, tx and receivers at
+    half height: every path stays in that plane."""
+    W = s.walls.astype(np.float64)
+    z0 = np.zeros((W.shape[0], 1))
+    a = np.concatenate([W[:, 0:2], z0], axis=1)
+    b = np.concatenate([W[:, 2:4], z0], axis=1)
+    c = np.concatenate([W[:, 0:2], z0 + height], axis=1)
+    h = np.full((s.rx.shape[0], 1), 0.5 * height)
+    return Scene3D(np.concatenate([a, b, c], axis=1).astype(np.float32),
+                   np.array([s.tx[0], s.tx[1], 0.5 * height], np.float32),
+                   np.concatenate([s.rx.astype(np.float64), h], axis=1).astype(np.float32),
+                   0, s.max_order, s.alpha)
+
+
 def random_points(config: int, scene: int, n: int) -> np.ndarray:
     """n points ~U[0,1]^2 as float32 [n, 2] (transmitter starts, sampled receivers)."""
     rng = rng_for(config, 1000 + scene)

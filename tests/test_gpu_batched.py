@@ -174,3 +174,19 @@ def test_full_batch_512_sampled():
         assert PU.rel_l2(gtx[s_i].numpy(), g1.numpy()) < 1e-5
         assert PU.rel_l2(gw[ws].numpy(), w1.numpy()) < 1e-5
     plan.close()
+
+
+def test_plan_rejects_scenes_beyond_the_lds_budget():
+    batched, tr = _mods()
+    from paper_2401_11882_amd._lib import DrtError
+    big = WL.scene_random_box(3, 1000, 8, 1, 100.0, seed=1)      # 1004 walls
+    with pytest.raises(DrtError):
+        batched.BatchPlan([big], 1)
+    ok = WL.scene_random_box(3, 900, 8, 1, 100.0, seed=1)        # 904 walls: fits at 4 wavefronts
+    plan = batched.BatchPlan([ok], 1)
+    assert plan.config()["nw"] == 4
+    with pytest.raises(DrtError):
+        plan.set_config(nw=16)
+    P, L, gtx, gw = plan.run()
+    assert torch.isfinite(P).all() and torch.isfinite(gw).all()
+    plan.close()

@@ -321,3 +321,24 @@ def test_graph_capture_replay_matches_eager():
         assert torch.equal(out[1], eager[i][0]), f"replay {i} loss"
         assert torch.equal(tx, eager[i][1]), f"replay {i} tx"
         _ = (tx * 2).sum().item()   # unrelated eager work between replays
+
+
+def test_maximum_wall_count_sampled():
+    """1024 walls (the ABI maximum: box + 1020 short segments), order <= 1
+    (1025 candidates), 16 x 16 receivers: sampled receivers against the
+    oracle, gradients over them; the launch shape adapts its LDS."""
+    tr = _tr()
+    rng = WL.rng_for(7, 0)
+    walls = np.concatenate([WL.BOX_WALLS, WL.random_segments(rng, 1020, 0.005, 0.03)]).astype(np.float32)
+    tx = np.array([0.43, 0.57], np.float32)
+    rx = WL.rx_grid(16)
+    sc = tr.Scene(_dev(walls), _dev(tx), _dev(rx), 1, 100.0, grid_nx=16)
+    P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    idx = np.array([0, 17, 85, 130, 201, 255])
+    P_o, kap = PU.kappa(walls, tx, rx[idx], 1, 100.0)
+    PU.check_power(P.cpu().numpy()[idx], P_o, kap, "1024 walls")
+    w = np.zeros(rx.shape[0], np.float32)
+    w[idx] = 1.0
+    gtx, gw, _ = tr.backward(sc, seed * _dev(w))
+    gw_o, gt_o, _ = T.vjp(walls, tx, rx[idx], 1, 100.0, seed.cpu().numpy()[idx])
+    PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, "1024 walls")
