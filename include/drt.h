@@ -358,6 +358,61 @@ int drt_mlp_scan(drt_mlp* mlp, const float* tx_dev, int32_t n_tx, const float* r
 /* y_dev[i] = log(power_dev[i] + eps), the surrogate's training target. */
 int drt_log_targets(const float* power_dev, int64_t n, float eps, float* y_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Scenes in three dimensions (Sec. V: the method makes no assumption on
+ * the number of dimensions)
+ *
+ * The walls become planar parallelogram panels {a + beta (b - a) +
+ * gamma (c - a) : beta, gamma in [0, 1]} given by the corner a and its two
+ * neighbours b and c.  Each step keeps its 2D meaning: images mirror across
+ * the panel's plane (normal (b - a) x (c - a)); the back-trace meets the
+ * plane at X_i = X_{i+1} + u_i (I_i - X_{i+1}) with panel coordinates
+ * (beta_i, gamma_i); an interaction's factor is in(beta) in(gamma) in(u);
+ * panel j obstructs a leg with 1 - in(upsilon) in(beta) in(gamma), upsilon
+ * the leg parameter of the plane crossing and (beta, gamma) its panel
+ * coordinates (Sec. IV-A with Eq. 3-4, sigmoid smoothing only).  A panel of
+ * zero area contributes no path and never obstructs; a back-trace parallel
+ * to a plane gives no path; a leg parallel to a plane is not obstructed by
+ * it.  Power, losses, error handling, determinism, graph capture and the
+ * contribution cache (drt_set_cache_limit) are as in the 2D calls above;
+ * there are no receiver gradients.
+ * ------------------------------------------------------------------------ */
+
+#define DRT3_MAX_PANELS 256
+
+/* One 3D scene.  All array pointers are device pointers. */
+typedef struct drt3_scene {
+  const float* panels_dev;  /* [n_panels][9] = (a, b, c), each (x, y, z) */
+  int32_t n_panels;         /* 0 .. DRT3_MAX_PANELS */
+  const float* tx_dev;      /* [3] transmitter */
+  const float* rx_dev;      /* [n_rx][3] receivers */
+  int32_t n_rx;             /* >= 0 */
+  int32_t rx_grid_nx;       /* as drt_scene.rx_grid_nx */
+  int32_t max_order;        /* K, 0 .. DRT_MAX_ORDER */
+  float alpha;              /* finite and > 0 */
+  int32_t smoothing;        /* DRT_SIGMOID (others: DRT_ENOTSUP) */
+  float d_min;              /* finite and > 0 */
+} drt3_scene;
+
+/* Workspace bytes for the drt3_* compute calls on this scene (host only). */
+int drt3_workspace_size(const drt3_scene* scene, size_t* bytes);
+
+/* As drt_forward, for a 3D scene: power_dev [n_rx]; loss_dev [1] or NULL;
+   seed_dev [n_rx] or NULL. */
+int drt3_forward(const drt3_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
+                 float* loss_dev, float* seed_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* As drt_backward: grad_tx_dev [3], grad_panels_dev [n_panels][9] (same
+   order as the panels), overwritten.  flags: 0 or DRT_BWD_REUSE_FORWARD. */
+int drt3_backward(const drt3_scene* scene, const float* grad_power_dev, int32_t flags,
+                  float* grad_tx_dev, float* grad_panels_dev, void* ws_dev, size_t ws_bytes,
+                  void* stream);
+
+/* Forward, loss seed and adjoint in one call (loss_kind must not be NONE). */
+int drt3_forward_backward(const drt3_scene* scene, int32_t loss_kind, float log_eps,
+                          float* power_dev, float* loss_dev, float* grad_tx_dev,
+                          float* grad_panels_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

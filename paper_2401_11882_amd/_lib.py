@@ -35,6 +35,15 @@ class DrtScene(ctypes.Structure):
     ]
 
 
+class Drt3Scene(ctypes.Structure):
+    _fields_ = [
+        ("panels_dev", c_void_p), ("n_panels", c_int32),
+        ("tx_dev", c_void_p),
+        ("rx_dev", c_void_p), ("n_rx", c_int32), ("rx_grid_nx", c_int32),
+        ("max_order", c_int32), ("alpha", c_float), ("smoothing", c_int32), ("d_min", c_float),
+    ]
+
+
 class DrtBatchShape(ctypes.Structure):
     _fields_ = [("n_scenes", c_int32), ("n_walls", ctypes.POINTER(c_int32)), ("n_rx", ctypes.POINTER(c_int32)),
                 ("rx_grid_nx", ctypes.POINTER(c_int32)), ("max_order", c_int32)]
@@ -97,6 +106,13 @@ _SIGS = {
     "drt_mlp_forward": ([c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p], c_int32),
     "drt_mlp_scan": ([c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p], c_int32),
     "drt_log_targets": ([c_void_p, ctypes.c_int64, c_float, c_void_p, c_void_p], c_int32),
+    "drt3_workspace_size": ([ctypes.POINTER(Drt3Scene), ctypes.POINTER(c_size_t)], c_int32),
+    "drt3_forward": ([ctypes.POINTER(Drt3Scene), c_int32, c_float, c_void_p, c_void_p, c_void_p,
+                      c_void_p, c_size_t, c_void_p], c_int32),
+    "drt3_backward": ([ctypes.POINTER(Drt3Scene), c_void_p, c_int32, c_void_p, c_void_p,
+                       c_void_p, c_size_t, c_void_p], c_int32),
+    "drt3_forward_backward": ([ctypes.POINTER(Drt3Scene), c_int32, c_float, c_void_p, c_void_p,
+                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
 }
 
 _lib = None
@@ -107,7 +123,7 @@ def header_symbols() -> list[str]:
     with open(HEADER) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(drt_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(drt3?_[a-z0-9_]+)\s*\(", text)))
 
 
 def lib() -> ctypes.CDLL:

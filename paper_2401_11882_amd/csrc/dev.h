@@ -175,6 +175,16 @@ __device__ __forceinline__ float wave_sum4(float a, float b, float c, float d) {
 // order, then lexicographically: the first wall is a base-W digit, each later
 // wall a base-(W-1) digit d mapped to d + (d >= previous wall), which skips a
 // back-to-back repeat.  c must be < the candidate count.
+// Compensated sum; a zero term leaves the state as it is, so which zero
+// contributions are visited does not change the result.
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
+  const float y = x - comp;
+  const float t = sum + y;
+  const float c = (t - sum) - y;
+  sum = x != 0.0f ? t : sum;
+  comp = x != 0.0f ? c : comp;
+}
+
 struct Cand {
   int k;
   int s0, s1, s2;

@@ -236,7 +236,7 @@ __device__ __forceinline__ ObsHard obstruction_hard(const SceneView& S, float de
 // d hs(x) hs(1 - x) / dx divided by alpha / 6: h2 where hs(x) is on its ramp,
 // minus h1 where hs(1 - x) is (0 on the flat parts; the kinks take 0).
 __device__ __forceinline__ float hard_ramp(float h1, float h2) {
-  return ((h1 > 0.0f) & (h1 < 1.0f) ? h2 : 0.0f) - ((h2 > 0.0f) & (h2 < 1.0f) ? h1 : 0.0f);
+  return (((h1 > 0.0f) & (h1 < 1.0f)) ? h2 : 0.0f) - (((h2 > 0.0f) & (h2 < 1.0f)) ? h1 : 0.0f);
 }
 
 // Wave-uniform oriented box around the band-extended legs
@@ -414,16 +414,6 @@ __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& 
   return V / fmaxf(d2, S.dmin2);
 }
 
-// Compensated sum; a zero term leaves the state as it is, so which zero
-// contributions are visited does not change the result.
-__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
-  const float y = x - comp;
-  const float t = sum + y;
-  const float c = (t - sum) - y;
-  sum = x != 0.0f ? t : sum;
-  comp = x != 0.0f ? c : comp;
-}
-
 // Per-wave accumulator layout: [0,1] = d/dtx, [2 + 4j + c] = d/d walls[j][c].
 // Lanes 0..3 add the wave totals of (dax, dbx, day, dby) to their entries.
 __device__ __forceinline__ void acc_wall(float* acc, int j, float dax, float day, float dbx, float dby,
@@ -566,8 +556,8 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
       const float h1 = med01(fmaf(S.a6, t, 0.5f)), h2 = med01(fmaf(-S.a6, t, S.a6h));
       const float h3 = med01(fmaf(S.a6, u, 0.5f)), h4 = med01(fmaf(-S.a6, u, S.a6h));
       const float aw = S.a6 * Wl;
-      gti = aw * (((h1 > 0.0f) & (h1 < 1.0f) ? rcp(h1) : 0.0f) - ((h2 > 0.0f) & (h2 < 1.0f) ? rcp(h2) : 0.0f));
-      gu = aw * (((h3 > 0.0f) & (h3 < 1.0f) ? rcp(h3) : 0.0f) - ((h4 > 0.0f) & (h4 < 1.0f) ? rcp(h4) : 0.0f));
+      gti = aw * ((((h1 > 0.0f) & (h1 < 1.0f)) ? rcp(h1) : 0.0f) - (((h2 > 0.0f) & (h2 < 1.0f)) ? rcp(h2) : 0.0f));
+      gu = aw * ((((h3 > 0.0f) & (h3 < 1.0f)) ? rcp(h3) : 0.0f) - (((h4 > 0.0f) & (h4 < 1.0f)) ? rcp(h4) : 0.0f));
     }
     // X_i = a + t e
     const float gt = gti + gXx[i] * w.ex + gXy[i] * w.ey;

@@ -1,0 +1,465 @@
+// Per-(receiver, candidate) evaluation of the smoothed image-method path in
+// 3D scenes of parallelogram panels, and its adjoint.  One lane = one
+// receiver; the candidate and the panel under test are wave-uniform.
+//
+// A panel {a + beta (b - a) + gamma (c - a): beta, gamma in [0, 1]} keeps, in
+// its prepared record, a, the normal n = (b - a) x (c - a), s = 1 / (n . n),
+// n . a, and the vectors m1 = ((c - a) x n) s, m2 = (n x (b - a)) s with
+// beta = (x - a) . m1 and gamma = (x - a) . m2 for x in its plane.  Every
+// step is the 2D step with the wall replaced by the panel (the method does
+// not depend on the dimension, Sec. V): mirror across the plane, back-trace
+// to the plane, the validity of an interaction in(beta) in(gamma) in(u) and
+// the obstruction factor 1 - in(upsilon) in(beta) in(gamma), with in(x) =
+// s(alpha x) s(alpha (1 - x)) and s the sigmoid (Sec. IV-A, Eq. 3-4).
+//
+// The adjoint accumulates, per panel, the gradients with respect to the
+// record's a, n, m1, m2 and s (13 numbers); a final kernel maps them to the
+// corners a, b, c.
+#pragma once
+#include "dev.h"
+
+namespace drt {
+
+struct PanelRec {
+  float ax, ay, az, nx, ny, nz, m1x, m1y, m1z, m2x, m2y, m2z, s, nda, pad0, pad1;
+};
+
+// Panel record at a wave-uniform index, through the scalar data cache (the
+// records are written by an earlier launch).
+__device__ __forceinline__ PanelRec load_panel(const PanelRec* panels, int j) {
+  typedef __attribute__((address_space(4))) const float* ConstF;
+  const int ju = __builtin_amdgcn_readfirstlane(j);
+  const ConstF p = (ConstF)(panels + ju);
+  PanelRec r;
+  r.ax = p[0];
+  r.ay = p[1];
+  r.az = p[2];
+  r.nx = p[3];
+  r.ny = p[4];
+  r.nz = p[5];
+  r.m1x = p[6];
+  r.m1y = p[7];
+  r.m1z = p[8];
+  r.m2x = p[9];
+  r.m2y = p[10];
+  r.m2z = p[11];
+  r.s = p[12];
+  r.nda = p[13];
+  r.pad0 = r.pad1 = 0.0f;
+  return r;
+}
+
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+  return fmaf(ax, bx, fmaf(ay, by, az * bz));
+}
+
+struct Scene3View {
+  const PanelRec* panels;
+  int n_panels;
+  float alpha, a2, band_k, dmin2;
+};
+
+template <int K>
+struct Path3 {
+  static constexpr int KI = K > 0 ? K : 1;
+  float Ix[K + 1], Iy[K + 1], Iz[K + 1];   // images (wave-uniform values)
+  float Xx[K + 2], Xy[K + 2], Xz[K + 2];   // X_0 = tx .. X_{K+1} = r
+  float u[KI], be[KI], ga[KI], inv[KI];    // interaction i at i - 1
+  float dx[KI], dy[KI], dz[KI];            // d = I_i - X_{i+1}
+  float h[KI];                             // mirror offsets ((I_{i-1} - a) . n) s
+  int s[KI];
+  int lo[K + 1], hi[K + 1];
+  float F;
+};
+
+// d log in(x) / dx = alpha (E1 / (1 + E1) - E2 / (1 + E2)), E1 = e^(-alpha x), E2 = e^(-alpha (1 - x)).
+__device__ __forceinline__ float dlog_in(float x, float alpha, float a2) {
+  const float E1 = ex2(-a2 * x), E2 = ex2(fmaf(a2, x, -a2));
+  const float r1 = E1 < kBig ? E1 * rcp(1.0f + E1) : 1.0f;
+  const float r2 = E2 < kBig ? E2 * rcp(1.0f + E2) : 1.0f;
+  return alpha * (r1 - r2);
+}
+
+// Images, back-trace and (if WANT_F) the interaction factors; with WANT_F,
+// false as soon as every lane's factor is exactly 0.
+template <int K, bool WANT_F>
+__device__ __forceinline__ bool setup3(const Scene3View& S, const Cand& cd, float tx, float ty, float tz,
+                                       float rx, float ry, float rz, bool live, Path3<K>& P) {
+  const int sv[3] = {cd.s0, cd.s1, cd.s2};
+#pragma unroll
+  for (int i = 0; i < Path3<K>::KI; ++i) P.s[i] = (i < K) ? sv[i] : -1;
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    P.lo[l] = (l >= 1) ? sv[l - 1] : -1;
+    P.hi[l] = (l + 1 <= K) ? sv[l] : -1;
+  }
+  P.Ix[0] = tx;
+  P.Iy[0] = ty;
+  P.Iz[0] = tz;
+  bool ok = live;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const PanelRec w = load_panel(S.panels, P.s[i]);
+    ok = ok && (w.s > 0.0f);
+    const float h = dot3(P.Ix[i] - w.ax, P.Iy[i] - w.ay, P.Iz[i] - w.az, w.nx, w.ny, w.nz) * w.s;
+    P.h[i] = h;
+    P.Ix[i + 1] = fmaf(-2.0f * h, w.nx, P.Ix[i]);
+    P.Iy[i + 1] = fmaf(-2.0f * h, w.ny, P.Iy[i]);
+    P.Iz[i + 1] = fmaf(-2.0f * h, w.nz, P.Iz[i]);
+  }
+  P.Xx[0] = tx;
+  P.Xy[0] = ty;
+  P.Xz[0] = tz;
+  P.Xx[K + 1] = rx;
+  P.Xy[K + 1] = ry;
+  P.Xz[K + 1] = rz;
+  float F = ok ? 1.0f : 0.0f;
+#pragma unroll
+  for (int i = K; i >= 1; --i) {
+    const PanelRec w = load_panel(S.panels, P.s[i - 1]);
+    const float dx = P.Ix[i] - P.Xx[i + 1], dy = P.Iy[i] - P.Xy[i + 1], dz = P.Iz[i] - P.Xz[i + 1];
+    const float den = dot3(dx, dy, dz, w.nx, w.ny, w.nz);
+    const bool good = den != 0.0f;
+    const float inv = good ? rcp(den) : 0.0f;
+    const float u = (w.nda - dot3(P.Xx[i + 1], P.Xy[i + 1], P.Xz[i + 1], w.nx, w.ny, w.nz)) * inv;
+    P.Xx[i] = fmaf(u, dx, P.Xx[i + 1]);
+    P.Xy[i] = fmaf(u, dy, P.Xy[i + 1]);
+    P.Xz[i] = fmaf(u, dz, P.Xz[i + 1]);
+    const float qx = P.Xx[i] - w.ax, qy = P.Xy[i] - w.ay, qz = P.Xz[i] - w.az;
+    const float be = dot3(qx, qy, qz, w.m1x, w.m1y, w.m1z);
+    const float ga = dot3(qx, qy, qz, w.m2x, w.m2y, w.m2z);
+    P.u[i - 1] = u;
+    P.be[i - 1] = be;
+    P.ga[i - 1] = ga;
+    P.inv[i - 1] = inv;
+    P.dx[i - 1] = dx;
+    P.dy[i - 1] = dy;
+    P.dz[i - 1] = dz;
+    if (WANT_F) {
+      F = good ? F : 0.0f;
+      const float z1 = -S.a2 * be, z2 = fmaf(S.a2, be, -S.a2);
+      const float z3 = -S.a2 * ga, z4 = fmaf(S.a2, ga, -S.a2);
+      const float z5 = -S.a2 * u, z6 = fmaf(S.a2, u, -S.a2);
+      const bool zero = (F == 0.0f) | (z1 >= 128.0f) | (z2 >= 128.0f) | (z3 >= 128.0f) | (z4 >= 128.0f) |
+                        (z5 >= 128.0f) | (z6 >= 128.0f);
+      if (ballot(!zero) == 0) {
+        P.F = 0.0f;
+        return false;
+      }
+      const float E1 = ex2(z1), E2 = ex2(z2), E3 = ex2(z3), E4 = ex2(z4), E5 = ex2(z5), E6 = ex2(z6);
+      F *= rcp(((1.0f + E1) * (1.0f + E2)) * ((1.0f + E3) * (1.0f + E4)) * ((1.0f + E5) * (1.0f + E6)));
+    }
+  }
+  P.F = F;
+  return true;
+}
+
+// 1 - in(ups) in(beta) in(gamma) = num / (1 + num) with
+// num = (1 + n_u)(1 + n_b)(1 + n_g) - 1 expanded into positive terms,
+// n_x = E1 + E2 + E1 E2 (E1 = e^(-alpha x), E2 = e^(-alpha (1 - x))).
+__device__ __forceinline__ float n_of(float x, float a2) {
+  const float E1 = ex2(-a2 * x), E2 = ex2(fmaf(a2, x, -a2));
+  return fmaf(E1, E2, E1 + E2);
+}
+
+struct Obs3 {
+  float ups, be, ga, inv, qx, qy, qz, num;
+};
+
+// Obstruction test of leg (X, D) by panel w: false if every lane's factor is
+// 1.0f (a parameter more than band outside [0, 1]); the leg parameter first.
+__device__ __forceinline__ bool obs3(const Scene3View& S, const PanelRec& w, float Xx, float Xy, float Xz, float Dx,
+                                     float Dy, float Dz, bool act, Obs3& o, bool& in_band) {
+  const float den = dot3(Dx, Dy, Dz, w.nx, w.ny, w.nz);
+  const float num = w.nda - dot3(Xx, Xy, Xz, w.nx, w.ny, w.nz);  // (a - X) . n
+  bool it = act && (fabsf(fmaf(2.0f, num, -den)) < S.band_k * fabsf(den));
+  in_band = false;
+  if (ballot(it) == 0) return false;
+  o.inv = rcp(den);
+  o.ups = num * o.inv;
+  const float Hx = fmaf(o.ups, Dx, Xx), Hy = fmaf(o.ups, Dy, Xy), Hz = fmaf(o.ups, Dz, Xz);
+  o.qx = Hx - w.ax;
+  o.qy = Hy - w.ay;
+  o.qz = Hz - w.az;
+  o.be = dot3(o.qx, o.qy, o.qz, w.m1x, w.m1y, w.m1z);
+  o.ga = dot3(o.qx, o.qy, o.qz, w.m2x, w.m2y, w.m2z);
+  it = it && (fabsf(fmaf(2.0f, o.be, -1.0f)) < S.band_k) && (fabsf(fmaf(2.0f, o.ga, -1.0f)) < S.band_k);
+  if (ballot(it) == 0) return false;
+  in_band = it;
+  if (it) {
+    const float nu = n_of(o.ups, S.a2), nb = n_of(o.be, S.a2), ng = n_of(o.ga, S.a2);
+    const float t = fmaf(nu, nb, nu + nb);
+    o.num = fmaf(t, ng, t + ng);
+  } else {
+    o.num = kBig;
+  }
+  return true;
+}
+
+template <int K>
+__device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<K>& P, float V) {
+  const bool act = P.F != 0.0f;
+  for (int j = 0; j < S.n_panels; ++j) {
+    const PanelRec w = load_panel(S.panels, j);
+    bool upd = false;
+#pragma unroll
+    for (int l = 0; l <= K; ++l) {
+      if (j == P.lo[l] || j == P.hi[l]) continue;
+      const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
+      Obs3 o;
+      bool ib;
+      if (!obs3(S, w, P.Xx[l], P.Xy[l], P.Xz[l], Dx, Dy, Dz, act, o, ib)) continue;
+      if (ib) {
+        V *= o.num * rcp(1.0f + o.num);
+        upd = true;
+      }
+    }
+    if (ballot(upd) != 0 && ballot(V != 0.0f) == 0) break;   // every lane fully blocked
+  }
+  return V;
+}
+
+template <int K>
+__device__ __forceinline__ float path_power3(const Scene3View& S, const Cand& cd, float tx, float ty, float tz,
+                                             float rx, float ry, float rz, bool live) {
+  Path3<K> P;
+  if (!setup3<K, true>(S, cd, tx, ty, tz, rx, ry, rz, live, P)) return 0.0f;
+  if (ballot(P.F != 0.0f) == 0) return 0.0f;
+  const float V = obstruct_all3<K>(S, P, P.F);
+  const float ex = rx - P.Ix[K], ey = ry - P.Iy[K], ez = rz - P.Iz[K];
+  const float d2 = dot3(ex, ey, ez, ex, ey, ez);
+  return V / fmaxf(d2, S.dmin2);
+}
+
+// Per-wave accumulator layout: [0..2] = d/dtx, [3 + 13 j + f] = d/d record of
+// panel j with f: a (0..2), n (3..5), m1 (6..8), m2 (9..11), s (12).
+constexpr int kPanelGrad = 13;
+
+__device__ __forceinline__ void acc_panel(float* acc, int j, const float (&g)[kPanelGrad], int lane) {
+  float* p = acc + 3 + kPanelGrad * j;
+#pragma unroll
+  for (int b = 0; b < 12; b += 4) {
+    const float s = wave_sum4(g[b], g[b + 1], g[b + 2], g[b + 3]);
+    if (lane < 4) p[b + ((lane & 1) << 1) + ((lane >> 1) & 1)] += s;
+  }
+  const float s12 = wave_sum(g[12]);
+  if (lane == 0) p[12] += s12;
+}
+
+struct LaneGrad3 {
+  float tx, ty, tz;
+};
+
+// Reverse sweep of one path given Wl = g(r) c (= dL / dlog V at this lane).
+template <int K>
+__device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K>& P, float Wl, float rx, float ry,
+                                              float rz, float* acc, int lane, LaneGrad3& G) {
+  const bool act = Wl != 0.0f;
+  // gradients of the path points X_0 .. X_{K+1} and of the images
+  float gXx[K + 2], gXy[K + 2], gXz[K + 2], gIx[K + 1], gIy[K + 1], gIz[K + 1];
+#pragma unroll
+  for (int i = 0; i < K + 2; ++i) gXx[i] = gXy[i] = gXz[i] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < K + 1; ++i) gIx[i] = gIy[i] = gIz[i] = 0.0f;
+
+  // -- obstruction factors: d log q / d(ups, beta, gamma) = -L_x / num
+  for (int j = 0; j < S.n_panels; ++j) {
+    const PanelRec w = load_panel(S.panels, j);
+    float g[kPanelGrad];
+#pragma unroll
+    for (int f = 0; f < kPanelGrad; ++f) g[f] = 0.0f;
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l <= K; ++l) {
+      if (j == P.lo[l] || j == P.hi[l]) continue;
+      const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
+      Obs3 o;
+      bool ib;
+      if (!obs3(S, w, P.Xx[l], P.Xy[l], P.Xz[l], Dx, Dy, Dz, act, o, ib)) continue;
+      if (!ib) continue;
+      const float c = -Wl * rcp(o.num);
+      const float gu = c * dlog_in(o.ups, S.alpha, S.a2);
+      const float gb = c * dlog_in(o.be, S.alpha, S.a2);
+      const float gg = c * dlog_in(o.ga, S.alpha, S.a2);
+      // beta = q . m1, gamma = q . m2, q = X + ups D - a
+      const float gqx = fmaf(gb, w.m1x, gg * w.m2x), gqy = fmaf(gb, w.m1y, gg * w.m2y),
+                  gqz = fmaf(gb, w.m1z, gg * w.m2z);
+      g[6] += gb * o.qx;
+      g[7] += gb * o.qy;
+      g[8] += gb * o.qz;
+      g[9] += gg * o.qx;
+      g[10] += gg * o.qy;
+      g[11] += gg * o.qz;
+      const float gut = gu + dot3(gqx, gqy, gqz, Dx, Dy, Dz);  // total d/d ups
+      // ups = ((a - X) . n) / (D . n)
+      const float gnum = gut * o.inv, gden = -gut * o.ups * o.inv;
+      const float w0x = w.ax - P.Xx[l], w0y = w.ay - P.Xy[l], w0z = w.az - P.Xz[l];
+      // d/dX_l: +gq (q) - gnum n (num) ; d/dD: ups gq + gden n
+      const float gDx = fmaf(o.ups, gqx, gden * w.nx), gDy = fmaf(o.ups, gqy, gden * w.ny),
+                  gDz = fmaf(o.ups, gqz, gden * w.nz);
+      gXx[l] += gqx - gnum * w.nx - gDx;
+      gXy[l] += gqy - gnum * w.ny - gDy;
+      gXz[l] += gqz - gnum * w.nz - gDz;
+      gXx[l + 1] += gDx;
+      gXy[l + 1] += gDy;
+      gXz[l + 1] += gDz;
+      // panel record: a (q and num), n (num and den)
+      g[0] += fmaf(gnum, w.nx, -gqx);
+      g[1] += fmaf(gnum, w.ny, -gqy);
+      g[2] += fmaf(gnum, w.nz, -gqz);
+      g[3] += fmaf(gnum, w0x, gden * Dx);
+      g[4] += fmaf(gnum, w0y, gden * Dy);
+      g[5] += fmaf(gnum, w0z, gden * Dz);
+      any = true;
+    }
+    if (ballot(any) != 0) acc_panel(acc, j, g, lane);
+  }
+
+  // -- image distance |r - I_K|^2 (zero gradient under the d_min floor)
+  {
+    const float ex = rx - P.Ix[K], ey = ry - P.Iy[K], ez = rz - P.Iz[K];
+    const float d2 = dot3(ex, ey, ez, ex, ey, ez);
+    if (d2 > S.dmin2) {
+      const float f = 2.0f * Wl / d2;
+      gIx[K] += f * ex;
+      gIy[K] += f * ey;
+      gIz[K] += f * ez;
+    }
+  }
+  // -- interactions i = 1 .. K: the back-trace made X_i from X_{i+1}, so its
+  // reverse runs from X_1 upwards (X_i's gradient is complete when reached)
+#pragma unroll
+  for (int i = 1; i <= K; ++i) {
+    const PanelRec w = load_panel(S.panels, P.s[i - 1]);
+    const float u = P.u[i - 1], inv = P.inv[i - 1];
+    const float dx = P.dx[i - 1], dy = P.dy[i - 1], dz = P.dz[i - 1];
+    const float gb = Wl * dlog_in(P.be[i - 1], S.alpha, S.a2);
+    const float gg = Wl * dlog_in(P.ga[i - 1], S.alpha, S.a2);
+    const float gu = Wl * dlog_in(u, S.alpha, S.a2);
+    float g[kPanelGrad];
+#pragma unroll
+    for (int f = 0; f < kPanelGrad; ++f) g[f] = 0.0f;
+    // beta = q . m1, gamma = q . m2 with q = X_i - a
+    const float qx = P.Xx[i] - w.ax, qy = P.Xy[i] - w.ay, qz = P.Xz[i] - w.az;
+    const float gqx = fmaf(gb, w.m1x, gg * w.m2x), gqy = fmaf(gb, w.m1y, gg * w.m2y),
+                gqz = fmaf(gb, w.m1z, gg * w.m2z);
+    g[6] = gb * qx;
+    g[7] = gb * qy;
+    g[8] = gb * qz;
+    g[9] = gg * qx;
+    g[10] = gg * qy;
+    g[11] = gg * qz;
+    g[0] = -gqx;
+    g[1] = -gqy;
+    g[2] = -gqz;
+    const float gXix = gXx[i] + gqx, gXiy = gXy[i] + gqy, gXiz = gXz[i] + gqz;
+    // X_i = X_{i+1} + u d
+    const float gut = gu + dot3(gXix, gXiy, gXiz, dx, dy, dz);
+    float gdx = u * gXix, gdy = u * gXiy, gdz = u * gXiz;
+    gXx[i + 1] += gXix;
+    gXy[i + 1] += gXiy;
+    gXz[i + 1] += gXiz;
+    // u = ((a - X_{i+1}) . n) / (d . n)
+    const float gnum = gut * inv, gden = -gut * u * inv;
+    const float wx = w.ax - P.Xx[i + 1], wy = w.ay - P.Xy[i + 1], wz = w.az - P.Xz[i + 1];
+    g[0] += gnum * w.nx;
+    g[1] += gnum * w.ny;
+    g[2] += gnum * w.nz;
+    gXx[i + 1] -= gnum * w.nx;
+    gXy[i + 1] -= gnum * w.ny;
+    gXz[i + 1] -= gnum * w.nz;
+    g[3] = fmaf(gnum, wx, gden * dx);
+    g[4] = fmaf(gnum, wy, gden * dy);
+    g[5] = fmaf(gnum, wz, gden * dz);
+    gdx = fmaf(gden, w.nx, gdx);
+    gdy = fmaf(gden, w.ny, gdy);
+    gdz = fmaf(gden, w.nz, gdz);
+    // d = I_i - X_{i+1}
+    gIx[i] += gdx;
+    gIy[i] += gdy;
+    gIz[i] += gdz;
+    gXx[i + 1] -= gdx;
+    gXy[i + 1] -= gdy;
+    gXz[i + 1] -= gdz;
+    acc_panel(acc, P.s[i - 1], g, lane);
+  }
+  G.tx += gXx[0];
+  G.ty += gXy[0];
+  G.tz += gXz[0];
+  if (K == 0) {
+    // I_0 is the transmitter itself
+    G.tx += gIx[0];
+    G.ty += gIy[0];
+    G.tz += gIz[0];
+    return;
+  }
+  // -- images, on wave-uniform values after one reduction over the lanes:
+  // I_i = I_{i-1} - 2 h n with h = ((I_{i-1} - a) . n) s, for i = K .. 1
+  float GIx[K + 1], GIy[K + 1], GIz[K + 1];
+#pragma unroll
+  for (int i = 1; i <= K; ++i) {
+    GIx[i] = wave_sum(gIx[i]);
+    GIy[i] = wave_sum(gIy[i]);
+    GIz[i] = wave_sum(gIz[i]);
+  }
+  GIx[0] = GIy[0] = GIz[0] = 0.0f;
+#pragma unroll
+  for (int i = K; i >= 1; --i) {
+    const PanelRec w = load_panel(S.panels, P.s[i - 1]);
+    const float h = P.h[i - 1];
+    const float pdx = P.Ix[i - 1] - w.ax, pdy = P.Iy[i - 1] - w.ay, pdz = P.Iz[i - 1] - w.az;
+    const float gh = -2.0f * dot3(GIx[i], GIy[i], GIz[i], w.nx, w.ny, w.nz);
+    const float ghs = gh * w.s;
+    GIx[i - 1] += fmaf(ghs, w.nx, GIx[i]);
+    GIy[i - 1] += fmaf(ghs, w.ny, GIy[i]);
+    GIz[i - 1] += fmaf(ghs, w.nz, GIz[i]);
+    if (lane == 0) {
+      float* p = acc + 3 + kPanelGrad * P.s[i - 1];
+      p[0] -= ghs * w.nx;
+      p[1] -= ghs * w.ny;
+      p[2] -= ghs * w.nz;
+      p[3] += fmaf(-2.0f * h, GIx[i], ghs * pdx);
+      p[4] += fmaf(-2.0f * h, GIy[i], ghs * pdy);
+      p[5] += fmaf(-2.0f * h, GIz[i], ghs * pdz);
+      p[12] += gh * dot3(pdx, pdy, pdz, w.nx, w.ny, w.nz);
+    }
+  }
+  if (lane == 0) {
+    acc[0] += GIx[0];
+    acc[1] += GIy[0];
+    acc[2] += GIz[0];
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void path_adjoint3_known(const Scene3View& S, const Cand& cd, float tx, float ty,
+                                                    float tz, float rx, float ry, float rz, bool live, float Wl,
+                                                    float* acc, int lane, LaneGrad3& G) {
+  Path3<K> P;
+  setup3<K, false>(S, cd, tx, ty, tz, rx, ry, rz, live, P);
+  P.F = Wl != 0.0f ? 1.0f : 0.0f;
+  path_adjoint3<K>(S, P, Wl, rx, ry, rz, acc, lane, G);
+}
+
+__device__ __forceinline__ float candidate_power3(const Scene3View& S, const Cand& cd, float tx, float ty,
+                                                  float tz, float rx, float ry, float rz, bool live) {
+  switch (cd.k) {
+    case 0: return path_power3<0>(S, cd, tx, ty, tz, rx, ry, rz, live);
+    case 1: return path_power3<1>(S, cd, tx, ty, tz, rx, ry, rz, live);
+    case 2: return path_power3<2>(S, cd, tx, ty, tz, rx, ry, rz, live);
+    default: return path_power3<3>(S, cd, tx, ty, tz, rx, ry, rz, live);
+  }
+}
+
+__device__ __forceinline__ void candidate_adjoint3(const Scene3View& S, const Cand& cd, float tx, float ty,
+                                                   float tz, float rx, float ry, float rz, bool live, float Wl,
+                                                   float* acc, int lane, LaneGrad3& G) {
+  switch (cd.k) {
+    case 0: path_adjoint3_known<0>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
+    case 1: path_adjoint3_known<1>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
+    case 2: path_adjoint3_known<2>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
+    default: path_adjoint3_known<3>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
+  }
+}
+
+}  // namespace drt

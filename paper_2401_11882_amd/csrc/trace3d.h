@@ -1,0 +1,41 @@
+// Internal interface between the C ABI (api3d.hip) and the 3D tracer kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace drt {
+
+struct PanelRec;
+
+struct Trace3Args {
+  const PanelRec* panels;  // prepared panel records [n_panels]
+  const float* tx;         // [3]
+  const float* rx;         // [n_rx][3]
+  int n_panels;
+  int n_rx;
+  int grid_nx;             // 0 = consecutive receivers per wavefront
+  int n_cand;
+  float alpha;
+  float a2;                // alpha * log2(e)
+  float band_k;            // 1 + 2 * 18 / alpha
+  float dmin2;
+  // contribution cache (NULL when disabled): per (tile, wavefront) slot
+  float* cache_c;          // [slots][cache_cap][64]
+  int* cache_idx;          // [slots][cache_cap]
+  int* cache_n;            // [slots], -1 when the list overflowed
+  int cache_cap;
+};
+
+hipError_t launch_prep_panels(const float* panels, int n, PanelRec* out, hipStream_t st);
+hipError_t launch_forward3(const Trace3Args& A, int n_tiles, int nw, float* power, float* seed, float* loss_part,
+                           int loss_kind, float log_eps, hipStream_t st);
+hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, int reuse,
+                            hipStream_t st);
+// grad_tx[3] and grad_panels[n][9] from the fixed-order column sums of the
+// per-tile partials [n_tiles][3 + 13 n] (tmp: 13 n floats).
+hipError_t launch_panel_grads(const float* part, int n_tiles, int n_panels, const float* panels, float* tmp,
+                              float* grad_tx, float* grad_panels, hipStream_t st);
+size_t backward3_lds_bytes(int nw, int n_panels);
+
+}  // namespace drt

@@ -154,3 +154,57 @@ def test_plan_create_validation():
     assert L.drt_plan_destroy(None) == 0
     assert L.drt_batched_forward_backward(None, None, 2, 1e-6, None, None, None, None, None) == _lib.DRT_EINVAL
     assert L.drt_plan_get_config(None, None) == _lib.DRT_EINVAL
+
+
+def _scene3(**kw):
+    d = dict(panels_dev=BOGUS, n_panels=8, tx_dev=BOGUS, rx_dev=BOGUS, n_rx=1024, rx_grid_nx=32,
+             max_order=2, alpha=100.0, smoothing=0, d_min=1e-3)
+    d.update(kw)
+    return _lib.Drt3Scene(**d)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("alpha", 0.0, _lib.DRT_EINVAL),
+    ("alpha", math.nan, _lib.DRT_EINVAL),
+    ("d_min", -1.0, _lib.DRT_EINVAL),
+    ("max_order", 4, _lib.DRT_EINVAL),
+    ("n_panels", -1, _lib.DRT_EINVAL),
+    ("n_panels", 257, _lib.DRT_EINVAL),
+    ("n_rx", -1, _lib.DRT_EINVAL),
+    ("rx_grid_nx", 12, _lib.DRT_EINVAL),
+    ("smoothing", 1, _lib.DRT_ENOTSUP),
+    ("panels_dev", None, _lib.DRT_EINVAL),
+    ("tx_dev", None, _lib.DRT_EINVAL),
+    ("rx_dev", None, _lib.DRT_EINVAL),
+])
+def test_scene3_validation(field, value, code):
+    L = _lib.lib()
+    sc = _scene3(**{field: value})
+    n = ctypes.c_size_t()
+    assert L.drt3_workspace_size(ctypes.byref(sc), ctypes.byref(n)) == code
+    assert L.drt_last_error()
+    assert L.drt3_forward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, None, BOGUS, 1 << 30, None) == code
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, BOGUS, BOGUS, BOGUS, 1 << 30, None) == code
+    assert L.drt3_forward_backward(ctypes.byref(sc), 2, 1e-6, BOGUS, None, BOGUS, BOGUS, BOGUS, 1 << 30,
+                                   None) == code
+
+
+def test_scene3_call_validation_before_launch():
+    L = _lib.lib()
+    sc = _scene3()
+    n = ctypes.c_size_t()
+    assert L.drt3_workspace_size(ctypes.byref(sc), ctypes.byref(n)) == 0
+    assert n.value > 0
+    # the largest scene fits its accumulators in LDS
+    assert L.drt3_workspace_size(ctypes.byref(_scene3(n_panels=256)), ctypes.byref(n)) == 0
+    assert L.drt3_forward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, None, None, n.value, None) == _lib.DRT_EWORKSPACE
+    assert L.drt3_forward(ctypes.byref(sc), 7, 1e-6, BOGUS, None, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_forward(ctypes.byref(sc), 2, 0.0, BOGUS, None, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_forward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 4, BOGUS, BOGUS, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, None, BOGUS, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_forward_backward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, BOGUS, 1 << 30,
+                                   None) == _lib.DRT_EINVAL
+    empty = _scene3(n_rx=0, rx_dev=None, rx_grid_nx=0)
+    assert L.drt3_forward(ctypes.byref(empty), 3, 1e-6, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
