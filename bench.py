@@ -179,6 +179,47 @@ def extra_surrogate():
             "heldout_rmse": round(r["heldout_rmse"], 4), "target_std": round(r["target_std"], 4)}
 
 
+def extra_3d(dev, steps: int = 10):
+    """Sec. V: the method in three dimensions.  Room (6 panels) + 32 random
+    rectangles, 256^2 receivers at mid-height, order <= 2 (1,445 panel
+    sequences), alpha = 100: forward, then the adjoint from the recorded
+    contributions, as in the main step."""
+    import numpy as np
+    import torch
+
+    from paper_2401_11882_amd import tracer3d as tr3
+    from paper_2401_11882_amd import workloads as WL
+    s = WL.scene3d_32()
+    pan, tx, rx = (torch.tensor(a, device=dev) for a in (s.panels, s.tx, s.rx))
+    sc = tr3.Scene3(pan, tx, rx, s.max_order, s.alpha, grid_nx=s.grid_n)
+    n_cand = 1 + s.n_panels + s.n_panels * (s.n_panels - 1)
+
+    def step():
+        P, L, seed = tr3.forward(sc, loss="neg_mean_log", want_seed=True)
+        mid = torch.cuda.Event(enable_timing=True)
+        mid.record()
+        tr3.backward(sc, seed, reuse_forward=True)
+        return mid
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    mids = []
+    for e0, e1 in ev:
+        e0.record()
+        mids.append(step())
+        e1.record()
+    torch.cuda.synchronize()
+    fwd = float(np.mean([e0.elapsed_time(m) for (e0, _), m in zip(ev, mids)]))
+    bwd = float(np.mean([m.elapsed_time(e1) for (_, e1), m in zip(ev, mids)]))
+    ms = fwd + bwd
+    return {"workload": "room + 32 rectangles (38 panels), 256^2 rx, order<=2 (1445 candidates), alpha=100, "
+                        "fwd + adjoint w.r.t. tx and all panel corners",
+            "ms_per_step": round(ms, 4), "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+            "value": s.n_rx * n_cand / (ms * 1e-3), "unit": "path-evals/s"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,7 +328,8 @@ def main() -> int:
     }
     if rank == 0 and not args.no_extras:
         out["extras"] = {"batched_512_scenes": extra_batched(dev), "order3_adam_loop": extra_order3_loop(dev),
-                         "hard_sigmoid": extra_hard_sigmoid(dev), "placement_study": extra_placement(),
+                         "hard_sigmoid": extra_hard_sigmoid(dev), "scene3d": extra_3d(dev),
+                         "placement_study": extra_placement(),
                          "surrogate": extra_surrogate()}
         out["surrogate_speedup_at_1pct"] = out["extras"]["surrogate"]["speedup_at_1pct"]
     if rank == 0 and not args.no_cpu_baseline:
