@@ -284,6 +284,19 @@ __device__ __forceinline__ void leg_boxes(const Path<K>& P, const LegGeom (&L)[K
   }
 }
 
+// Separating-axis test of a wall's culling box q against a leg box (axis
+// (ux, uy), centre (umid, vmid) and half extents (uh, vh) in that frame).
+__device__ __forceinline__ bool sat_separated(const WallBox& q, float ux, float uy, float umid, float uh,
+                                              float vmid, float vh) {
+  const float uc = fmaf(ux, q.cx, uy * q.cy), uw = fabsf(fmaf(ux, q.hx, uy * q.hy));
+  const float vc = fmaf(ux, q.cy, -uy * q.cx), vw = fabsf(fmaf(ux, q.hy, -uy * q.hx));
+  const bool sep_u = fabsf(uc - umid) > uw + uh;
+  const bool sep_v = fabsf(vc - vmid) > vw + vh;
+  const float nu = fmaf(q.nx, ux, q.ny * uy), nv = fmaf(q.ny, ux, -q.nx * uy);
+  const bool sep_n = fabsf(fmaf(umid, nu, fmaf(vmid, nv, -q.nd))) > fmaf(fabsf(nu), uh, fmaf(fabsf(nv), vh, q.en));
+  return sep_u | sep_v | sep_n;
+}
+
 // Calls fn(wall, masks, bit) for every wall that is not separated from some
 // leg box (walls in increasing order) until fn returns false; masks[l] bit
 // `bit` tells whether leg l needs the test (its own end walls are excluded
@@ -296,29 +309,63 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
                                             Fn&& fn) {
   const int lane = threadIdx.x & (kWave - 1);
   for (int b = 0; b < S.n_walls; b += kWave) {
-    const int wj = b + lane;
-    const bool valid = wj < S.n_walls;
-    WallBox q;
-    if (valid) {
-      q = S.boxes[wj];
-    } else {
-      q.cx = q.cy = q.hx = q.hy = q.nx = q.ny = q.nd = q.en = 0.0f;
-    }
     uint64_t m[K + 1];
     uint64_t uni = 0;
+    const int r = S.n_walls - b;  // walls left (wave-uniform)
+    if (K > 0 && (K + 1) * r <= kWave) {
+      // short last batch: one pass over (leg, wall) pairs, lane = l r + i
+      int ls = 0;
 #pragma unroll
-    for (int l = 0; l <= K; ++l) {
-      const LegBox& L = B[l];
-      const float uc = fmaf(L.ux, q.cx, L.uy * q.cy), uw = fabsf(fmaf(L.ux, q.hx, L.uy * q.hy));
-      const float vc = fmaf(L.ux, q.cy, -L.uy * q.cx), vw = fabsf(fmaf(L.ux, q.hy, -L.uy * q.hx));
-      const bool sep_u = fabsf(uc - L.umid) > uw + L.uh;
-      const bool sep_v = fabsf(vc - L.vmid) > vw + L.vh;
-      const float nu = fmaf(q.nx, L.ux, q.ny * L.uy), nv = fmaf(q.ny, L.ux, -q.nx * L.uy);
-      const bool sep_n = fabsf(fmaf(L.umid, nu, fmaf(L.vmid, nv, -q.nd))) >
-                         fmaf(fabsf(nu), L.uh, fmaf(fabsf(nv), L.vh, q.en));
-      const bool ov = valid & !L.empty & !sep_u & !sep_v & !sep_n & (wj != P.lo[l]) & (wj != P.hi[l]);
-      m[l] = ballot(ov);
-      uni |= m[l];
+      for (int l = 1; l <= K; ++l) ls += lane >= l * r;
+      const int wj = b + lane - ls * r;
+      const bool valid = lane < (K + 1) * r;
+      WallBox q;
+      if (valid) {
+        q = S.boxes[wj];
+      } else {
+        q.cx = q.cy = q.hx = q.hy = q.nx = q.ny = q.nd = q.en = 0.0f;
+      }
+      float ux = B[0].ux, uy = B[0].uy, umid = B[0].umid, uh = B[0].uh, vmid = B[0].vmid, vh = B[0].vh;
+      bool empty = B[0].empty;
+      int lo = P.lo[0], hi = P.hi[0];
+#pragma unroll
+      for (int l = 1; l <= K; ++l) {
+        const bool t = ls == l;
+        ux = t ? B[l].ux : ux;
+        uy = t ? B[l].uy : uy;
+        umid = t ? B[l].umid : umid;
+        uh = t ? B[l].uh : uh;
+        vmid = t ? B[l].vmid : vmid;
+        vh = t ? B[l].vh : vh;
+        empty = t ? B[l].empty : empty;
+        lo = t ? P.lo[l] : lo;
+        hi = t ? P.hi[l] : hi;
+      }
+      const bool ov = valid & !empty & !sat_separated(q, ux, uy, umid, uh, vmid, vh) & (wj != lo) & (wj != hi);
+      const uint64_t M = ballot(ov);
+      const uint64_t low = (1ull << r) - 1ull;
+#pragma unroll
+      for (int l = 0; l <= K; ++l) {
+        m[l] = (M >> (l * r)) & low;
+        uni |= m[l];
+      }
+    } else {
+      const int wj = b + lane;
+      const bool valid = wj < S.n_walls;
+      WallBox q;
+      if (valid) {
+        q = S.boxes[wj];
+      } else {
+        q.cx = q.cy = q.hx = q.hy = q.nx = q.ny = q.nd = q.en = 0.0f;
+      }
+#pragma unroll
+      for (int l = 0; l <= K; ++l) {
+        const LegBox& L = B[l];
+        const bool ov = valid & !L.empty & !sat_separated(q, L.ux, L.uy, L.umid, L.uh, L.vmid, L.vh) &
+                        (wj != P.lo[l]) & (wj != P.hi[l]);
+        m[l] = ballot(ov);
+        uni |= m[l];
+      }
     }
     while (uni) {
       const int j = __builtin_ctzll(uni);

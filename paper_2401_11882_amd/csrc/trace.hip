@@ -134,7 +134,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
 // ---------------------------------------------------------------------------
 
 template <int NW, int MODE>
-__global__ __launch_bounds__(NW * kWave) void k_backward(TraceArgs A, const float* __restrict__ gP,
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_backward(TraceArgs A, const float* __restrict__ gP,
                                                          float* __restrict__ part,
                                                          float* __restrict__ grad_rx, int reuse) {
   extern __shared__ float smem[];
