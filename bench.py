@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (datasheet, counts packed issue)
+UNPACKED_FP32_TFLOPS = 78.6     # the same without packed FP32: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
 
 
 def source_hash() -> str:
@@ -39,9 +40,10 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(tag: str, kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
-    when the kernels changed since those counters were taken."""
+def measured_counters(tag: str, kernel: str):
+    """The committed rocprofv3 PMC summary of one kernel (HBM bytes per launch,
+    executed FP32 FLOPs per launch, ...), or None when the kernels changed
+    since those counters were taken."""
     p = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     if not os.path.exists(p):
         return None
@@ -49,7 +51,12 @@ def measured_traffic(tag: str, kernel: str):
         t = json.load(f)
     if t.get("source_sha256") != source_hash():
         return None
-    k = t["kernels"].get(kernel)
+    return t["kernels"].get(kernel)
+
+
+def measured_traffic(tag: str, kernel: str):
+    """HBM bytes per launch, or None (see measured_counters)."""
+    k = measured_counters(tag, kernel)
     return None if k is None else int(k["hbm_bytes"])
 
 
@@ -152,6 +159,44 @@ def extra_hard_sigmoid(dev, steps: int = 10):
     return out
 
 
+def extra_alpha_sweep(dev, steps: int = 10):
+    """The benchmark step at the other sharpness values of the 64-segment
+    workload (alpha = 10 and 1000; 100 is the main line)."""
+    import numpy as np
+    import torch
+
+    from paper_2401_11882_amd import tracer as tr
+    from paper_2401_11882_amd import workloads as WL
+    out = {"workload": "box + 64 segments, 256^2 rx, order<=2 (4625 candidates), fwd + adjoint from the cache"}
+    for alpha in (10.0, 1000.0):
+        s = WL.scene_64(alpha=alpha)
+        walls, tx, rx = (torch.tensor(a, device=dev) for a in (s.walls, s.tx, s.rx))
+        sc = tr.Scene(walls, tx, rx, 2, alpha, grid_nx=s.grid_n)
+
+        def step():
+            P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+            mid = torch.cuda.Event(enable_timing=True)
+            mid.record()
+            tr.backward(sc, seed, reuse_forward=True)
+            return mid
+
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        mids = []
+        for e0, e1 in ev:
+            e0.record()
+            mids.append(step())
+            e1.record()
+        torch.cuda.synchronize()
+        fwd = float(np.mean([e0.elapsed_time(m) for (e0, _), m in zip(ev, mids)]))
+        bwd = float(np.mean([m.elapsed_time(e1) for (_, e1), m in zip(ev, mids)]))
+        out[f"alpha_{int(alpha)}"] = {"ms_per_step": round(fwd + bwd, 4), "fwd_ms": round(fwd, 4),
+                                      "bwd_ms": round(bwd, 4), "value": s.n_rx * 4625 / ((fwd + bwd) * 1e-3)}
+    return out
+
+
 def extra_placement():
     """Sec. VI: success rate of annealed versus unsmoothed transmitter placement."""
     import torch
@@ -230,6 +275,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, order-3 loop and surrogate measurements")
+    ap.add_argument("--extra", default=None,
+                    help="run only the named extra measurement (scene3d, alpha_sweep, hard_sigmoid, ...) "
+                         "and print its JSON")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     args = ap.parse_args()
@@ -238,6 +286,18 @@ def main() -> int:
               "note, not part of this build.", file=sys.stderr)
         return 2
     rank = int(os.environ.get("RANK", "0"))
+    if args.extra is not None:
+        import torch
+        dev = torch.device("cuda:0")
+        fns = {"scene3d": lambda: extra_3d(dev), "alpha_sweep": lambda: extra_alpha_sweep(dev),
+               "hard_sigmoid": lambda: extra_hard_sigmoid(dev), "batched": lambda: extra_batched(dev),
+               "order3_loop": lambda: extra_order3_loop(dev), "placement": extra_placement,
+               "surrogate": extra_surrogate}
+        if args.extra not in fns:
+            print(f"unknown extra {args.extra!r}; choose from {sorted(fns)}", file=sys.stderr)
+            return 2
+        print(json.dumps({args.extra: fns[args.extra]()}), flush=True)
+        return 0
 
     import numpy as np
     import torch
@@ -308,11 +368,20 @@ def main() -> int:
             else:
                 name, ms, per = "k_forward", fwd_ms, pa["fwd_flops_per_path_eval"]
             achieved = per * pe_per_step / (ms * 1e-3) / 1e12
+            tag = f"scene64_alpha{int(args.alpha)}"
             roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                        "traffic": measured_traffic(f"scene64_alpha{int(args.alpha)}", name),
+                        "traffic": measured_traffic(tag, name),
                         "kernel": name, "kernel_ms": round(ms, 4),
-                        "flops_per_path_eval": round(per, 2)}
+                        "flops_per_path_eval": round(per, 2),
+                        "frac_of_unpacked_peak": round(achieved / UNPACKED_FP32_TFLOPS, 4)}
+            ctr = measured_counters(tag, name)
+            if ctr is not None and ctr.get("executed_fp32_flops"):
+                # rocprofv3 count of executed FP32 work: 64 lanes x (add + mul + trans + 2 fma)
+                ex = ctr["executed_fp32_flops"] / (ms * 1e-3) / 1e12
+                roofline["executed_tflops"] = round(ex, 3)
+                roofline["executed_frac"] = round(ex / PEAK_FP32_TFLOPS, 4)
+                roofline["executed_frac_of_unpacked_peak"] = round(ex / UNPACKED_FP32_TFLOPS, 4)
 
     out = {
         "metric": "smoothed path-evals/s fwd+bwd (rx x candidates)",
@@ -329,6 +398,7 @@ def main() -> int:
     if rank == 0 and not args.no_extras:
         out["extras"] = {"batched_512_scenes": extra_batched(dev), "order3_adam_loop": extra_order3_loop(dev),
                          "hard_sigmoid": extra_hard_sigmoid(dev), "scene3d": extra_3d(dev),
+                         "alpha_sweep": extra_alpha_sweep(dev),
                          "placement_study": extra_placement(),
                          "surrogate": extra_surrogate()}
         out["surrogate_speedup_at_1pct"] = out["extras"]["surrogate"]["speedup_at_1pct"]
