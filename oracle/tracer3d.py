@@ -217,3 +217,68 @@ def path_details(panels, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_
                     "d2": float(info["d2"][0, ci]),
                 })
     return out
+
+
+def work_counts(panels, tx, rx, max_order: int, alpha: float, margin: float = 18.0,
+                active_log_floor: float = -88.72):
+    """Algorithmic work of the 3D method at these receivers (instrumentation).
+
+    Counts over all (receiver, candidate) pairs, as the 2D reference's
+    work_counts: ``path_evals``, ``interactions``, ``active`` pairs (product of
+    interaction factors above exp(active_log_floor), below which it is 0 in
+    FP32), ``active_interactions``, ``tests`` (obstruction tests of active
+    pairs, a leg's own end panels excluded) and ``unsaturated`` tests (leg
+    parameter and both panel coordinates within margin/alpha of [0, 1];
+    outside, the factor rounds to 1 in FP32).
+    """
+    Pn = _as64(panels).reshape(-1, 9)
+    T = _as64(tx).reshape(3)
+    Rx = _as64(rx).reshape(-1, 3)
+    a = Pn[:, 0:3]
+    e1 = Pn[:, 3:6] - a
+    e2 = Pn[:, 6:9] - a
+    n = torch.linalg.cross(e1, e2, dim=-1)
+    nn = _dot(n, n)
+    nn_s = torch.where(nn > 0, nn, torch.ones_like(nn))
+    groups = _groups(Pn.shape[0], max_order)
+    cs = _chunk(Rx.shape[0], groups, Pn.shape[0], budget=1e6)
+    band = margin / alpha
+    out = dict(path_evals=0, interactions=0, active=0, active_interactions=0, tests=0, unsaturated=0)
+    P = Pn.shape[0]
+    jidx = torch.arange(P)
+    with torch.no_grad():
+        for s in range(0, Rx.shape[0], cs):
+            rxc = Rx[s:s + cs]
+            for k, seq in groups.items():
+                _, info = _group_terms(Pn, T, rxc, seq, alpha, "sigmoid", DEFAULT_DMIN, want_paths=True)
+                X = info["X"]
+                Cn = seq.shape[0]
+                logf = torch.zeros(rxc.shape[0], Cn, dtype=DTYPE)
+                for i, (beta, gamma, u) in info["params"].items():
+                    logf = logf + _log_inside(beta, alpha) + _log_inside(gamma, alpha) + _log_inside(u, alpha)
+                act = info["valid"] & (logf > active_log_floor)
+                out["path_evals"] += rxc.shape[0] * Cn
+                out["interactions"] += rxc.shape[0] * Cn * k
+                out["active"] += int(act.sum())
+                out["active_interactions"] += int(act.sum()) * k
+                for l in range(k + 1):
+                    P0 = X[l]
+                    D = (X[l + 1] - P0)[:, :, None, :]
+                    w0 = a[None, None] - P0[:, :, None, :]
+                    den = _dot(D, n[None, None])
+                    excl = torch.zeros(Cn, P, dtype=torch.bool)
+                    if l >= 1:
+                        excl |= seq[:, l - 1][:, None] == jidx[None]
+                    if l + 1 <= k:
+                        excl |= seq[:, l][:, None] == jidx[None]
+                    use = (~excl[None]) & act[:, :, None] & (nn[None, None] > 0)
+                    den_s = torch.where(den != 0, den, torch.ones_like(den))
+                    ups = _dot(w0, n[None, None]) / den_s
+                    H = P0[:, :, None, :] + ups[..., None] * D
+                    beta, gamma = _panel_coords(H - a[None, None], e1[None, None], e2[None, None], n[None, None],
+                                                nn_s[None, None])
+                    live = use & (den != 0) & ((ups - 0.5).abs() < 0.5 + band) & \
+                        ((beta - 0.5).abs() < 0.5 + band) & ((gamma - 0.5).abs() < 0.5 + band)
+                    out["tests"] += int(use.sum())
+                    out["unsaturated"] += int(live.sum())
+    return out

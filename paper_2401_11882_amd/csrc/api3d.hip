@@ -12,6 +12,7 @@
 
 extern "C" __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char* msg);
 extern "C" __attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void);
+extern "C" __attribute__((visibility("hidden"))) int drt_internal_screen(void);
 
 namespace {
 
@@ -45,7 +46,7 @@ struct Plan3 {
   int nw;
   int ncol;       // 3 + 13 P
   int cache_cap;  // 0 = no contribution cache
-  size_t off_panels, off_loss, off_seed, off_grad, off_tmp, off_cache_c, off_cache_idx, off_cache_n, total;
+  size_t off_panels, off_boxes, off_loss, off_seed, off_grad, off_tmp, off_cache_c, off_cache_idx, off_cache_n, total;
 };
 
 int check_scene3(const drt3_scene* s) {
@@ -82,6 +83,8 @@ Plan3 make_plan3(const drt3_scene* s) {
   size_t off = 0;
   p.off_panels = off;
   off = align_up(off + sizeof(drt::PanelRec) * P1);
+  p.off_boxes = off;
+  off = align_up(off + sizeof(drt::PanelBox) * P1);
   p.off_loss = off;
   off = align_up(off + sizeof(float) * T1);
   p.off_seed = off;
@@ -118,6 +121,8 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   drt::Trace3Args A{};
   char* w = static_cast<char*>(ws);
   A.panels = reinterpret_cast<const drt::PanelRec*>(w + p.off_panels);
+  A.boxes = drt_internal_screen() ? reinterpret_cast<const drt::PanelBox*>(w + p.off_boxes) : nullptr;
+  A.cull_c = drt::kCullMargin / s->alpha;
   A.tx = s->tx_dev;
   A.rx = s->rx_dev;
   A.n_panels = s->n_panels;
@@ -153,8 +158,10 @@ int check_loss3(int32_t loss_kind, float log_eps) {
 }
 
 int prep3(const drt3_scene* s, const Plan3& p, void* ws, hipStream_t st) {
-  hipError_t e = drt::launch_prep_panels(s->panels_dev, s->n_panels,
-                                         reinterpret_cast<drt::PanelRec*>(static_cast<char*>(ws) + p.off_panels), st);
+  char* w = static_cast<char*>(ws);
+  hipError_t e = drt::launch_prep_panels(s->panels_dev, s->n_panels, drt::kCullMargin / s->alpha,
+                                         reinterpret_cast<drt::PanelRec*>(w + p.off_panels),
+                                         reinterpret_cast<drt::PanelBox*>(w + p.off_boxes), st);
   return e == hipSuccess ? DRT_OK : hip_fail(e, "prep_panels launch");
 }
 

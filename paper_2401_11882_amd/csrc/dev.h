@@ -171,10 +171,6 @@ __device__ __forceinline__ float wave_sum4(float a, float b, float c, float d) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);               // lane ^ 16
 }
 
-// Candidate index -> (order k, walls s[0..k-1]).  Candidates are ordered by
-// order, then lexicographically: the first wall is a base-W digit, each later
-// wall a base-(W-1) digit d mapped to d + (d >= previous wall), which skips a
-// back-to-back repeat.  c must be < the candidate count.
 // Compensated sum; a zero term leaves the state as it is, so which zero
 // contributions are visited does not change the result.
 __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
@@ -185,6 +181,10 @@ __device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
   comp = x != 0.0f ? c : comp;
 }
 
+// Candidate index -> (order k, walls s[0..k-1]).  Candidates are ordered by
+// order, then lexicographically: the first wall is a base-W digit, each later
+// wall a base-(W-1) digit d mapped to d + (d >= previous wall), which skips a
+// back-to-back repeat.  c must be < the candidate count.
 struct Cand {
   int k;
   int s0, s1, s2;

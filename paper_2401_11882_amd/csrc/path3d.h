@@ -53,10 +53,29 @@ __device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, fl
   return fmaf(ax, bx, fmaf(ay, by, az * bz));
 }
 
+// Culling data of a panel: the axis-aligned box of the panel extended by
+// cull_c of each edge beyond both ends (centre c, half extents h, grown by a
+// relative 1e-5), its plane (n, n . a) and the scale of its coordinates for
+// the rounding margin of the plane test.
+struct PanelBox {
+  float cx, cy, cz, hx, hy, hz, nx, ny, nz, nda, scale, pad;
+};
+
 struct Scene3View {
   const PanelRec* panels;
+  const PanelBox* boxes;  // NULL: no culling
   int n_panels;
-  float alpha, a2, band_k, dmin2;
+  float alpha, a2, band_k, dmin2, cull_c;
+};
+
+// Wave-uniform axis-aligned box around the extended legs
+// [X_l - c D, X_{l+1} + c D] of the active lanes.  A panel whose extended box
+// misses it, or whose plane does not cut it, cannot give an in-band test on
+// that leg in any of those lanes: the crossing point would have to lie in
+// both.
+struct LegBox3 {
+  float cx, cy, cz, hx, hy, hz;
+  bool empty;
 };
 
 template <int K>
@@ -197,14 +216,97 @@ __device__ __forceinline__ bool obs3(const Scene3View& S, const PanelRec& w, flo
 }
 
 template <int K>
+__device__ __forceinline__ void leg_boxes3(const Path3<K>& P, bool act, float c, LegBox3 (&B)[K + 1]) {
+  const float I = __builtin_inff();
+  const bool none = ballot(act) == 0;
+#pragma unroll
+  for (int l = 0; l <= K; ++l) {
+    const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
+    const float p0x = fmaf(-c, Dx, P.Xx[l]), p0y = fmaf(-c, Dy, P.Xy[l]), p0z = fmaf(-c, Dz, P.Xz[l]);
+    const float p1x = fmaf(c, Dx, P.Xx[l + 1]), p1y = fmaf(c, Dy, P.Xy[l + 1]), p1z = fmaf(c, Dz, P.Xz[l + 1]);
+    // maxima of -lo and hi over the active lanes (others give -inf)
+    float a = act ? -fminf(p0x, p1x) : -I, b = act ? -fminf(p0y, p1y) : -I;
+    float cc = act ? -fminf(p0z, p1z) : -I, d = act ? fmaxf(p0x, p1x) : -I;
+    float e = act ? fmaxf(p0y, p1y) : -I, f = act ? fmaxf(p0z, p1z) : -I, g = -I, h = -I;
+    wave_max4(a, b, cc, d);
+    wave_max4(e, f, g, h);
+    B[l].empty = none;
+    if (none) a = b = cc = d = e = f = 0.0f;
+    const float hx = 0.5f * (d + a), hy = 0.5f * (e + b), hz = 0.5f * (f + cc);
+    B[l].cx = uniformf(0.5f * (d - a));
+    B[l].cy = uniformf(0.5f * (e - b));
+    B[l].cz = uniformf(0.5f * (f - cc));
+    B[l].hx = uniformf(hx + 1e-5f * (fabsf(B[l].cx) + hx));
+    B[l].hy = uniformf(hy + 1e-5f * (fabsf(B[l].cy) + hy));
+    B[l].hz = uniformf(hz + 1e-5f * (fabsf(B[l].cz) + hz));
+  }
+}
+
+// Calls fn(panel, masks, bit) for every panel not culled for some leg, in
+// increasing order; masks[l] bit `bit` says whether leg l needs the test (a
+// leg's own end panels excluded).  Lane j checks panel b + j of each batch of
+// 64.  Without culling data every panel is visited.
+template <int K, class Fn>
+__device__ __forceinline__ void visit_panels(const Scene3View& S, const Path3<K>& P, const LegBox3 (&B)[K + 1],
+                                             Fn&& fn) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int b = 0; b < S.n_panels; b += kWave) {
+    const int pj = b + lane;
+    const bool valid = pj < S.n_panels;
+    uint64_t m[K + 1];
+    uint64_t uni = 0;
+    if (S.boxes) {
+      PanelBox q;
+      if (valid) {
+        q = S.boxes[pj];
+      } else {
+        q.cx = q.cy = q.cz = q.hx = q.hy = q.hz = q.nx = q.ny = q.nz = q.nda = q.scale = q.pad = 0.0f;
+      }
+      const float an = fabsf(q.nx) + fabsf(q.ny) + fabsf(q.nz);
+#pragma unroll
+      for (int l = 0; l <= K; ++l) {
+        const LegBox3& L = B[l];
+        const bool sep_box = (fabsf(q.cx - L.cx) > q.hx + L.hx) | (fabsf(q.cy - L.cy) > q.hy + L.hy) |
+                             (fabsf(q.cz - L.cz) > q.hz + L.hz);
+        const float ext = fmaf(fabsf(q.nx), L.hx, fmaf(fabsf(q.ny), L.hy, fabsf(q.nz) * L.hz));
+        const float mar = 1e-5f * an * (fabsf(L.cx) + fabsf(L.cy) + fabsf(L.cz) + L.hx + L.hy + L.hz + q.scale);
+        const bool sep_plane = fabsf(dot3(q.nx, q.ny, q.nz, L.cx, L.cy, L.cz) - q.nda) > ext + mar;
+        const bool ov = valid & !L.empty & !sep_box & !sep_plane & (pj != P.lo[l]) & (pj != P.hi[l]);
+        m[l] = ballot(ov);
+        uni |= m[l];
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l <= K; ++l) {
+        m[l] = ballot(valid & !B[l].empty & (pj != P.lo[l]) & (pj != P.hi[l]));
+        uni |= m[l];
+      }
+    }
+    while (uni) {
+      const int j = __builtin_ctzll(uni);
+      uni &= uni - 1;
+      if (!fn(b + j, m, j)) return;
+    }
+  }
+}
+
+template <int K>
 __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<K>& P, float V) {
   const bool act = P.F != 0.0f;
-  for (int j = 0; j < S.n_panels; ++j) {
+  LegBox3 B[K + 1];
+  if (S.boxes) {
+    leg_boxes3<K>(P, act, S.cull_c, B);
+  } else {
+    const bool none = ballot(act) == 0;
+#pragma unroll
+    for (int l = 0; l <= K; ++l) B[l].empty = none;
+  }
+  visit_panels<K>(S, P, B, [&](int j, const uint64_t* m, int bit) {
     const PanelRec w = load_panel(S.panels, j);
     bool upd = false;
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
-      if (j == P.lo[l] || j == P.hi[l]) continue;
+      if (((m[l] >> bit) & 1ull) == 0) continue;
       const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
       Obs3 o;
       bool ib;
@@ -214,8 +316,9 @@ __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<
         upd = true;
       }
     }
-    if (ballot(upd) != 0 && ballot(V != 0.0f) == 0) break;   // every lane fully blocked
-  }
+    // once every lane's product is exactly 0 no further factor can change it
+    return ballot(upd) == 0 || ballot(V != 0.0f) != 0;
+  });
   return V;
 }
 
@@ -263,7 +366,15 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
   for (int i = 0; i < K + 1; ++i) gIx[i] = gIy[i] = gIz[i] = 0.0f;
 
   // -- obstruction factors: d log q / d(ups, beta, gamma) = -L_x / num
-  for (int j = 0; j < S.n_panels; ++j) {
+  LegBox3 B[K + 1];
+  if (S.boxes) {
+    leg_boxes3<K>(P, act, S.cull_c, B);
+  } else {
+    const bool none = ballot(act) == 0;
+#pragma unroll
+    for (int l = 0; l <= K; ++l) B[l].empty = none;
+  }
+  visit_panels<K>(S, P, B, [&](int j, const uint64_t* m, int bit) {
     const PanelRec w = load_panel(S.panels, j);
     float g[kPanelGrad];
 #pragma unroll
@@ -271,7 +382,7 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
     bool any = false;
 #pragma unroll
     for (int l = 0; l <= K; ++l) {
-      if (j == P.lo[l] || j == P.hi[l]) continue;
+      if (((m[l] >> bit) & 1ull) == 0) continue;
       const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
       Obs3 o;
       bool ib;
@@ -313,7 +424,8 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
       any = true;
     }
     if (ballot(any) != 0) acc_panel(acc, j, g, lane);
-  }
+    return true;
+  });
 
   // -- image distance |r - I_K|^2 (zero gradient under the d_min floor)
   {

@@ -7,9 +7,12 @@
 namespace drt {
 
 struct PanelRec;
+struct PanelBox;
 
 struct Trace3Args {
   const PanelRec* panels;  // prepared panel records [n_panels]
+  const PanelBox* boxes;   // culling boxes [n_panels], NULL: no culling
+  float cull_c;            // 20 / alpha: culling extension of legs and panels
   const float* tx;         // [3]
   const float* rx;         // [n_rx][3]
   int n_panels;
@@ -27,7 +30,8 @@ struct Trace3Args {
   int cache_cap;
 };
 
-hipError_t launch_prep_panels(const float* panels, int n, PanelRec* out, hipStream_t st);
+hipError_t launch_prep_panels(const float* panels, int n, float cull_c, PanelRec* out, PanelBox* boxes,
+                              hipStream_t st);
 hipError_t launch_forward3(const Trace3Args& A, int n_tiles, int nw, float* power, float* seed, float* loss_part,
                            int loss_kind, float log_eps, hipStream_t st);
 hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, int reuse,

@@ -16,6 +16,8 @@ namespace drt {
 __device__ __forceinline__ Scene3View view3_of(const Trace3Args& A) {
   Scene3View S;
   S.panels = A.panels;
+  S.boxes = A.boxes;
+  S.cull_c = A.cull_c;
   S.n_panels = A.n_panels;
   S.alpha = A.alpha;
   S.a2 = A.a2;
@@ -24,8 +26,9 @@ __device__ __forceinline__ Scene3View view3_of(const Trace3Args& A) {
   return S;
 }
 
-// Panel records from the corners (a, b, c).
-__global__ void k_prep_panels(const float* __restrict__ pan, int n, PanelRec* __restrict__ out) {
+// Panel records and culling boxes from the corners (a, b, c).
+__global__ void k_prep_panels(const float* __restrict__ pan, int n, float cull_c, PanelRec* __restrict__ out,
+                              PanelBox* __restrict__ boxes) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const float* p = pan + 9 * (size_t)j;
@@ -53,6 +56,33 @@ __global__ void k_prep_panels(const float* __restrict__ pan, int n, PanelRec* __
   r.nda = nx * ax + ny * ay + nz * az;
   r.pad0 = r.pad1 = 0.0f;
   out[j] = r;
+  if (!boxes) return;
+  // extended parallelogram a - c (e1 + e2) + [0, 1 + 2c] e1 + [0, 1 + 2c] e2
+  const float k = 1.0f + 2.0f * cull_c;
+  const float q0x = ax - cull_c * (e1x + e2x), q0y = ay - cull_c * (e1y + e2y), q0z = az - cull_c * (e1z + e2z);
+  const float lox = q0x + fminf(0.0f, k * e1x) + fminf(0.0f, k * e2x);
+  const float loy = q0y + fminf(0.0f, k * e1y) + fminf(0.0f, k * e2y);
+  const float loz = q0z + fminf(0.0f, k * e1z) + fminf(0.0f, k * e2z);
+  const float hix = q0x + fmaxf(0.0f, k * e1x) + fmaxf(0.0f, k * e2x);
+  const float hiy = q0y + fmaxf(0.0f, k * e1y) + fmaxf(0.0f, k * e2y);
+  const float hiz = q0z + fmaxf(0.0f, k * e1z) + fmaxf(0.0f, k * e2z);
+  PanelBox q;
+  q.cx = 0.5f * (lox + hix);
+  q.cy = 0.5f * (loy + hiy);
+  q.cz = 0.5f * (loz + hiz);
+  const float hx = 0.5f * (hix - lox), hy = 0.5f * (hiy - loy), hz = 0.5f * (hiz - loz);
+  q.hx = hx + 1e-5f * (fabsf(q.cx) + hx);
+  q.hy = hy + 1e-5f * (fabsf(q.cy) + hy);
+  q.hz = hz + 1e-5f * (fabsf(q.cz) + hz);
+  if (!(N > 0.0f)) q.hx = q.hy = q.hz = -__builtin_inff();  // zero area: never tested
+  q.nx = nx;
+  q.ny = ny;
+  q.nz = nz;
+  q.nda = r.nda;
+  q.scale = fabsf(ax) + fabsf(ay) + fabsf(az) + fabsf(e1x) + fabsf(e1y) + fabsf(e1z) + fabsf(e2x) + fabsf(e2y) +
+            fabsf(e2z);
+  q.pad = 0.0f;
+  boxes[j] = q;
 }
 
 template <int NW>
@@ -228,9 +258,10 @@ __global__ void k_panel_grads(const float* __restrict__ gr, const float* __restr
   o[8] = ge2z;
 }
 
-hipError_t launch_prep_panels(const float* panels, int n, PanelRec* out, hipStream_t st) {
+hipError_t launch_prep_panels(const float* panels, int n, float cull_c, PanelRec* out, PanelBox* boxes,
+                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep_panels, dim3((n + 255) / 256), dim3(256), 0, st, panels, n, out);
+  hipLaunchKernelGGL(k_prep_panels, dim3((n + 255) / 256), dim3(256), 0, st, panels, n, cull_c, out, boxes);
   return hipGetLastError();
 }
 

@@ -151,3 +151,22 @@ def test_empty_receiver_set():
     P, L, gtx, gp = tr.forward_backward(sc, loss="sum")
     assert P.numel() == 0 and float(L) == 0.0
     assert torch.count_nonzero(gtx) == 0 and torch.count_nonzero(gp) == 0
+
+
+@pytest.mark.parametrize("alpha", [10.0, 100.0])
+def test_panel_culling_changes_no_bit(alpha):
+    """Culled (panel, leg) pairs are ones whose factor is exactly 1 in every
+    lane: with culling off (the process-wide screen switch) every output is
+    bitwise the same."""
+    from paper_2401_11882_amd import tracer as tr
+    tr3 = _tr3()
+    s = WL.scene3d_room(9, 12, 16, 2, alpha, seed=21)
+    sc = _scene(s)
+    on = tr3.forward_backward(sc, loss="neg_mean_log")
+    tr.set_screen(False)
+    try:
+        off = tr3.forward_backward(sc, loss="neg_mean_log")
+    finally:
+        tr.set_screen(True)
+    for a, b in zip(on, off):
+        assert torch.equal(a, b)
