@@ -259,10 +259,22 @@ def extra_3d(dev, steps: int = 10):
     fwd = float(np.mean([e0.elapsed_time(m) for (e0, _), m in zip(ev, mids)]))
     bwd = float(np.mean([m.elapsed_time(e1) for (_, e1), m in zip(ev, mids)]))
     ms = fwd + bwd
-    return {"workload": "room + 32 rectangles (38 panels), 256^2 rx, order<=2 (1445 candidates), alpha=100, "
-                        "fwd + adjoint w.r.t. tx and all panel corners",
-            "ms_per_step": round(ms, 4), "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
-            "value": s.n_rx * n_cand / (ms * 1e-3), "unit": "path-evals/s"}
+    out = {"workload": "room + 32 rectangles (38 panels), 256^2 rx, order<=2 (1445 candidates), alpha=100, "
+                       "fwd + adjoint w.r.t. tx and all panel corners",
+           "ms_per_step": round(ms, 4), "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+           "value": s.n_rx * n_cand / (ms * 1e-3), "unit": "path-evals/s"}
+    wm_path = os.path.join(ROOT, "bench_work_model.json")
+    if os.path.exists(wm_path):
+        with open(wm_path) as f:
+            pa = json.load(f).get("scene3d", {}).get("per_alpha", {}).get(str(int(s.alpha)))
+        if pa is not None:
+            name, kms, per = (("k_backward3", bwd, pa["bwd_flops_per_path_eval"]) if bwd >= fwd
+                              else ("k_forward3", fwd, pa["fwd_flops_per_path_eval"]))
+            achieved = per * s.n_rx * n_cand / (kms * 1e-3) / 1e12
+            out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                               "kernel": name, "kernel_ms": round(kms, 4), "flops_per_path_eval": round(per, 2)}
+    return out
 
 
 def main() -> int:

@@ -1,10 +1,11 @@
 """Write the algorithmic work model of the benchmark workload.
 
 Runs only oracle code (FP64, CPU) on a seeded receiver sample of the
-64-segment scene (box + 64 segments, 256x256 receivers, order <= 2) and
-writes per-path-evaluation counts to bench_work_model.json at the repository
-root.  bench.py turns them into algorithmic FLOPs with the per-operation
-weights stored alongside.
+64-segment scene (box + 64 segments, 256x256 receivers, order <= 2) and of
+the 3D scene (room + 32 rectangles, 256x256 receivers, order <= 2) and writes
+per-path-evaluation counts to bench_work_model.json at the repository root.
+bench.py turns them into algorithmic FLOPs with the per-operation weights
+stored alongside.
 
 Usage: python -m oracle.count_work [--sample 256]
 """
@@ -21,6 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 from oracle import tracer as T  # noqa: E402
+from oracle import tracer3d as T3  # noqa: E402
 from paper_2401_11882_amd import workloads as WL  # noqa: E402
 
 # FLOPs per operation (FMA = 2, add/mul/compare = 1, exp2/rcp = 1).  Only
@@ -39,6 +41,32 @@ WEIGHTS = {
 }
 
 
+# The same accounting for panels in 3D (dot products of three, one more
+# panel coordinate and one more smoothed comparison per test).
+WEIGHTS_3D = {
+    "fwd_per_path_eval": 14,           # |r - I_k|^2, floor, divide, compensated sum
+    "fwd_per_interaction": 36,         # back-trace step to the plane, panel coordinates
+    "fwd_per_active_interaction": 28,  # in(beta) in(gamma) in(u): 6 exp, products, reciprocal
+    "fwd_per_unsaturated": 76,         # plane crossing and band tests (42), three n_x and the factor (34)
+    "bwd_per_active_path_eval": 14,    # dL/dc, |r - I_k|^2 adjoint
+    "bwd_per_active_interaction": 141,  # derivatives of the three factors, back-trace and mirror adjoint
+    "bwd_per_unsaturated": 176,        # the test's values (72) + three log-derivatives and the chain (104)
+}
+
+
+def model(counts: dict, W: dict) -> dict:
+    n = counts["path_evals"]
+    per = {k: v / n for k, v in counts.items()}
+    fwd = (W["fwd_per_path_eval"] + W["fwd_per_interaction"] * per["interactions"] +
+           W["fwd_per_active_interaction"] * per["active_interactions"] +
+           W["fwd_per_unsaturated"] * per["unsaturated"])
+    # reverse sweep from the recorded contributions
+    bwd = (W["bwd_per_active_path_eval"] * per["active"] +
+           W["bwd_per_active_interaction"] * per["active_interactions"] +
+           W["bwd_per_unsaturated"] * per["unsaturated"])
+    return {"counts": counts, "per_path_eval": per, "fwd_flops_per_path_eval": fwd, "bwd_flops_per_path_eval": bwd}
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--sample", type=int, default=256)
@@ -50,22 +78,14 @@ def main() -> None:
         s = WL.scene_64(alpha=a)
         idx = np.random.default_rng(11882).choice(s.n_rx, size=args.sample, replace=False)
         c = T.work_counts(s.walls, s.tx, s.rx[idx], s.max_order, a)
-        n = c["path_evals"]
-        per = {k: v / n for k, v in c.items()}
-        W = WEIGHTS
-        fwd = (W["fwd_per_path_eval"] + W["fwd_per_interaction"] * per["interactions"] +
-               W["fwd_per_active_interaction"] * per["active_interactions"] +
-               W["fwd_per_unsaturated"] * per["unsaturated"])
-        # reverse sweep from the recorded contributions
-        bwd = (W["bwd_per_active_path_eval"] * per["active"] +
-               W["bwd_per_active_interaction"] * per["active_interactions"] +
-               W["bwd_per_unsaturated"] * per["unsaturated"])
-        out["per_alpha"][str(int(a))] = {
-            "counts": c, "per_path_eval": per,
-            "fwd_flops_per_path_eval": fwd,
-            "bwd_flops_per_path_eval": bwd,
-        }
+        out["per_alpha"][str(int(a))] = model(c, WEIGHTS)
         print(a, json.dumps(out["per_alpha"][str(int(a))]), flush=True)
+    s3 = WL.scene3d_32()
+    idx = np.random.default_rng(11882).choice(s3.n_rx, size=args.sample, replace=False)
+    c3 = T3.work_counts(s3.panels, s3.tx, s3.rx[idx], s3.max_order, s3.alpha)
+    out["scene3d"] = {"workload": "room + 32 rectangles (38 panels), 256x256 receivers, order <= 2 (1,445 candidates)",
+                      "weights": WEIGHTS_3D, "per_alpha": {str(int(s3.alpha)): model(c3, WEIGHTS_3D)}}
+    print("3d", json.dumps(out["scene3d"]["per_alpha"]), flush=True)
     with open(os.path.join(ROOT, "bench_work_model.json"), "w") as f:
         json.dump(out, f, indent=1)
 

@@ -86,7 +86,7 @@ __global__ void k_prep_panels(const float* __restrict__ pan, int n, float cull_c
 }
 
 template <int NW>
-__global__ __launch_bounds__(NW * kWave) void k_forward3(Trace3Args A, float* __restrict__ power,
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_forward3(Trace3Args A, float* __restrict__ power,
                                                          float* __restrict__ seed, float* __restrict__ loss_part,
                                                          int loss_kind, float log_eps) {
   __shared__ float red[NW][2][kWave];
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(NW * kWave) void k_forward3(Trace3Args A, float* __
 }
 
 template <int NW>
-__global__ __launch_bounds__(NW * kWave) void k_backward3(Trace3Args A, const float* __restrict__ gP,
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_backward3(Trace3Args A, const float* __restrict__ gP,
                                                           float* __restrict__ part, int reuse) {
   extern __shared__ float smem3[];
   const Scene3View S = view3_of(A);
