@@ -387,6 +387,13 @@ def main() -> int:
                         "kernel": name, "kernel_ms": round(ms, 4),
                         "flops_per_path_eval": round(per, 2),
                         "frac_of_unpacked_peak": round(achieved / UNPACKED_FP32_TFLOPS, 4)}
+            try:
+                fma_peak, exp_rate = tr.valu_peak()
+                roofline["sustained_fma_tflops"] = round(fma_peak, 2)
+                roofline["sustained_exp_tlanes"] = round(exp_rate, 2)
+                roofline["frac_of_sustained_fma"] = round(achieved / fma_peak, 4)
+            except Exception as exc:  # diagnostic only; the line is valid without it
+                roofline["sustained_fma_tflops"] = f"unavailable: {exc}"
             ctr = measured_counters(tag, name)
             if ctr is not None and ctr.get("executed_fp32_flops"):
                 # rocprofv3 count of executed FP32 work: 64 lanes x (add + mul + trans + 2 fma)

@@ -31,8 +31,9 @@
  *   - Pointers named *_dev are DEVICE pointers, owned by the caller; the
  *     library never frees or retains them.  Only drt_plan_create,
  *     drt_plan_set_config, drt_batched_autotune and drt_mlp_create allocate
- *     device memory, which their handle owns.  Pointers to drt_* structs are
- *     HOST pointers read during the call only.
+ *     device memory, which their handle owns (the diagnostic drt_valu_peak
+ *     frees what it allocates).  Pointers to drt_* structs are HOST
+ *     pointers read during the call only.
  *   - Layouts: walls float32 [n_walls][4] = (ax, ay, bx, by); tx float32 [2];
  *     rx float32 [n_rx][2]; grad_walls float32 [n_walls][4] in the same
  *     order; power / grad_power float32 [n_rx].
@@ -133,8 +134,10 @@ int drt_set_cache_limit(int64_t bytes);
    wavefront first tests 64 candidates at a time against the bounding box of
    its receivers and drops those whose interaction factor is provably
    exactly 0 at every receiver of the box (a back-trace parameter beyond the
-   range where exp(-alpha x) overflows FP32; Sec. IV-A, Eq. 3-4).  It changes
-   no result beyond the summation order of zero terms; turning it off exists
+   range where exp(-alpha x) overflows FP32; Sec. IV-A, Eq. 3-4).  The same
+   switch controls the panel culling of the 3D calls (obstruction tests whose
+   factor is exactly 1 in every lane are not evaluated).  Neither changes any
+   result beyond the summation order of zero terms; turning them off exists
    to verify that.  Process-wide. */
 int drt_set_screen(int32_t enabled);
 
@@ -357,6 +360,15 @@ int drt_mlp_scan(drt_mlp* mlp, const float* tx_dev, int32_t n_tx, const float* r
 
 /* y_dev[i] = log(power_dev[i] + eps), the surrogate's training target. */
 int drt_log_targets(const float* power_dev, int64_t n, float eps, float* y_dev, void* stream);
+
+/* Diagnostic, not part of the method: sustained FP32 VALU rates of the
+   current device, measured with two throughput kernels (plain FMA chains and
+   v_exp_f32 chains, a few ms each, best of three): fma_tflops in TFLOP/s
+   (an FMA counts 2), exp_tlanes in 1e12 lane-operations/s.  They put the
+   tracer kernels' rates in context next to the datasheet peak.  Allocates a
+   32 MiB buffer, runs on the default stream and synchronises; not for
+   graph capture. */
+int drt_valu_peak(double* fma_tflops, double* exp_tlanes);
 
 /* ------------------------------------------------------------------------
  * Scenes in three dimensions (Sec. V: the method makes no assumption on

@@ -106,6 +106,7 @@ _SIGS = {
     "drt_mlp_forward": ([c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p], c_int32),
     "drt_mlp_scan": ([c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p], c_int32),
     "drt_log_targets": ([c_void_p, ctypes.c_int64, c_float, c_void_p, c_void_p], c_int32),
+    "drt_valu_peak": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)], c_int32),
     "drt3_workspace_size": ([ctypes.POINTER(Drt3Scene), ctypes.POINTER(c_size_t)], c_int32),
     "drt3_forward": ([ctypes.POINTER(Drt3Scene), c_int32, c_float, c_void_p, c_void_p, c_void_p,
                       c_void_p, c_size_t, c_void_p], c_int32),

@@ -97,6 +97,13 @@ def num_candidates(n_walls: int, max_order: int) -> int:
     return int(c.value)
 
 
+def valu_peak() -> tuple[float, float]:
+    """(sustained FP32 FMA TFLOP/s, v_exp_f32 1e12 lane-ops/s) of the current device (diagnostic)."""
+    f, e = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    check(lib().drt_valu_peak(ctypes.byref(f), ctypes.byref(e)))
+    return float(f.value), float(e.value)
+
+
 def set_launch_config(nw: int = 0, cchunk: int = 0) -> None:
     check(lib().drt_set_launch_config(int(nw), int(cchunk)))
 

@@ -208,3 +208,10 @@ def test_scene3_call_validation_before_launch():
                                    None) == _lib.DRT_EINVAL
     empty = _scene3(n_rx=0, rx_dev=None, rx_grid_nx=0)
     assert L.drt3_forward(ctypes.byref(empty), 3, 1e-6, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+
+
+def test_valu_peak_rejects_null_outputs():
+    L = _lib.lib()
+    d = ctypes.c_double()
+    assert L.drt_valu_peak(None, ctypes.byref(d)) == _lib.DRT_EINVAL
+    assert L.drt_valu_peak(ctypes.byref(d), None) == _lib.DRT_EINVAL

@@ -342,3 +342,13 @@ def test_maximum_wall_count_sampled():
     gtx, gw, _ = tr.backward(sc, seed * _dev(w))
     gw_o, gt_o, _ = T.vjp(walls, tx, rx[idx], 1, 100.0, seed.cpu().numpy()[idx])
     PU.check_grads(gtx.cpu().numpy(), gw.cpu().numpy(), gt_o, gw_o, "1024 walls")
+
+
+def test_valu_peak_probe_is_plausible():
+    """The sustained-rate diagnostic used for roofline context: an FMA rate
+    below the datasheet FP32 peak (157.3 TFLOP/s counts packed issue) and a
+    positive exponential rate below the FMA lane rate."""
+    tr = _tr()
+    fma, ex = tr.valu_peak()
+    assert 10.0 < fma < 157.3
+    assert 0.0 < ex < fma
