@@ -123,6 +123,7 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   A.panels = reinterpret_cast<const drt::PanelRec*>(w + p.off_panels);
   A.boxes = drt_internal_screen() ? reinterpret_cast<const drt::PanelBox*>(w + p.off_boxes) : nullptr;
   A.cull_c = drt::kCullMargin / s->alpha;
+  A.screen = drt_internal_screen();
   A.tx = s->tx_dev;
   A.rx = s->rx_dev;
   A.n_panels = s->n_panels;

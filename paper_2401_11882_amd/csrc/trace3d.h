@@ -13,6 +13,7 @@ struct Trace3Args {
   const PanelRec* panels;  // prepared panel records [n_panels]
   const PanelBox* boxes;   // culling boxes [n_panels], NULL: no culling
   float cull_c;            // 20 / alpha: culling extension of legs and panels
+  int screen;              // 1: drop candidates that are exactly 0 over a wavefront's receiver box
   const float* tx;         // [3]
   const float* rx;         // [n_rx][3]
   int n_panels;

@@ -2,12 +2,14 @@
 // gradient map, for gfx950 (wave64).  Same decomposition as the 2D tracer: a
 // workgroup owns 64 receivers, its wavefronts split the candidates, every
 // lane is one receiver, and the candidate and the panel under test are
-// wave-uniform.  Exact skips: a candidate whose interaction factor is 0 in
+// wave-uniform.  Exact skips: candidates screened out over the wavefront's
+// receiver box (screen3.h); a candidate whose interaction factor is 0 in
 // every lane stops before its exponentials; an obstruction test whose leg
 // parameter, or panel coordinates, lie more than 18/alpha outside [0, 1] has
 // the factor 1.0f and is skipped wave-wide; a candidate whose lanes are all
 // fully blocked stops its panel loop.
 #include "path3d.h"
+#include "screen3.h"
 #include "trace.h"
 #include "trace3d.h"
 
@@ -103,20 +105,20 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   int* cache_idx = A.cache_c ? A.cache_idx + (size_t)slot * A.cache_cap : nullptr;
   int nst = 0;
   float sum = 0.0f, comp = 0.0f;
-  if (ballot(live) != 0) {
-    for (int c = wave; c < A.n_cand; c += NW) {
-      const Cand cd = decode_candidate(c, A.n_panels);
-      const float v = candidate_power3(S, cd, tx, ty, tz, rx, ry, rz, live);
-      kahan_add(sum, comp, v);
-      if (cache_c && ballot(v != 0.0f) != 0) {
-        if (nst < A.cache_cap) {
-          cache_c[(size_t)nst * kWave + lane] = v;
-          if (lane == 0) cache_idx[nst] = c;
-        }
-        ++nst;
-      }
-    }
-  }
+  const RxBox3 box = rx_box3(rx, ry, rz, live);
+  const float lim = 128.0f / A.a2 * 1.00001f;
+  for_screened3(A.panels, A.n_panels, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box,
+                [&](int c, const Cand& cd) {
+                  const float v = candidate_power3(S, cd, tx, ty, tz, rx, ry, rz, live);
+                  kahan_add(sum, comp, v);
+                  if (cache_c && ballot(v != 0.0f) != 0) {
+                    if (nst < A.cache_cap) {
+                      cache_c[(size_t)nst * kWave + lane] = v;
+                      if (lane == 0) cache_idx[nst] = c;
+                    }
+                    ++nst;
+                  }
+                });
   if (cache_c && lane == 0) A.cache_n[slot] = nst <= A.cache_cap ? nst : -1;
   red[wave][0][lane] = sum;
   red[wave][1][lane] = comp;
