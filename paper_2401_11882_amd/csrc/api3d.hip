@@ -46,8 +46,14 @@ struct Plan3 {
   int nw;
   int ncol;       // 3 + 13 P
   int cache_cap;  // 0 = no contribution cache
-  size_t off_panels, off_boxes, off_loss, off_seed, off_grad, off_tmp, off_cache_c, off_cache_idx, off_cache_n, total;
+  size_t off_panels, off_boxes, off_loss, off_seed, off_grad, off_tmp, off_cache_c, off_cache_idx, off_cache_n,
+      off_cache_mask, total;
+  int mask_nb;      // 64-panel batches: max(1, ceil(P / 64))
+  int mask_stride;  // culling-mask words per cache entry: (max_order + 1) mask_nb
 };
+
+// A cache entry's culling masks occupy one 64-bit register per lane.
+static_assert((DRT_MAX_ORDER + 1) * ((DRT3_MAX_PANELS + 63) / 64) <= 64, "culling masks exceed one wavefront");
 
 int check_scene3(const drt3_scene* s) {
   if (!s) return failf(DRT_EINVAL, "scene is NULL");
@@ -97,7 +103,9 @@ Plan3 make_plan3(const drt3_scene* s) {
   const int64_t n_cand = count_candidates(s->n_panels, s->max_order);
   const int64_t per_wave = (n_cand + p.nw - 1) / p.nw;
   const int64_t slots = (int64_t)p.n_tiles * p.nw;
-  const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int);
+  p.mask_nb = s->n_panels > 0 ? (s->n_panels + drt::kWave - 1) / drt::kWave : 1;
+  p.mask_stride = (s->max_order + 1) * p.mask_nb;
+  const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int) + (int64_t)p.mask_stride * sizeof(uint64_t);
   const int64_t limit = drt_internal_cache_limit();
   int64_t cap = per_wave;
   if (slots > 0 && limit > 0) {
@@ -113,6 +121,8 @@ Plan3 make_plan3(const drt3_scene* s) {
   off = align_up(off + sizeof(int) * (size_t)slots * p.cache_cap);
   p.off_cache_n = off;
   off = align_up(off + sizeof(int) * (size_t)(p.cache_cap > 0 ? slots : 0));
+  p.off_cache_mask = off;
+  off = align_up(off + sizeof(uint64_t) * (size_t)slots * p.cache_cap * p.mask_stride);
   p.total = off;
   return p;
 }
@@ -139,7 +149,10 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
     A.cache_idx = reinterpret_cast<int*>(w + p.off_cache_idx);
     A.cache_n = reinterpret_cast<int*>(w + p.off_cache_n);
     A.cache_cap = p.cache_cap;
+    A.cache_mask = reinterpret_cast<uint64_t*>(w + p.off_cache_mask);
+    A.mask_stride = p.mask_stride;
   }
+  A.mask_nb = p.mask_nb;
   return A;
 }
 

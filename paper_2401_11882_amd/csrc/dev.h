@@ -85,6 +85,13 @@ __device__ __forceinline__ float uniformf(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
+// Lane l's 64-bit value (l wave-uniform).
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Sum over the 64 lanes of a wavefront with DPP; the total is returned as a
 // wave-uniform value.  Steps: quad swaps, row shifts by 4 and 8 (lane 15 of
 // each 16-lane row then holds the row sum), row broadcasts 15 and 31 (lane 63

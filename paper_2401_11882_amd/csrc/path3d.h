@@ -65,6 +65,7 @@ struct Scene3View {
   const PanelRec* panels;
   const PanelBox* boxes;  // NULL: no culling
   int n_panels;
+  int mask_nb;            // 64-panel batches per leg in a recorded culling mask
   float alpha, a2, band_k, dmin2, cull_c;
 };
 
@@ -246,16 +247,28 @@ __device__ __forceinline__ void leg_boxes3(const Path3<K>& P, bool act, float c,
 // increasing order; masks[l] bit `bit` says whether leg l needs the test (a
 // leg's own end panels excluded).  Lane j checks panel b + j of each batch of
 // 64.  Without culling data every panel is visited.
+// The mask of batch i for leg l is word l * nb + i of a candidate's record
+// (nb = S.mask_nb, (K + 1) nb <= 64 words).  With mask_out (the wavefront's
+// LDS record) each computed mask is written there; with mask_in (one word per
+// lane, lane = word) the masks are taken from it (the boxes are then not
+// used), so an adjoint visits exactly the panels its forward visited.
 template <int K, class Fn>
 __device__ __forceinline__ void visit_panels(const Scene3View& S, const Path3<K>& P, const LegBox3 (&B)[K + 1],
-                                             Fn&& fn) {
+                                             Fn&& fn, uint64_t* mask_out = nullptr,
+                                             const uint64_t* mask_in = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
-  for (int b = 0; b < S.n_panels; b += kWave) {
+  for (int b = 0, bi = 0; b < S.n_panels; b += kWave, ++bi) {
     const int pj = b + lane;
     const bool valid = pj < S.n_panels;
     uint64_t m[K + 1];
     uint64_t uni = 0;
-    if (S.boxes) {
+    if (mask_in) {
+#pragma unroll
+      for (int l = 0; l <= K; ++l) {
+        m[l] = readlane_u64(*mask_in, l * S.mask_nb + bi);
+        uni |= m[l];
+      }
+    } else if (S.boxes) {
       PanelBox q;
       if (valid) {
         q = S.boxes[pj];
@@ -274,12 +287,14 @@ __device__ __forceinline__ void visit_panels(const Scene3View& S, const Path3<K>
         const bool ov = valid & !L.empty & !sep_box & !sep_plane & (pj != P.lo[l]) & (pj != P.hi[l]);
         m[l] = ballot(ov);
         uni |= m[l];
+        if (mask_out && lane == 0) mask_out[l * S.mask_nb + bi] = m[l];
       }
     } else {
 #pragma unroll
       for (int l = 0; l <= K; ++l) {
         m[l] = ballot(valid & !B[l].empty & (pj != P.lo[l]) & (pj != P.hi[l]));
         uni |= m[l];
+        if (mask_out && lane == 0) mask_out[l * S.mask_nb + bi] = m[l];
       }
     }
     while (uni) {
@@ -291,7 +306,8 @@ __device__ __forceinline__ void visit_panels(const Scene3View& S, const Path3<K>
 }
 
 template <int K>
-__device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<K>& P, float V) {
+__device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<K>& P, float V,
+                                               uint64_t* mask_out = nullptr) {
   const bool act = P.F != 0.0f;
   LegBox3 B[K + 1];
   if (S.boxes) {
@@ -318,17 +334,17 @@ __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<
     }
     // once every lane's product is exactly 0 no further factor can change it
     return ballot(upd) == 0 || ballot(V != 0.0f) != 0;
-  });
+  }, mask_out);
   return V;
 }
 
 template <int K>
 __device__ __forceinline__ float path_power3(const Scene3View& S, const Cand& cd, float tx, float ty, float tz,
-                                             float rx, float ry, float rz, bool live) {
+                                             float rx, float ry, float rz, bool live, uint64_t* mask_out) {
   Path3<K> P;
   if (!setup3<K, true>(S, cd, tx, ty, tz, rx, ry, rz, live, P)) return 0.0f;
   if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all3<K>(S, P, P.F);
+  const float V = obstruct_all3<K>(S, P, P.F, mask_out);
   const float ex = rx - P.Ix[K], ey = ry - P.Iy[K], ez = rz - P.Iz[K];
   const float d2 = dot3(ex, ey, ez, ex, ey, ez);
   return V / fmaxf(d2, S.dmin2);
@@ -356,7 +372,8 @@ struct LaneGrad3 {
 // Reverse sweep of one path given Wl = g(r) c (= dL / dlog V at this lane).
 template <int K>
 __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K>& P, float Wl, float rx, float ry,
-                                              float rz, float* acc, int lane, LaneGrad3& G) {
+                                              float rz, float* acc, int lane, LaneGrad3& G,
+                                              const uint64_t* mask_in = nullptr) {
   const bool act = Wl != 0.0f;
   // gradients of the path points X_0 .. X_{K+1} and of the images
   float gXx[K + 2], gXy[K + 2], gXz[K + 2], gIx[K + 1], gIy[K + 1], gIz[K + 1];
@@ -366,8 +383,11 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
   for (int i = 0; i < K + 1; ++i) gIx[i] = gIy[i] = gIz[i] = 0.0f;
 
   // -- obstruction factors: d log q / d(ups, beta, gamma) = -L_x / num
+  // culling masks recorded by the forward, or boxes around the legs of the
+  // lanes with a nonzero W
   LegBox3 B[K + 1];
-  if (S.boxes) {
+  if (mask_in) {
+  } else if (S.boxes) {
     leg_boxes3<K>(P, act, S.cull_c, B);
   } else {
     const bool none = ballot(act) == 0;
@@ -425,7 +445,7 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
     }
     if (ballot(any) != 0) acc_panel(acc, j, g, lane);
     return true;
-  });
+  }, nullptr, mask_in);
 
   // -- image distance |r - I_K|^2 (zero gradient under the d_min floor)
   {
@@ -546,31 +566,37 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
 template <int K>
 __device__ __forceinline__ void path_adjoint3_known(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                     float tz, float rx, float ry, float rz, bool live, float Wl,
-                                                    float* acc, int lane, LaneGrad3& G) {
+                                                    float* acc, int lane, LaneGrad3& G, const uint64_t* mask_in) {
   Path3<K> P;
   setup3<K, false>(S, cd, tx, ty, tz, rx, ry, rz, live, P);
   P.F = Wl != 0.0f ? 1.0f : 0.0f;
-  path_adjoint3<K>(S, P, Wl, rx, ry, rz, acc, lane, G);
+  path_adjoint3<K>(S, P, Wl, rx, ry, rz, acc, lane, G, mask_in);
 }
 
+// Contribution of candidate cd at this lane; with mask_out, its culling masks
+// are kept there (see visit_panels).
 __device__ __forceinline__ float candidate_power3(const Scene3View& S, const Cand& cd, float tx, float ty,
-                                                  float tz, float rx, float ry, float rz, bool live) {
+                                                  float tz, float rx, float ry, float rz, bool live,
+                                                  uint64_t* mask_out = nullptr) {
   switch (cd.k) {
-    case 0: return path_power3<0>(S, cd, tx, ty, tz, rx, ry, rz, live);
-    case 1: return path_power3<1>(S, cd, tx, ty, tz, rx, ry, rz, live);
-    case 2: return path_power3<2>(S, cd, tx, ty, tz, rx, ry, rz, live);
-    default: return path_power3<3>(S, cd, tx, ty, tz, rx, ry, rz, live);
+    case 0: return path_power3<0>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    case 1: return path_power3<1>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    case 2: return path_power3<2>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    default: return path_power3<3>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
   }
 }
 
+// Adjoint of candidate cd given Wl = g(r) c; with mask_in, the culling masks
+// its forward recorded.
 __device__ __forceinline__ void candidate_adjoint3(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                    float tz, float rx, float ry, float rz, bool live, float Wl,
-                                                   float* acc, int lane, LaneGrad3& G) {
+                                                   float* acc, int lane, LaneGrad3& G,
+                                                   const uint64_t* mask_in = nullptr) {
   switch (cd.k) {
-    case 0: path_adjoint3_known<0>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
-    case 1: path_adjoint3_known<1>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
-    case 2: path_adjoint3_known<2>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
-    default: path_adjoint3_known<3>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G); break;
+    case 0: path_adjoint3_known<0>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    case 1: path_adjoint3_known<1>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    case 2: path_adjoint3_known<2>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    default: path_adjoint3_known<3>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
   }
 }
 

@@ -29,6 +29,9 @@ struct Trace3Args {
   int* cache_idx;          // [slots][cache_cap]
   int* cache_n;            // [slots], -1 when the list overflowed
   int cache_cap;
+  uint64_t* cache_mask;    // [slots][cache_cap][mask_stride] culling masks of each entry
+  int mask_stride;         // (max_order + 1) mask_nb <= 16
+  int mask_nb;             // 64-panel batches: ceil(n_panels / 64)
 };
 
 hipError_t launch_prep_panels(const float* panels, int n, float cull_c, PanelRec* out, PanelBox* boxes,

@@ -21,6 +21,7 @@ __device__ __forceinline__ Scene3View view3_of(const Trace3Args& A) {
   S.boxes = A.boxes;
   S.cull_c = A.cull_c;
   S.n_panels = A.n_panels;
+  S.mask_nb = A.mask_nb;
   S.alpha = A.alpha;
   S.a2 = A.a2;
   S.band_k = A.band_k;
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
                                                          float* __restrict__ seed, float* __restrict__ loss_part,
                                                          int loss_kind, float log_eps) {
   __shared__ float red[NW][2][kWave];
+  __shared__ uint64_t mrec[NW][16];  // culling masks of the candidate being evaluated
   const Scene3View S = view3_of(A);
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x >> 6);
@@ -109,12 +111,15 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   const float lim = 128.0f / A.a2 * 1.00001f;
   for_screened3(A.panels, A.n_panels, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box,
                 [&](int c, const Cand& cd) {
-                  const float v = candidate_power3(S, cd, tx, ty, tz, rx, ry, rz, live);
+                  const float v =
+                      candidate_power3(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr);
                   kahan_add(sum, comp, v);
                   if (cache_c && ballot(v != 0.0f) != 0) {
                     if (nst < A.cache_cap) {
                       cache_c[(size_t)nst * kWave + lane] = v;
                       if (lane == 0) cache_idx[nst] = c;
+                      if (lane < A.mask_stride)
+                        A.cache_mask[((size_t)slot * A.cache_cap + nst) * A.mask_stride + lane] = mrec[wave][lane];
                     }
                     ++nst;
                   }
@@ -175,7 +180,9 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         const float Wl = g * cache_c[(size_t)p * kWave + lane];
         if (ballot(Wl != 0.0f) == 0) continue;
         const Cand cd = decode_candidate(cache_idx[p], A.n_panels);
-        candidate_adjoint3(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
+        const uint64_t masks =
+            lane < A.mask_stride ? A.cache_mask[((size_t)slot * A.cache_cap + p) * A.mask_stride + lane] : 0;
+        candidate_adjoint3(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, &masks);
       }
     } else {
       for (int c = wave; c < A.n_cand; c += NW) {
