@@ -170,3 +170,26 @@ def test_panel_culling_changes_no_bit(alpha):
         tr.set_screen(True)
     for a, b in zip(on, off):
         assert torch.equal(a, b)
+
+
+def test_maximum_panel_count_sampled():
+    """DRT3_MAX_PANELS panels (room + 250 rectangles, four 64-panel batches in
+    the culling masks), order <= 1, a 16 x 16 grid: sampled receivers and a
+    sampled-loss gradient against the reference."""
+    tr = _tr3()
+    s = WL.scene3d_room(9, 250, 16, 1, 100.0, seed=77)
+    assert s.n_panels == 256
+    sc = _scene(s)
+    P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    idx = np.random.default_rng(3).choice(s.n_rx, 24, replace=False)
+    P_o, kap = kappa3(s.panels, s.tx, s.rx[idx], 1, 100.0)
+    PU.check_power(P.cpu().numpy()[idx], P_o, kap, "256 panels")
+    w = np.zeros(s.n_rx, np.float32)
+    w[idx[:12]] = 1.0
+    gtx, gp = tr.backward(sc, seed * _dev(w), reuse_forward=False)
+    gp_o, gt_o, _ = T3.vjp(s.panels, s.tx, s.rx[idx[:12]], 1, 100.0, seed.cpu().numpy()[idx[:12]])
+    PU.check_grads(gtx.cpu().numpy(), gp.cpu().numpy(), gt_o, gp_o, "256 panels")
+    # the adjoint from the recorded contributions and masks gives the same gradients
+    P2, L2, seed2 = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    g2 = tr.backward(sc, seed2 * _dev(w), reuse_forward=True)
+    assert torch.equal(g2[0], gtx) and torch.equal(g2[1], gp)
