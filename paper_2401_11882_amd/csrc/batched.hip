@@ -50,7 +50,7 @@ __device__ __forceinline__ int batch_rx_of_lane(int tile, int lane, int nx, int 
 }
 
 template <int NW, int MODE>
-__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batched(BatchArgs B) {
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_batched(BatchArgs B) {
   extern __shared__ float smem[];
   __shared__ int item_sh;
   __shared__ float gsh[kWave];
