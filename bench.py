@@ -29,13 +29,17 @@ PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (datasheet, counts packed i
 UNPACKED_FP32_TFLOPS = 78.6     # the same without packed FP32: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
 
 
+# The sources the single-scene 2D tracer kernels (k_forward, k_backward) are
+# built from: counter figures are valid only while these are unchanged.
+TRACER_SOURCES = ("dev.h", "path.h", "screen.h", "trace.h", "trace.hip")
+
+
 def source_hash() -> str:
-    """sha256 over the HIP sources; HBM traffic figures are valid for this hash only."""
-    import glob
+    """sha256 over the tracer kernels' HIP sources; counter figures are valid for this hash only."""
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2401_11882_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in TRACER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2401_11882_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
