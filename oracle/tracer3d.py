@@ -25,7 +25,8 @@ adjacent corners b and c), and every step keeps its 2D meaning:
   with identity coefficient); gradients by torch autograd.
 
 Smoothing modes: "sigmoid" (Eq. 3-4, products formed as exp of summed
-logsigmoids and 1 - exp(z) as -expm1(z)) and "hard" (the unit step of
+logsigmoids and 1 - exp(z) as -expm1(z)), "hard_sigmoid" (Eq. 5-6,
+relu6(alpha x + 3) / 6, products as written) and "hard" (the unit step of
 Eq. 1).  Degenerate cases as in 2D: a zero-area panel gives 0 and never
 blocks; a back-trace parallel to a plane gives 0; a leg parallel to a plane
 gives the factor 1.
@@ -37,6 +38,7 @@ import torch
 import torch.nn.functional as F
 
 from .tracer import candidates  # the candidate enumeration is dimension-free (Sec. IV)
+from .tracer import hard_sigmoid  # Eq. 5-6
 
 DTYPE = torch.float64
 DEFAULT_DMIN = 1e-3
@@ -55,6 +57,11 @@ def _log_inside(x, alpha):
 
 def _hard_inside(x):
     return ((x > 0) & (x < 1)).to(DTYPE)
+
+
+def _hs_inside(x, alpha):
+    """hard sigmoid(x) * hard sigmoid(1 - x) (Eq. 5-6): the check 0 < x < 1."""
+    return hard_sigmoid(x, alpha) * hard_sigmoid(1.0 - x, alpha)
 
 
 def _dot(u, v):
@@ -113,6 +120,8 @@ def _group_terms(panels, tx, rxc, seq, alpha, mode, d_min, want_paths=False):
         beta, gamma = _panel_coords(X[i] - A, E1, E2, N, NN)
         if mode == "sigmoid":
             log_f = log_f + _log_inside(beta, alpha) + _log_inside(gamma, alpha) + _log_inside(u, alpha)
+        elif mode == "hard_sigmoid":
+            f_hard = f_hard * _hs_inside(beta, alpha) * _hs_inside(gamma, alpha) * _hs_inside(u, alpha)
         else:
             f_hard = f_hard * _hard_inside(beta) * _hard_inside(gamma) * _hard_inside(u)
         params[i] = (beta, gamma, u)
@@ -138,6 +147,8 @@ def _group_terms(panels, tx, rxc, seq, alpha, mode, d_min, want_paths=False):
                                     nn_s[None, None])
         if mode == "sigmoid":
             q = -torch.expm1(_log_inside(ups, alpha) + _log_inside(beta, alpha) + _log_inside(gamma, alpha))
+        elif mode == "hard_sigmoid":
+            q = 1.0 - _hs_inside(ups, alpha) * _hs_inside(beta, alpha) * _hs_inside(gamma, alpha)
         else:
             q = 1.0 - _hard_inside(ups) * _hard_inside(beta) * _hard_inside(gamma)
         q = torch.where(use, q, torch.ones_like(q))

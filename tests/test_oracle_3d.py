@@ -122,3 +122,68 @@ def test_degenerate_panels():
     rx = np.array([[0.8, 0.5, 0.3]])
     P = T3.power(flat, tx, rx, 1, 100.0)
     assert P[0] == pytest.approx(1.0 / 0.36, rel=1e-12)
+
+
+# --- hard-sigmoid smoothing (Eq. 5-6) in 3D ---------------------------------
+
+HS = "hard_sigmoid"
+
+
+@pytest.mark.parametrize("K", [0, 1, 2])
+def test_hard_sigmoid_extruded_matches_2d(K):
+    """At half height the vertical panel coordinate is 1/2, where
+    hs(alpha / 2)^2 = 1 exactly for alpha >= 6: the 2D hard-sigmoid reference."""
+    s = WL.scene_random_box(2, 5, 6, K, 30.0, seed=60 + K)
+    e = WL.extrude(s)
+    P2 = T2.power(s.walls, s.tx, s.rx, K, 30.0, mode=HS)
+    P3 = T3.power(e.panels, e.tx, e.rx, K, 30.0, mode=HS)
+    np.testing.assert_allclose(P3, P2, rtol=1e-12, atol=1e-300)
+
+
+def test_hard_sigmoid_blocked_and_partial_closed_forms():
+    alpha = 50.0
+    tx = np.array([0.2, 0.5, 0.5])
+    rx = np.array([[0.8, 0.5, 0.5]])
+    d2 = 0.36
+    # a square panel x = 0.5 centred on the line of sight: in(.) = 1 for every coordinate, factor exactly 0
+    centred = np.array([[0.5, 0.25, 0.25, 0.5, 0.75, 0.25, 0.5, 0.25, 0.75]])
+    assert T3.power(centred, tx, rx, 0, alpha, mode=HS)[0] == 0.0
+    # the same panel shifted so that the crossing has beta = -1/alpha: in(beta) = hs(-1) = 1/3, factor 2/3
+    shifted = centred.copy()
+    shifted[0, 1::3] += 0.25 + 0.5 / alpha   # y of a, b, c: beta = (0.5 - y_a) / 0.5 = -1/alpha
+    P = T3.power(shifted, tx, rx, 0, alpha, mode=HS)[0]
+    assert P == pytest.approx((2.0 / 3.0) / d2, rel=1e-12)
+
+
+def test_hard_sigmoid_large_alpha_tends_to_unit_step():
+    s = WL.scene3d_room(8, 3, 6, 2, 100.0, seed=5)
+    Ph = T3.power(s.panels, s.tx, s.rx, 2, 1.0, mode="hard")
+    P = T3.power(s.panels, s.tx, s.rx, 2, 1e9, mode=HS)
+    rel = np.abs(P - Ph) / np.maximum(Ph, 1e-300)
+    assert np.mean(rel < 1e-9) > 0.95
+
+
+@pytest.mark.parametrize("alpha", [20.0, 50.0])
+def test_hard_sigmoid_autograd_matches_central_differences(alpha):
+    s = WL.scene3d_room(8, 3, 2, 1, alpha, seed=12)
+    g = np.ones(s.n_rx)
+    gp, gt, _ = T3.vjp(s.panels, s.tx, s.rx, 1, alpha, g, mode=HS)
+
+    def f(pan, tx):
+        return T3.power(pan, tx, s.rx, 1, alpha, mode=HS).sum()
+
+    h = 1e-7   # piecewise linear factors: exact away from the kinks
+    tx = s.tx.astype(np.float64)
+    for c in range(3):
+        tp, tm = tx.copy(), tx.copy()
+        tp[c] += h
+        tm[c] -= h
+        fd = (f(s.panels, tp) - f(s.panels, tm)) / (2 * h)
+        assert gt[c] == pytest.approx(fd, rel=1e-5, abs=1e-7 * np.abs(gt).max())
+    pan = s.panels.astype(np.float64)
+    for j, c in [(6, 0), (7, 4), (8, 8), (2, 1), (0, 2)]:
+        pp, pm = pan.copy(), pan.copy()
+        pp[j, c] += h
+        pm[j, c] -= h
+        fd = (f(pp, tx) - f(pm, tx)) / (2 * h)
+        assert gp[j, c] == pytest.approx(fd, rel=1e-5, abs=1e-7 * np.abs(gp).max())
