@@ -228,7 +228,7 @@ def extra_surrogate():
             "heldout_rmse": round(r["heldout_rmse"], 4), "target_std": round(r["target_std"], 4)}
 
 
-def extra_3d(dev, steps: int = 10):
+def extra_3d(dev, steps: int = 10, smoothing: str = "sigmoid"):
     """Sec. V: the method in three dimensions.  Room (6 panels) + 32 random
     rectangles, 256^2 receivers at mid-height, order <= 2 (1,445 panel
     sequences), alpha = 100: forward, then the adjoint from the recorded
@@ -240,7 +240,7 @@ def extra_3d(dev, steps: int = 10):
     from paper_2401_11882_amd import workloads as WL
     s = WL.scene3d_32()
     pan, tx, rx = (torch.tensor(a, device=dev) for a in (s.panels, s.tx, s.rx))
-    sc = tr3.Scene3(pan, tx, rx, s.max_order, s.alpha, grid_nx=s.grid_n)
+    sc = tr3.Scene3(pan, tx, rx, s.max_order, s.alpha, grid_nx=s.grid_n, smoothing=smoothing)
     n_cand = 1 + s.n_panels + s.n_panels * (s.n_panels - 1)
 
     def step():
@@ -267,6 +267,10 @@ def extra_3d(dev, steps: int = 10):
                        "fwd + adjoint w.r.t. tx and all panel corners",
            "ms_per_step": round(ms, 4), "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
            "value": s.n_rx * n_cand / (ms * 1e-3), "unit": "path-evals/s"}
+    if smoothing != "sigmoid":
+        return out
+    out["hard_sigmoid"] = extra_3d(dev, steps, smoothing="hard_sigmoid")
+    out["hard_over_sigmoid_speed"] = round(out["ms_per_step"] / out["hard_sigmoid"]["ms_per_step"], 3)
     wm_path = os.path.join(ROOT, "bench_work_model.json")
     if os.path.exists(wm_path):
         with open(wm_path) as f:

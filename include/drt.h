@@ -382,7 +382,7 @@ int drt_valu_peak(double* fma_tflops, double* exp_tlanes);
  * (beta_i, gamma_i); an interaction's factor is in(beta) in(gamma) in(u);
  * panel j obstructs a leg with 1 - in(upsilon) in(beta) in(gamma), upsilon
  * the leg parameter of the plane crossing and (beta, gamma) its panel
- * coordinates (Sec. IV-A with Eq. 3-4, sigmoid smoothing only).  A panel of
+ * coordinates (Sec. IV-A with Eq. 3-4, or the hard sigmoid of Eq. 5-6).  A panel of
  * zero area contributes no path and never obstructs; a back-trace parallel
  * to a plane gives no path; a leg parallel to a plane is not obstructed by
  * it.  Power, losses, error handling, determinism, graph capture and the
@@ -402,7 +402,7 @@ typedef struct drt3_scene {
   int32_t rx_grid_nx;       /* as drt_scene.rx_grid_nx */
   int32_t max_order;        /* K, 0 .. DRT_MAX_ORDER */
   float alpha;              /* finite and > 0 */
-  int32_t smoothing;        /* DRT_SIGMOID (others: DRT_ENOTSUP) */
+  int32_t smoothing;        /* drt_smoothing */
   float d_min;              /* finite and > 0 */
 } drt3_scene;
 

@@ -67,7 +67,8 @@ int check_scene3(const drt3_scene* s) {
     return failf(DRT_EINVAL, "max_order=%d outside [0, %d]", s->max_order, DRT_MAX_ORDER);
   if (!std::isfinite(s->alpha) || !(s->alpha > 0.0f)) return failf(DRT_EINVAL, "alpha must be finite and > 0");
   if (!std::isfinite(s->d_min) || !(s->d_min > 0.0f)) return failf(DRT_EINVAL, "d_min must be finite and > 0");
-  if (s->smoothing != DRT_SIGMOID) return failf(DRT_ENOTSUP, "smoothing=%d not supported in 3D", s->smoothing);
+  if (s->smoothing != DRT_SIGMOID && s->smoothing != DRT_HARD_SIGMOID)
+    return failf(DRT_ENOTSUP, "smoothing=%d not supported", s->smoothing);
   if (s->rx_grid_nx != 0) {
     const int nx = s->rx_grid_nx;
     if (nx < 0 || nx % 8 != 0 || s->n_rx % (8 * nx) != 0)
@@ -132,7 +133,9 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   char* w = static_cast<char*>(ws);
   A.panels = reinterpret_cast<const drt::PanelRec*>(w + p.off_panels);
   A.boxes = drt_internal_screen() ? reinterpret_cast<const drt::PanelBox*>(w + p.off_boxes) : nullptr;
-  A.cull_c = drt::kCullMargin / s->alpha;
+  const bool hard = s->smoothing == DRT_HARD_SIGMOID;
+  A.mode = hard ? 1 : 0;
+  A.cull_c = (hard ? drt::kHardCullMargin : drt::kCullMargin) / s->alpha;
   A.screen = drt_internal_screen();
   A.tx = s->tx_dev;
   A.rx = s->rx_dev;
@@ -142,7 +145,7 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   A.n_cand = (int)count_candidates(s->n_panels, s->max_order);
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
-  A.band_k = 1.0f + 2.0f * drt::kBandMargin / s->alpha;
+  A.band_k = 1.0f + 2.0f * (hard ? drt::kHardBandMargin : drt::kBandMargin) / s->alpha;
   A.dmin2 = s->d_min * s->d_min;
   if (p.cache_cap > 0) {
     A.cache_c = reinterpret_cast<float*>(w + p.off_cache_c);
@@ -173,7 +176,8 @@ int check_loss3(int32_t loss_kind, float log_eps) {
 
 int prep3(const drt3_scene* s, const Plan3& p, void* ws, hipStream_t st) {
   char* w = static_cast<char*>(ws);
-  hipError_t e = drt::launch_prep_panels(s->panels_dev, s->n_panels, drt::kCullMargin / s->alpha,
+  const float cull_c = (s->smoothing == DRT_HARD_SIGMOID ? drt::kHardCullMargin : drt::kCullMargin) / s->alpha;
+  hipError_t e = drt::launch_prep_panels(s->panels_dev, s->n_panels, cull_c,
                                          reinterpret_cast<drt::PanelRec*>(w + p.off_panels),
                                          reinterpret_cast<drt::PanelBox*>(w + p.off_boxes), st);
   return e == hipSuccess ? DRT_OK : hip_fail(e, "prep_panels launch");

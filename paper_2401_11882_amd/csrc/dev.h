@@ -85,6 +85,13 @@ __device__ __forceinline__ float uniformf(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
+// Smoothing of the comparisons (Sec. III-B): sigmoid (Eq. 4) or hard sigmoid
+// (Eq. 5-6, relu6(alpha x + 3) / 6 = clamp(x alpha / 6 + 1/2, 0, 1)).
+constexpr int kSigmoid = 0;
+constexpr int kHardSigmoid = 1;
+
+__device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
 // Lane l's 64-bit value (l wave-uniform).
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);

@@ -31,12 +31,6 @@ struct SceneView {
   float a6, a6h, a6m;  // hard sigmoid: alpha / 6, alpha / 6 + 1/2, 1/2 - alpha / 6
 };
 
-// Smoothing of the comparisons (Sec. III-B): sigmoid (Eq. 4) or hard sigmoid
-// (Eq. 5-6, relu6(alpha x + 3) / 6 = clamp(x alpha / 6 + 1/2, 0, 1)).
-constexpr int kSigmoid = 0;
-constexpr int kHardSigmoid = 1;
-
-__device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
 template <int K>
 struct Path {

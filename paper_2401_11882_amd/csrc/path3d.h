@@ -67,7 +67,34 @@ struct Scene3View {
   int n_panels;
   int mask_nb;            // 64-panel batches per leg in a recorded culling mask
   float alpha, a2, band_k, dmin2, cull_c;
+  float a6, a6h, a6m;     // hard sigmoid: alpha / 6, alpha / 6 + 1/2, 1/2 - alpha / 6
 };
+
+// Hard sigmoid (Eq. 5-6): in(x) = hs(alpha x) hs(alpha (1 - x)) with
+// hs(z) = clamp(z / 6 + 1/2, 0, 1); h1 = hs(alpha x), h2 = hs(alpha (1 - x)).
+struct HardIn {
+  float h1, h2, in, n;  // n = 1 - in = (1 - h1) + h1 (1 - h2), a sum of nonnegative terms
+};
+
+__device__ __forceinline__ HardIn hard_in(const Scene3View& S, float x) {
+  HardIn r;
+  r.h1 = med01(fmaf(S.a6, x, 0.5f));
+  r.h2 = med01(fmaf(-S.a6, x, S.a6h));
+  r.in = r.h1 * r.h2;
+  r.n = fmaf(r.h1, med01(fmaf(S.a6, x, S.a6m)), med01(fmaf(-S.a6, x, 0.5f)));
+  return r;
+}
+
+// d in(x) / dx divided by alpha / 6: h2 where hs(alpha x) is on its ramp,
+// minus h1 where hs(alpha (1 - x)) is (0 on the flat parts; the kinks take 0).
+__device__ __forceinline__ float ramp3(const HardIn& r) {
+  return (((r.h1 > 0.0f) & (r.h1 < 1.0f)) ? r.h2 : 0.0f) - (((r.h2 > 0.0f) & (r.h2 < 1.0f)) ? r.h1 : 0.0f);
+}
+
+// d log in(x) / dx divided by alpha / 6 (on the ramps, where in(x) > 0).
+__device__ __forceinline__ float dlog_ramp3(const HardIn& r) {
+  return (((r.h1 > 0.0f) & (r.h1 < 1.0f)) ? rcp(r.h1) : 0.0f) - (((r.h2 > 0.0f) & (r.h2 < 1.0f)) ? rcp(r.h2) : 0.0f);
+}
 
 // Wave-uniform axis-aligned box around the extended legs
 // [X_l - c D, X_{l+1} + c D] of the active lanes.  A panel whose extended box
@@ -102,7 +129,7 @@ __device__ __forceinline__ float dlog_in(float x, float alpha, float a2) {
 
 // Images, back-trace and (if WANT_F) the interaction factors; with WANT_F,
 // false as soon as every lane's factor is exactly 0.
-template <int K, bool WANT_F>
+template <int K, bool WANT_F, int MODE>
 __device__ __forceinline__ bool setup3(const Scene3View& S, const Cand& cd, float tx, float ty, float tz,
                                        float rx, float ry, float rz, bool live, Path3<K>& P) {
   const int sv[3] = {cd.s0, cd.s1, cd.s2};
@@ -155,7 +182,15 @@ __device__ __forceinline__ bool setup3(const Scene3View& S, const Cand& cd, floa
     P.dx[i - 1] = dx;
     P.dy[i - 1] = dy;
     P.dz[i - 1] = dz;
-    if (WANT_F) {
+    if constexpr (WANT_F && MODE == kHardSigmoid) {
+      // exactly 0 beyond 3 / alpha outside [0, 1]
+      F = good ? F : 0.0f;
+      F *= (hard_in(S, be).in * hard_in(S, ga).in) * hard_in(S, u).in;
+      if (ballot(F != 0.0f) == 0) {
+        P.F = 0.0f;
+        return false;
+      }
+    } else if constexpr (WANT_F) {
       F = good ? F : 0.0f;
       const float z1 = -S.a2 * be, z2 = fmaf(S.a2, be, -S.a2);
       const float z3 = -S.a2 * ga, z4 = fmaf(S.a2, ga, -S.a2);
@@ -183,11 +218,12 @@ __device__ __forceinline__ float n_of(float x, float a2) {
 }
 
 struct Obs3 {
-  float ups, be, ga, inv, qx, qy, qz, num;
+  float ups, be, ga, inv, qx, qy, qz, num;  // num: sigmoid num; hard sigmoid: the factor q itself
 };
 
 // Obstruction test of leg (X, D) by panel w: false if every lane's factor is
 // 1.0f (a parameter more than band outside [0, 1]); the leg parameter first.
+template <int MODE>
 __device__ __forceinline__ bool obs3(const Scene3View& S, const PanelRec& w, float Xx, float Xy, float Xz, float Dx,
                                      float Dy, float Dz, bool act, Obs3& o, bool& in_band) {
   const float den = dot3(Dx, Dy, Dz, w.nx, w.ny, w.nz);
@@ -206,12 +242,18 @@ __device__ __forceinline__ bool obs3(const Scene3View& S, const PanelRec& w, flo
   it = it && (fabsf(fmaf(2.0f, o.be, -1.0f)) < S.band_k) && (fabsf(fmaf(2.0f, o.ga, -1.0f)) < S.band_k);
   if (ballot(it) == 0) return false;
   in_band = it;
-  if (it) {
-    const float nu = n_of(o.ups, S.a2), nb = n_of(o.be, S.a2), ng = n_of(o.ga, S.a2);
-    const float t = fmaf(nu, nb, nu + nb);
-    o.num = fmaf(t, ng, t + ng);
+  if constexpr (MODE == kHardSigmoid) {
+    // q = 1 - in_u in_b in_g = n_u + in_u (n_b + in_b n_g): nonnegative terms
+    const HardIn u = hard_in(S, o.ups), b = hard_in(S, o.be), g = hard_in(S, o.ga);
+    o.num = it ? fmaf(u.in, fmaf(b.in, g.n, b.n), u.n) : 1.0f;
   } else {
-    o.num = kBig;
+    if (it) {
+      const float nu = n_of(o.ups, S.a2), nb = n_of(o.be, S.a2), ng = n_of(o.ga, S.a2);
+      const float t = fmaf(nu, nb, nu + nb);
+      o.num = fmaf(t, ng, t + ng);
+    } else {
+      o.num = kBig;
+    }
   }
   return true;
 }
@@ -305,7 +347,7 @@ __device__ __forceinline__ void visit_panels(const Scene3View& S, const Path3<K>
   }
 }
 
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<K>& P, float V,
                                                uint64_t* mask_out = nullptr) {
   const bool act = P.F != 0.0f;
@@ -326,9 +368,10 @@ __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<
       const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
       Obs3 o;
       bool ib;
-      if (!obs3(S, w, P.Xx[l], P.Xy[l], P.Xz[l], Dx, Dy, Dz, act, o, ib)) continue;
+      if (!obs3<MODE>(S, w, P.Xx[l], P.Xy[l], P.Xz[l], Dx, Dy, Dz, act, o, ib)) continue;
       if (ib) {
-        V *= o.num * rcp(1.0f + o.num);
+        if constexpr (MODE == kHardSigmoid) V *= o.num;
+        else V *= o.num * rcp(1.0f + o.num);
         upd = true;
       }
     }
@@ -338,13 +381,13 @@ __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<
   return V;
 }
 
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ float path_power3(const Scene3View& S, const Cand& cd, float tx, float ty, float tz,
                                              float rx, float ry, float rz, bool live, uint64_t* mask_out) {
   Path3<K> P;
-  if (!setup3<K, true>(S, cd, tx, ty, tz, rx, ry, rz, live, P)) return 0.0f;
+  if (!setup3<K, true, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, P)) return 0.0f;
   if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all3<K>(S, P, P.F, mask_out);
+  const float V = obstruct_all3<K, MODE>(S, P, P.F, mask_out);
   const float ex = rx - P.Ix[K], ey = ry - P.Iy[K], ez = rz - P.Iz[K];
   const float d2 = dot3(ex, ey, ez, ex, ey, ez);
   return V / fmaxf(d2, S.dmin2);
@@ -370,7 +413,7 @@ struct LaneGrad3 {
 };
 
 // Reverse sweep of one path given Wl = g(r) c (= dL / dlog V at this lane).
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K>& P, float Wl, float rx, float ry,
                                               float rz, float* acc, int lane, LaneGrad3& G,
                                               const uint64_t* mask_in = nullptr) {
@@ -406,12 +449,22 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
       const float Dx = P.Xx[l + 1] - P.Xx[l], Dy = P.Xy[l + 1] - P.Xy[l], Dz = P.Xz[l + 1] - P.Xz[l];
       Obs3 o;
       bool ib;
-      if (!obs3(S, w, P.Xx[l], P.Xy[l], P.Xz[l], Dx, Dy, Dz, act, o, ib)) continue;
+      if (!obs3<MODE>(S, w, P.Xx[l], P.Xy[l], P.Xz[l], Dx, Dy, Dz, act, o, ib)) continue;
       if (!ib) continue;
-      const float c = -Wl * rcp(o.num);
-      const float gu = c * dlog_in(o.ups, S.alpha, S.a2);
-      const float gb = c * dlog_in(o.be, S.alpha, S.a2);
-      const float gg = c * dlog_in(o.ga, S.alpha, S.a2);
+      float gu, gb, gg;  // Wl d log q / d(ups, beta, gamma)
+      if constexpr (MODE == kHardSigmoid) {
+        // q = 1 - in_u in_b in_g, dq/dx_u = -in'_u in_b in_g (likewise)
+        const HardIn hu = hard_in(S, o.ups), hb = hard_in(S, o.be), hg = hard_in(S, o.ga);
+        const float c = o.num > 0.0f ? -S.a6 * Wl * rcp(o.num) : 0.0f;
+        gu = c * ramp3(hu) * (hb.in * hg.in);
+        gb = c * ramp3(hb) * (hu.in * hg.in);
+        gg = c * ramp3(hg) * (hu.in * hb.in);
+      } else {
+        const float c = -Wl * rcp(o.num);
+        gu = c * dlog_in(o.ups, S.alpha, S.a2);
+        gb = c * dlog_in(o.be, S.alpha, S.a2);
+        gg = c * dlog_in(o.ga, S.alpha, S.a2);
+      }
       // beta = q . m1, gamma = q . m2, q = X + ups D - a
       const float gqx = fmaf(gb, w.m1x, gg * w.m2x), gqy = fmaf(gb, w.m1y, gg * w.m2y),
                   gqz = fmaf(gb, w.m1z, gg * w.m2z);
@@ -465,9 +518,17 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
     const PanelRec w = load_panel(S.panels, P.s[i - 1]);
     const float u = P.u[i - 1], inv = P.inv[i - 1];
     const float dx = P.dx[i - 1], dy = P.dy[i - 1], dz = P.dz[i - 1];
-    const float gb = Wl * dlog_in(P.be[i - 1], S.alpha, S.a2);
-    const float gg = Wl * dlog_in(P.ga[i - 1], S.alpha, S.a2);
-    const float gu = Wl * dlog_in(u, S.alpha, S.a2);
+    float gb, gg, gu;  // Wl d log in / d(beta, gamma, u)
+    if constexpr (MODE == kHardSigmoid) {
+      const float aw = S.a6 * Wl;
+      gb = aw * dlog_ramp3(hard_in(S, P.be[i - 1]));
+      gg = aw * dlog_ramp3(hard_in(S, P.ga[i - 1]));
+      gu = aw * dlog_ramp3(hard_in(S, u));
+    } else {
+      gb = Wl * dlog_in(P.be[i - 1], S.alpha, S.a2);
+      gg = Wl * dlog_in(P.ga[i - 1], S.alpha, S.a2);
+      gu = Wl * dlog_in(u, S.alpha, S.a2);
+    }
     float g[kPanelGrad];
 #pragma unroll
     for (int f = 0; f < kPanelGrad; ++f) g[f] = 0.0f;
@@ -563,40 +624,42 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
   }
 }
 
-template <int K>
+template <int K, int MODE>
 __device__ __forceinline__ void path_adjoint3_known(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                     float tz, float rx, float ry, float rz, bool live, float Wl,
                                                     float* acc, int lane, LaneGrad3& G, const uint64_t* mask_in) {
   Path3<K> P;
-  setup3<K, false>(S, cd, tx, ty, tz, rx, ry, rz, live, P);
+  setup3<K, false, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, P);
   P.F = Wl != 0.0f ? 1.0f : 0.0f;
-  path_adjoint3<K>(S, P, Wl, rx, ry, rz, acc, lane, G, mask_in);
+  path_adjoint3<K, MODE>(S, P, Wl, rx, ry, rz, acc, lane, G, mask_in);
 }
 
 // Contribution of candidate cd at this lane; with mask_out, its culling masks
 // are kept there (see visit_panels).
+template <int MODE>
 __device__ __forceinline__ float candidate_power3(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                   float tz, float rx, float ry, float rz, bool live,
                                                   uint64_t* mask_out = nullptr) {
   switch (cd.k) {
-    case 0: return path_power3<0>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
-    case 1: return path_power3<1>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
-    case 2: return path_power3<2>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
-    default: return path_power3<3>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    case 0: return path_power3<0, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    case 1: return path_power3<1, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    case 2: return path_power3<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    default: return path_power3<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
   }
 }
 
 // Adjoint of candidate cd given Wl = g(r) c; with mask_in, the culling masks
 // its forward recorded.
+template <int MODE>
 __device__ __forceinline__ void candidate_adjoint3(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                    float tz, float rx, float ry, float rz, bool live, float Wl,
                                                    float* acc, int lane, LaneGrad3& G,
                                                    const uint64_t* mask_in = nullptr) {
   switch (cd.k) {
-    case 0: path_adjoint3_known<0>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
-    case 1: path_adjoint3_known<1>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
-    case 2: path_adjoint3_known<2>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
-    default: path_adjoint3_known<3>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    case 0: path_adjoint3_known<0, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    case 1: path_adjoint3_known<1, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    case 2: path_adjoint3_known<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    default: path_adjoint3_known<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
   }
 }
 

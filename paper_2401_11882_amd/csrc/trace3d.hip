@@ -26,6 +26,9 @@ __device__ __forceinline__ Scene3View view3_of(const Trace3Args& A) {
   S.a2 = A.a2;
   S.band_k = A.band_k;
   S.dmin2 = A.dmin2;
+  S.a6 = A.alpha * (1.0f / 6.0f);
+  S.a6h = S.a6 + 0.5f;
+  S.a6m = 0.5f - S.a6;
   return S;
 }
 
@@ -88,7 +91,7 @@ __global__ void k_prep_panels(const float* __restrict__ pan, int n, float cull_c
   boxes[j] = q;
 }
 
-template <int NW>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_forward3(Trace3Args A, float* __restrict__ power,
                                                          float* __restrict__ seed, float* __restrict__ loss_part,
                                                          int loss_kind, float log_eps) {
@@ -108,11 +111,12 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   int nst = 0;
   float sum = 0.0f, comp = 0.0f;
   const RxBox3 box = rx_box3(rx, ry, rz, live);
-  const float lim = 128.0f / A.a2 * 1.00001f;
+  // parameter range beyond which an interaction factor is exactly 0
+  const float lim = (MODE == kHardSigmoid ? kHardBandMargin / A.alpha : 128.0f / A.a2) * 1.00001f;
   for_screened3(A.panels, A.n_panels, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box,
                 [&](int c, const Cand& cd) {
                   const float v =
-                      candidate_power3(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr);
+                      candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr);
                   kahan_add(sum, comp, v);
                   if (cache_c && ballot(v != 0.0f) != 0) {
                     if (nst < A.cache_cap) {
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   }
 }
 
-template <int NW>
+template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_backward3(Trace3Args A, const float* __restrict__ gP,
                                                           float* __restrict__ part, int reuse) {
   extern __shared__ float smem3[];
@@ -182,15 +186,15 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         const Cand cd = decode_candidate(cache_idx[p], A.n_panels);
         const uint64_t masks =
             lane < A.mask_stride ? A.cache_mask[((size_t)slot * A.cache_cap + p) * A.mask_stride + lane] : 0;
-        candidate_adjoint3(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, &masks);
+        candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, &masks);
       }
     } else {
       for (int c = wave; c < A.n_cand; c += NW) {
         const Cand cd = decode_candidate(c, A.n_panels);
-        const float v = candidate_power3(S, cd, tx, ty, tz, rx, ry, rz, live);
+        const float v = candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live);
         const float Wl = g * v;
         if (ballot(Wl != 0.0f) == 0) continue;
-        candidate_adjoint3(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
+        candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
       }
     }
   }
@@ -274,10 +278,10 @@ hipError_t launch_prep_panels(const float* panels, int n, float cull_c, PanelRec
   return hipGetLastError();
 }
 
-template <int NW>
+template <int NW, int MODE>
 static hipError_t fwd3_nw(const Trace3Args& A, int n_tiles, float* power, float* seed, float* loss_part,
                           int loss_kind, float log_eps, hipStream_t st) {
-  hipLaunchKernelGGL((k_forward3<NW>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part, loss_kind,
+  hipLaunchKernelGGL((k_forward3<NW, MODE>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part, loss_kind,
                      log_eps);
   return hipGetLastError();
 }
@@ -285,10 +289,14 @@ static hipError_t fwd3_nw(const Trace3Args& A, int n_tiles, float* power, float*
 hipError_t launch_forward3(const Trace3Args& A, int n_tiles, int nw, float* power, float* seed, float* loss_part,
                            int loss_kind, float log_eps, hipStream_t st) {
   switch (nw) {
-    case 2: return fwd3_nw<2>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
-    case 4: return fwd3_nw<4>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
-    case 8: return fwd3_nw<8>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
-    case 16: return fwd3_nw<16>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
+    case 2: return A.mode ? fwd3_nw<2, kHardSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st)
+                     : fwd3_nw<2, kSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
+    case 4: return A.mode ? fwd3_nw<4, kHardSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st)
+                     : fwd3_nw<4, kSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
+    case 8: return A.mode ? fwd3_nw<8, kHardSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st)
+                     : fwd3_nw<8, kSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
+    case 16: return A.mode ? fwd3_nw<16, kHardSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st)
+                     : fwd3_nw<16, kSigmoid>(A, n_tiles, power, seed, loss_part, loss_kind, log_eps, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -297,9 +305,9 @@ size_t backward3_lds_bytes(int nw, int n_panels) {
   return sizeof(float) * (size_t)nw * (3 + kPanelGrad * (size_t)n_panels);
 }
 
-template <int NW>
+template <int NW, int MODE>
 static hipError_t bwd3_nw(const Trace3Args& A, int n_tiles, const float* gP, float* part, int reuse, hipStream_t st) {
-  hipLaunchKernelGGL((k_backward3<NW>), dim3(n_tiles), dim3(NW * kWave), backward3_lds_bytes(NW, A.n_panels), st, A,
+  hipLaunchKernelGGL((k_backward3<NW, MODE>), dim3(n_tiles), dim3(NW * kWave), backward3_lds_bytes(NW, A.n_panels), st, A,
                      gP, part, reuse);
   return hipGetLastError();
 }
@@ -307,10 +315,14 @@ static hipError_t bwd3_nw(const Trace3Args& A, int n_tiles, const float* gP, flo
 hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, int reuse,
                             hipStream_t st) {
   switch (nw) {
-    case 2: return bwd3_nw<2>(A, n_tiles, gP, part, reuse, st);
-    case 4: return bwd3_nw<4>(A, n_tiles, gP, part, reuse, st);
-    case 8: return bwd3_nw<8>(A, n_tiles, gP, part, reuse, st);
-    case 16: return bwd3_nw<16>(A, n_tiles, gP, part, reuse, st);
+    case 2: return A.mode ? bwd3_nw<2, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
+                     : bwd3_nw<2, kSigmoid>(A, n_tiles, gP, part, reuse, st);
+    case 4: return A.mode ? bwd3_nw<4, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
+                     : bwd3_nw<4, kSigmoid>(A, n_tiles, gP, part, reuse, st);
+    case 8: return A.mode ? bwd3_nw<8, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
+                     : bwd3_nw<8, kSigmoid>(A, n_tiles, gP, part, reuse, st);
+    case 16: return A.mode ? bwd3_nw<16, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
+                     : bwd3_nw<16, kSigmoid>(A, n_tiles, gP, part, reuse, st);
     default: return hipErrorInvalidValue;
   }
 }

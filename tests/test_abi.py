@@ -172,7 +172,7 @@ def _scene3(**kw):
     ("n_panels", 257, _lib.DRT_EINVAL),
     ("n_rx", -1, _lib.DRT_EINVAL),
     ("rx_grid_nx", 12, _lib.DRT_EINVAL),
-    ("smoothing", 1, _lib.DRT_ENOTSUP),
+    ("smoothing", 2, _lib.DRT_ENOTSUP),
     ("panels_dev", None, _lib.DRT_EINVAL),
     ("tx_dev", None, _lib.DRT_EINVAL),
     ("rx_dev", None, _lib.DRT_EINVAL),

@@ -225,3 +225,69 @@ def test_graph_capture_replay_matches_eager():
         want = tr.forward_backward(sc, loss="neg_mean_log")
         for a, b in zip(got, want):
             assert torch.equal(a, b), f"replay {i}"
+
+
+# --- hard-sigmoid smoothing (Eq. 5-6) ---------------------------------------
+
+def _scene_hs(s, alpha):
+    return _tr3().Scene3(_dev(s.panels), _dev(s.tx), _dev(s.rx), s.max_order, alpha, grid_nx=s.grid_n,
+                         smoothing="hard_sigmoid")
+
+
+def kappa3_hs(panels, tx, rx, K, alpha, runs=4, seed=0):
+    rng = np.random.default_rng(seed)
+    P0 = T3.power(panels, tx, rx, K, alpha, mode="hard_sigmoid")
+    kap = np.zeros_like(P0)
+    for _ in range(runs):
+        P = T3.power(PU.perturb(panels, rng), PU.perturb(tx, rng), PU.perturb(rx, rng), K, alpha,
+                     mode="hard_sigmoid")
+        kap = np.maximum(kap, np.abs(P - P0))
+    return P0, kap
+
+
+@pytest.mark.parametrize("K", [0, 1, 2, 3])
+@pytest.mark.parametrize("alpha", [10.0, 50.0])
+def test_hard_sigmoid_room_scenes_all_orders(K, alpha):
+    tr = _tr3()
+    s = WL.scene3d_room(9, 2 if K < 3 else 0, 16, K, alpha, seed=50 + K)
+    sc = _scene_hs(s, alpha)
+    P, L, gtx, gp = tr.forward_backward(sc, loss="neg_mean_log")
+    P_o, kap = kappa3_hs(s.panels, s.tx, s.rx, K, alpha)
+    PU.check_power(P.cpu().numpy(), P_o, kap, f"3D hard K={K}")
+    L_o = -np.mean(np.log(P_o + 1e-6))
+    assert float(L) == pytest.approx(L_o, rel=1e-5, abs=1e-5 * float(np.mean(np.abs(np.log(P_o + 1e-6)))))
+    g = -1.0 / (s.n_rx * (P_o + 1e-6))
+    gp_o, gt_o, _ = T3.vjp(s.panels, s.tx, s.rx, K, alpha, g, mode="hard_sigmoid")
+    PU.check_grads(gtx.cpu().numpy(), gp.cpu().numpy(), gt_o, gp_o, f"3D hard K={K}")
+
+
+def test_hard_sigmoid_full_size_sampled():
+    tr = _tr3()
+    s = WL.scene3d_32()
+    sc = _scene_hs(s, 100.0)
+    P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
+    rng = np.random.default_rng(8)
+    idx = np.unique(np.concatenate([rng.choice(s.n_rx, 62, replace=False), [0, s.n_rx - 1]]))
+    P_o, kap = kappa3_hs(s.panels, s.tx, s.rx[idx], 2, 100.0)
+    PU.check_power(P.cpu().numpy()[idx], P_o, kap, "scene3d_32 hard")
+    w = np.zeros(s.n_rx, np.float32)
+    w[idx[:24]] = 1.0
+    gtx, gp = tr.backward(sc, seed * _dev(w))
+    gp_o, gt_o, _ = T3.vjp(s.panels, s.tx, s.rx[idx[:24]], 2, 100.0, seed.cpu().numpy()[idx[:24]],
+                           mode="hard_sigmoid")
+    PU.check_grads(gtx.cpu().numpy(), gp.cpu().numpy(), gt_o, gp_o, "scene3d_32 hard")
+
+
+def test_hard_sigmoid_screen_and_culling_change_no_bit():
+    from paper_2401_11882_amd import tracer as tr
+    tr3 = _tr3()
+    s = WL.scene3d_room(9, 12, 16, 2, 30.0, seed=23)
+    sc = _scene_hs(s, 30.0)
+    on = tr3.forward_backward(sc, loss="neg_mean_log")
+    tr.set_screen(False)
+    try:
+        off = tr3.forward_backward(sc, loss="neg_mean_log")
+    finally:
+        tr.set_screen(True)
+    for a, b in zip(on, off):
+        assert torch.equal(a, b)
