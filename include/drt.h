@@ -385,9 +385,9 @@ int drt_valu_peak(double* fma_tflops, double* exp_tlanes);
  * coordinates (Sec. IV-A with Eq. 3-4, or the hard sigmoid of Eq. 5-6).  A panel of
  * zero area contributes no path and never obstructs; a back-trace parallel
  * to a plane gives no path; a leg parallel to a plane is not obstructed by
- * it.  Power, losses, error handling, determinism, graph capture and the
- * contribution cache (drt_set_cache_limit) are as in the 2D calls above;
- * there are no receiver gradients.
+ * it.  Power, losses, error handling, determinism, graph capture, receiver
+ * gradients and the contribution cache (drt_set_cache_limit) are as in the
+ * 2D calls above.
  * ------------------------------------------------------------------------ */
 
 #define DRT3_MAX_PANELS 256
@@ -415,15 +415,18 @@ int drt3_forward(const drt3_scene* scene, int32_t loss_kind, float log_eps, floa
                  float* loss_dev, float* seed_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* As drt_backward: grad_tx_dev [3], grad_panels_dev [n_panels][9] (same
-   order as the panels), overwritten.  flags: 0 or DRT_BWD_REUSE_FORWARD. */
+   order as the panels) and, if not NULL, grad_rx_dev [n_rx][3], overwritten.
+   flags: 0 or DRT_BWD_REUSE_FORWARD. */
 int drt3_backward(const drt3_scene* scene, const float* grad_power_dev, int32_t flags,
-                  float* grad_tx_dev, float* grad_panels_dev, void* ws_dev, size_t ws_bytes,
-                  void* stream);
+                  float* grad_tx_dev, float* grad_panels_dev, float* grad_rx_dev, void* ws_dev,
+                  size_t ws_bytes, void* stream);
 
-/* Forward, loss seed and adjoint in one call (loss_kind must not be NONE). */
+/* Forward, loss seed and adjoint in one call (loss_kind must not be NONE);
+   grad_rx_dev and loss_dev may be NULL. */
 int drt3_forward_backward(const drt3_scene* scene, int32_t loss_kind, float log_eps,
                           float* power_dev, float* loss_dev, float* grad_tx_dev,
-                          float* grad_panels_dev, void* ws_dev, size_t ws_bytes, void* stream);
+                          float* grad_panels_dev, float* grad_rx_dev, void* ws_dev, size_t ws_bytes,
+                          void* stream);
 
 #ifdef __cplusplus
 }

@@ -110,10 +110,10 @@ _SIGS = {
     "drt3_workspace_size": ([ctypes.POINTER(Drt3Scene), ctypes.POINTER(c_size_t)], c_int32),
     "drt3_forward": ([ctypes.POINTER(Drt3Scene), c_int32, c_float, c_void_p, c_void_p, c_void_p,
                       c_void_p, c_size_t, c_void_p], c_int32),
-    "drt3_backward": ([ctypes.POINTER(Drt3Scene), c_void_p, c_int32, c_void_p, c_void_p,
+    "drt3_backward": ([ctypes.POINTER(Drt3Scene), c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                        c_void_p, c_size_t, c_void_p], c_int32),
     "drt3_forward_backward": ([ctypes.POINTER(Drt3Scene), c_int32, c_float, c_void_p, c_void_p,
-                               c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
 }
 
 _lib = None

@@ -209,12 +209,12 @@ int enqueue_forward3(const drt3_scene* s, const Plan3& p, const drt::Trace3Args&
 }
 
 int enqueue_backward3(const drt3_scene* s, const Plan3& p, const drt::Trace3Args& A, const float* gP, float* gtx,
-                      float* gpanels, int reuse, void* ws, hipStream_t st) {
+                      float* gpanels, float* grx, int reuse, void* ws, hipStream_t st) {
   char* w = static_cast<char*>(ws);
   float* part = reinterpret_cast<float*>(w + p.off_grad);
   hipError_t e;
   if (p.n_tiles > 0) {
-    e = drt::launch_backward3(A, p.n_tiles, p.nw, gP, part, reuse, st);
+    e = drt::launch_backward3(A, p.n_tiles, p.nw, gP, part, grx, reuse, st);
     if (e != hipSuccess) return hip_fail(e, "backward3 launch");
   }
   e = drt::launch_panel_grads(part, p.n_tiles, s->n_panels, s->panels_dev, reinterpret_cast<float*>(w + p.off_tmp),
@@ -250,7 +250,7 @@ int drt3_forward(const drt3_scene* scene, int32_t loss_kind, float log_eps, floa
 }
 
 int drt3_backward(const drt3_scene* scene, const float* grad_power_dev, int32_t flags, float* grad_tx_dev,
-                  float* grad_panels_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+                  float* grad_panels_dev, float* grad_rx_dev, void* ws_dev, size_t ws_bytes, void* stream) {
   int rc = check_scene3(scene);
   if (rc) return rc;
   if (flags & ~DRT_BWD_REUSE_FORWARD) return failf(DRT_EINVAL, "unknown flags 0x%x", flags);
@@ -262,13 +262,13 @@ int drt3_backward(const drt3_scene* scene, const float* grad_power_dev, int32_t 
   const drt::Trace3Args A = make_args3(scene, p, ws_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = prep3(scene, p, ws_dev, st))) return rc;
-  return enqueue_backward3(scene, p, A, grad_power_dev, grad_tx_dev, grad_panels_dev,
+  return enqueue_backward3(scene, p, A, grad_power_dev, grad_tx_dev, grad_panels_dev, grad_rx_dev,
                            (flags & DRT_BWD_REUSE_FORWARD) ? 1 : 0, ws_dev, st);
 }
 
 int drt3_forward_backward(const drt3_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
-                          float* loss_dev, float* grad_tx_dev, float* grad_panels_dev, void* ws_dev, size_t ws_bytes,
-                          void* stream) {
+                          float* loss_dev, float* grad_tx_dev, float* grad_panels_dev, float* grad_rx_dev,
+                          void* ws_dev, size_t ws_bytes, void* stream) {
   int rc = check_scene3(scene);
   if (rc) return rc;
   if ((rc = check_loss3(loss_kind, log_eps))) return rc;
@@ -284,7 +284,7 @@ int drt3_forward_backward(const drt3_scene* scene, int32_t loss_kind, float log_
   float* seed = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + p.off_seed);
   rc = enqueue_forward3(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed, ws_dev, st);
   if (rc) return rc;
-  return enqueue_backward3(scene, p, A, seed, grad_tx_dev, grad_panels_dev, 1, ws_dev, st);
+  return enqueue_backward3(scene, p, A, seed, grad_tx_dev, grad_panels_dev, grad_rx_dev, 1, ws_dev, st);
 }
 
 }  // extern "C"

@@ -409,7 +409,8 @@ __device__ __forceinline__ void acc_panel(float* acc, int j, const float (&g)[kP
 }
 
 struct LaneGrad3 {
-  float tx, ty, tz;
+  float tx, ty, tz;  // transmitter (summed over lanes later)
+  float rx, ry, rz;  // this lane's receiver
 };
 
 // Reverse sweep of one path given Wl = g(r) c (= dL / dlog V at this lane).
@@ -509,6 +510,9 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
       gIx[K] += f * ex;
       gIy[K] += f * ey;
       gIz[K] += f * ez;
+      gXx[K + 1] -= f * ex;
+      gXy[K + 1] -= f * ey;
+      gXz[K + 1] -= f * ez;
     }
   }
   // -- interactions i = 1 .. K: the back-trace made X_i from X_{i+1}, so its
@@ -579,6 +583,9 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
   G.tx += gXx[0];
   G.ty += gXy[0];
   G.tz += gXz[0];
+  G.rx += gXx[K + 1];
+  G.ry += gXy[K + 1];
+  G.rz += gXz[K + 1];
   if (K == 0) {
     // I_0 is the transmitter itself
     G.tx += gIx[0];

@@ -39,8 +39,9 @@ hipError_t launch_prep_panels(const float* panels, int n, float cull_c, PanelRec
                               hipStream_t st);
 hipError_t launch_forward3(const Trace3Args& A, int n_tiles, int nw, float* power, float* seed, float* loss_part,
                            int loss_kind, float log_eps, hipStream_t st);
-hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, int reuse,
-                            hipStream_t st);
+// grad_rx: [n_rx][3] or NULL.
+hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, float* grad_rx,
+                            int reuse, hipStream_t st);
 // grad_tx[3] and grad_panels[n][9] from the fixed-order column sums of the
 // per-tile partials [n_tiles][3 + 13 n] (tmp: 13 n floats).
 hipError_t launch_panel_grads(const float* part, int n_tiles, int n_panels, const float* panels, float* tmp,

@@ -157,11 +157,13 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
 
 template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_backward3(Trace3Args A, const float* __restrict__ gP,
-                                                          float* __restrict__ part, int reuse) {
+                                                          float* __restrict__ part, float* __restrict__ grad_rx,
+                                                          int reuse) {
   extern __shared__ float smem3[];
   const Scene3View S = view3_of(A);
   const int ncol = 3 + kPanelGrad * A.n_panels;
-  float* accs = smem3;  // [NW][ncol]
+  float* accs = smem3;                 // [NW][ncol]
+  float* rxr = smem3 + NW * ncol;      // [NW][3][64] per-wave receiver gradients
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uniform(threadIdx.x >> 6);
   for (int i = threadIdx.x; i < NW * ncol; i += NW * kWave) accs[i] = 0.0f;
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
   const float rx = live ? A.rx[3 * m] : 0.5f, ry = live ? A.rx[3 * m + 1] : 0.5f, rz = live ? A.rx[3 * m + 2] : 0.5f;
   const float g = live ? gP[m] : 0.0f;
   const float tx = A.tx[0], ty = A.tx[1], tz = A.tx[2];
-  LaneGrad3 G{0.0f, 0.0f, 0.0f};
+  LaneGrad3 G{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   if (ballot(g != 0.0f) != 0) {
     const int slot = tile * NW + wave;
     const int n_cached = (reuse && A.cache_c) ? A.cache_n[slot] : -1;
@@ -206,7 +208,22 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
       acc[2] += sz;
     }
   }
+  rxr[(wave * 3 + 0) * kWave + lane] = G.rx;
+  rxr[(wave * 3 + 1) * kWave + lane] = G.ry;
+  rxr[(wave * 3 + 2) * kWave + lane] = G.rz;
   __syncthreads();
+  if (wave == 0 && live && grad_rx) {
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      s0 += rxr[(w * 3 + 0) * kWave + lane];
+      s1 += rxr[(w * 3 + 1) * kWave + lane];
+      s2 += rxr[(w * 3 + 2) * kWave + lane];
+    }
+    grad_rx[3 * m] = s0;
+    grad_rx[3 * m + 1] = s1;
+    grad_rx[3 * m + 2] = s2;
+  }
   for (int col = threadIdx.x; col < ncol; col += NW * kWave) {
     float s = 0.0f;
 #pragma unroll
@@ -302,27 +319,28 @@ hipError_t launch_forward3(const Trace3Args& A, int n_tiles, int nw, float* powe
 }
 
 size_t backward3_lds_bytes(int nw, int n_panels) {
-  return sizeof(float) * (size_t)nw * (3 + kPanelGrad * (size_t)n_panels);
+  return sizeof(float) * (size_t)nw * (3 + kPanelGrad * (size_t)n_panels + 3 * kWave);
 }
 
 template <int NW, int MODE>
-static hipError_t bwd3_nw(const Trace3Args& A, int n_tiles, const float* gP, float* part, int reuse, hipStream_t st) {
+static hipError_t bwd3_nw(const Trace3Args& A, int n_tiles, const float* gP, float* part, float* grad_rx, int reuse,
+                          hipStream_t st) {
   hipLaunchKernelGGL((k_backward3<NW, MODE>), dim3(n_tiles), dim3(NW * kWave), backward3_lds_bytes(NW, A.n_panels), st, A,
-                     gP, part, reuse);
+                     gP, part, grad_rx, reuse);
   return hipGetLastError();
 }
 
-hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, int reuse,
-                            hipStream_t st) {
+hipError_t launch_backward3(const Trace3Args& A, int n_tiles, int nw, const float* gP, float* part, float* grad_rx,
+                            int reuse, hipStream_t st) {
   switch (nw) {
-    case 2: return A.mode ? bwd3_nw<2, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
-                     : bwd3_nw<2, kSigmoid>(A, n_tiles, gP, part, reuse, st);
-    case 4: return A.mode ? bwd3_nw<4, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
-                     : bwd3_nw<4, kSigmoid>(A, n_tiles, gP, part, reuse, st);
-    case 8: return A.mode ? bwd3_nw<8, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
-                     : bwd3_nw<8, kSigmoid>(A, n_tiles, gP, part, reuse, st);
-    case 16: return A.mode ? bwd3_nw<16, kHardSigmoid>(A, n_tiles, gP, part, reuse, st)
-                     : bwd3_nw<16, kSigmoid>(A, n_tiles, gP, part, reuse, st);
+    case 2: return A.mode ? bwd3_nw<2, kHardSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st)
+                     : bwd3_nw<2, kSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st);
+    case 4: return A.mode ? bwd3_nw<4, kHardSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st)
+                     : bwd3_nw<4, kSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st);
+    case 8: return A.mode ? bwd3_nw<8, kHardSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st)
+                     : bwd3_nw<8, kSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st);
+    case 16: return A.mode ? bwd3_nw<16, kHardSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st)
+                     : bwd3_nw<16, kSigmoid>(A, n_tiles, gP, part, grad_rx, reuse, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -78,8 +78,9 @@ def forward(scene: Scene3, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS,
     return P, L, seed
 
 
-def backward(scene: Scene3, grad_power: torch.Tensor, reuse_forward: bool = False, stream=None):
-    """(dL/dtx [3], dL/dpanels [P,9]) for a given dL/dP."""
+def backward(scene: Scene3, grad_power: torch.Tensor, reuse_forward: bool = False, want_rx: bool = False,
+             stream=None):
+    """(dL/dtx [3], dL/dpanels [P,9]) for a given dL/dP, and dL/drx [R,3] when want_rx."""
     _dev_f32(grad_power, "grad_power")
     if grad_power.numel() != scene.n_rx:
         raise ValueError("grad_power must have one entry per receiver")
@@ -87,15 +88,18 @@ def backward(scene: Scene3, grad_power: torch.Tensor, reuse_forward: bool = Fals
     ws, nbytes = workspace(sc, scene.device)
     gtx = torch.empty(3, dtype=torch.float32, device=scene.device)
     gp = torch.empty(scene.n_panels, 9, dtype=torch.float32, device=scene.device)
+    grx = torch.empty(scene.n_rx, 3, dtype=torch.float32, device=scene.device) if want_rx else None
     flags = _lib.DRT_BWD_REUSE_FORWARD if reuse_forward else 0
     check(lib().drt3_backward(ctypes.byref(sc), _ptr(grad_power), flags, _ptr(gtx),
-                              _ptr(gp if scene.n_panels else None), _ptr(ws), nbytes, stream_handle(stream)))
-    return gtx, gp
+                              _ptr(gp if scene.n_panels else None), _ptr(grx), _ptr(ws), nbytes,
+                              stream_handle(stream)))
+    return (gtx, gp, grx) if want_rx else (gtx, gp)
 
 
 def forward_backward(scene: Scene3, loss: str = "neg_mean_log", log_eps: float = DEFAULT_LOG_EPS, out=None,
-                     stream=None):
-    """(P, L, dL/dtx, dL/dpanels) in one call; ``out`` may hold those tensors preallocated."""
+                     want_rx: bool = False, stream=None):
+    """(P, L, dL/dtx, dL/dpanels), plus dL/drx [R,3] when want_rx, in one call; ``out`` may hold
+    those tensors preallocated."""
     if loss == "none":
         raise ValueError("forward_backward needs a loss")
     sc = scene.c_struct()
@@ -106,8 +110,11 @@ def forward_backward(scene: Scene3, loss: str = "neg_mean_log", log_eps: float =
                torch.empty(1, dtype=torch.float32, device=dev),
                torch.empty(3, dtype=torch.float32, device=dev),
                torch.empty(scene.n_panels, 9, dtype=torch.float32, device=dev))
-    P, L, gtx, gp = out
+        if want_rx:
+            out = out + (torch.empty(scene.n_rx, 3, dtype=torch.float32, device=dev),)
+    P, L, gtx, gp = out[:4]
+    grx = out[4] if len(out) > 4 else None
     check(lib().drt3_forward_backward(ctypes.byref(sc), _lib.LOSS[loss], float(log_eps), _ptr(P), _ptr(L),
-                                      _ptr(gtx), _ptr(gp if scene.n_panels else None), _ptr(ws), nbytes,
-                                      stream_handle(stream)))
+                                      _ptr(gtx), _ptr(gp if scene.n_panels else None), _ptr(grx), _ptr(ws),
+                                      nbytes, stream_handle(stream)))
     return out

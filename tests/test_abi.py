@@ -184,8 +184,8 @@ def test_scene3_validation(field, value, code):
     assert L.drt3_workspace_size(ctypes.byref(sc), ctypes.byref(n)) == code
     assert L.drt_last_error()
     assert L.drt3_forward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, None, BOGUS, 1 << 30, None) == code
-    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, BOGUS, BOGUS, BOGUS, 1 << 30, None) == code
-    assert L.drt3_forward_backward(ctypes.byref(sc), 2, 1e-6, BOGUS, None, BOGUS, BOGUS, BOGUS, 1 << 30,
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, BOGUS, BOGUS, None, BOGUS, 1 << 30, None) == code
+    assert L.drt3_forward_backward(ctypes.byref(sc), 2, 1e-6, BOGUS, None, BOGUS, BOGUS, None, BOGUS, 1 << 30,
                                    None) == code
 
 
@@ -201,10 +201,10 @@ def test_scene3_call_validation_before_launch():
     assert L.drt3_forward(ctypes.byref(sc), 7, 1e-6, BOGUS, None, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
     assert L.drt3_forward(ctypes.byref(sc), 2, 0.0, BOGUS, None, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
     assert L.drt3_forward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
-    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 4, BOGUS, BOGUS, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
-    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, None, BOGUS, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
-    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
-    assert L.drt3_forward_backward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, BOGUS, 1 << 30,
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 4, BOGUS, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_backward(ctypes.byref(sc), BOGUS, 0, BOGUS, None, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
+    assert L.drt3_forward_backward(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, None, BOGUS, 1 << 30,
                                    None) == _lib.DRT_EINVAL
     empty = _scene3(n_rx=0, rx_dev=None, rx_grid_nx=0)
     assert L.drt3_forward(ctypes.byref(empty), 3, 1e-6, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL

@@ -63,14 +63,15 @@ def test_room_scenes_all_orders(K, alpha):
     tr = _tr3()
     s = WL.scene3d_room(9, 2 if K < 3 else 0, 16, K, alpha, seed=40 + K)
     sc = _scene(s)
-    P, L, gtx, gp = tr.forward_backward(sc, loss="neg_mean_log")
+    P, L, gtx, gp, grx = tr.forward_backward(sc, loss="neg_mean_log", want_rx=True)
     P_o, kap = kappa3(s.panels, s.tx, s.rx, K, alpha)
     PU.check_power(P.cpu().numpy(), P_o, kap, f"3D K={K}")
     L_o = -np.mean(np.log(P_o + 1e-6))
     assert float(L) == pytest.approx(L_o, rel=1e-5)
     g = -1.0 / (s.n_rx * (P_o + 1e-6))
-    gp_o, gt_o, _ = T3.vjp(s.panels, s.tx, s.rx, K, alpha, g)
+    gp_o, gt_o, grx_o = T3.vjp(s.panels, s.tx, s.rx, K, alpha, g)
     PU.check_grads(gtx.cpu().numpy(), gp.cpu().numpy(), gt_o, gp_o, f"3D K={K}")
+    assert PU.rel_l2(grx.cpu().numpy(), grx_o) <= PU.GRAD_REL, "receiver gradients"
 
 
 def test_extruded_2d_scene_matches_the_2d_reference():
@@ -101,9 +102,12 @@ def test_full_size_scene_sampled():
     w = np.zeros(s.n_rx, np.float32)
     w[idx[:24]] = 1.0
     g = seed * _dev(w)
-    gtx, gp = tr.backward(sc, g)
-    gp_o, gt_o, _ = T3.vjp(s.panels, s.tx, s.rx[idx[:24]], 2, s.alpha, seed.cpu().numpy()[idx[:24]])
+    gtx, gp, grx = tr.backward(sc, g, want_rx=True)
+    gp_o, gt_o, grx_o = T3.vjp(s.panels, s.tx, s.rx[idx[:24]], 2, s.alpha, seed.cpu().numpy()[idx[:24]])
     PU.check_grads(gtx.cpu().numpy(), gp.cpu().numpy(), gt_o, gp_o, "scene3d_32")
+    assert PU.rel_l2(grx.cpu().numpy()[idx[:24]], grx_o) <= PU.GRAD_REL, "receiver gradients"
+    rest = np.setdiff1d(np.arange(s.n_rx), idx[:24])
+    assert torch.count_nonzero(grx[torch.as_tensor(rest, device="cuda")]) == 0
 
 
 def test_degenerate_panel_and_ragged_receivers():
