@@ -209,16 +209,13 @@ __device__ __forceinline__ bool setup3(const Scene3View& S, const Cand& cd, floa
   return true;
 }
 
-// 1 - in(ups) in(beta) in(gamma) = num / (1 + num) with
+// Sigmoid: 1 - in(ups) in(beta) in(gamma) = num / (1 + num) with
 // num = (1 + n_u)(1 + n_b)(1 + n_g) - 1 expanded into positive terms,
 // n_x = E1 + E2 + E1 E2 (E1 = e^(-alpha x), E2 = e^(-alpha (1 - x))).
-__device__ __forceinline__ float n_of(float x, float a2) {
-  const float E1 = ex2(-a2 * x), E2 = ex2(fmaf(a2, x, -a2));
-  return fmaf(E1, E2, E1 + E2);
-}
-
 struct Obs3 {
   float ups, be, ga, inv, qx, qy, qz, num;  // num: sigmoid num; hard sigmoid: the factor q itself
+  // sigmoid: per parameter (ups, beta, gamma) E1 - E2 and A = (1 + E1)(1 + E2) = 1 + n
+  float dE[3], A[3];
 };
 
 // Obstruction test of leg (X, D) by panel w: false if every lane's factor is
@@ -248,9 +245,17 @@ __device__ __forceinline__ bool obs3(const Scene3View& S, const PanelRec& w, flo
     o.num = it ? fmaf(u.in, fmaf(b.in, g.n, b.n), u.n) : 1.0f;
   } else {
     if (it) {
-      const float nu = n_of(o.ups, S.a2), nb = n_of(o.be, S.a2), ng = n_of(o.ga, S.a2);
-      const float t = fmaf(nu, nb, nu + nb);
-      o.num = fmaf(t, ng, t + ng);
+      const float x[3] = {o.ups, o.be, o.ga};
+      float n[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float E1 = ex2(-S.a2 * x[k]), E2 = ex2(fmaf(S.a2, x[k], -S.a2));
+        n[k] = fmaf(E1, E2, E1 + E2);
+        o.dE[k] = E1 - E2;
+        o.A[k] = 1.0f + n[k];
+      }
+      const float t = fmaf(n[0], n[1], n[0] + n[1]);
+      o.num = fmaf(t, n[2], t + n[2]);
     } else {
       o.num = kBig;
     }
@@ -461,10 +466,12 @@ __device__ __forceinline__ void path_adjoint3(const Scene3View& S, const Path3<K
         gb = c * ramp3(hb) * (hu.in * hg.in);
         gg = c * ramp3(hg) * (hu.in * hb.in);
       } else {
-        const float c = -Wl * rcp(o.num);
-        gu = c * dlog_in(o.ups, S.alpha, S.a2);
-        gb = c * dlog_in(o.be, S.alpha, S.a2);
-        gg = c * dlog_in(o.ga, S.alpha, S.a2);
+        // q = num / (1 + num), 1 + num = A_u A_b A_g: d log q / dx = alpha (E2 - E1) / (A_x num)
+        // (E1, E2 <= e^18 within the band, so A_x num stays finite)
+        const float c = -S.alpha * Wl;
+        gu = c * o.dE[0] * rcp(o.A[0] * o.num);
+        gb = c * o.dE[1] * rcp(o.A[1] * o.num);
+        gg = c * o.dE[2] * rcp(o.A[2] * o.num);
       }
       // beta = q . m1, gamma = q . m2, q = X + ups D - a
       const float gqx = fmaf(gb, w.m1x, gg * w.m2x), gqy = fmaf(gb, w.m1y, gg * w.m2y),
