@@ -141,6 +141,20 @@ int drt_set_cache_limit(int64_t bytes);
    to verify that.  Process-wide. */
 int drt_set_screen(int32_t enabled);
 
+/* Contribution cut on (1, default) or off (0), for the 2D calls (single
+   scene and batched).  With the cut on, a receiver drops a candidate as soon
+   as the candidate's contribution is provably at most 2^-44 times a lower
+   bound of that receiver's power: the sum of its order-0 and order-1
+   contributions plus the running sum of the candidates already evaluated by
+   the same wavefront (every term is >= 0).  The forward may stop a
+   candidate's obstruction tests there; the dropped terms of a receiver add up
+   to at most C 2^-44 P(r) for C candidates (3e-10 P at C = 4,625), far below
+   the FP32 rounding of P.  Decisions depend only on the receiver, the
+   candidate order and the launch shape, so results stay deterministic; the
+   adjoint differentiates what the forward summed.  Turning the cut off gives
+   the exact (uncut) sums, to verify the bound.  Process-wide. */
+int drt_set_cut(int32_t enabled);
+
 /* Workspace bytes that drt_forward / drt_backward / drt_forward_backward
    need for this scene (depends on n_walls, n_rx and the launch shape).
    Host only; reads no device memory. */

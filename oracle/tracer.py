@@ -353,7 +353,7 @@ def path_details(walls, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_D
 
 
 def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
-                active_log_floor: float = -88.72):
+                active_log_floor: float = -88.72, cut: float = 0.0):
     """Algorithmic work of the method at these receivers (instrumentation).
 
     Counts, over all (receiver, candidate) pairs ("path evaluations"):
@@ -361,12 +361,18 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
       * ``active``: pairs whose product of interaction factors is above
         exp(active_log_floor) -- below it the product of the four
         (1 + exp) terms exceeds the FP32 range, the factor is exactly 0 in
-        FP32 and the obstruction tests of that pair contribute nothing;
+        FP32 and the obstruction tests of that pair contribute nothing --
+        and, with ``cut`` > 0, whose contribution bound F / max(d^2, d_min^2)
+        exceeds cut * P(r);
       * ``tests``: obstruction tests of active pairs (a leg is not tested
         against its own end walls);
       * ``unsaturated``: tests of active pairs whose tau and upsilon both lie
         within margin/alpha of [0, 1] (outside that band the smoothed factor
-        is within 2^-25 of 1 and rounds to 1 in FP32);
+        is within 2^-25 of 1 and rounds to 1 in FP32) and, with ``cut`` > 0,
+        that come while the pair's product so far V (walls in increasing
+        order, legs in order within a wall) still exceeds
+        cut * P(r) max(d^2, d_min^2): a pair below that can no longer change
+        P(r) by more than cut * P(r);
       * ``active_interactions``: interactions of active pairs.
     """
     W = _as64(walls).reshape(-1, 4)
@@ -375,30 +381,38 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
     a = W[:, 0:2]
     e = W[:, 2:4] - W[:, 0:2]
     groups = _groups(W.shape[0], max_order)
-    cs = _chunk_size(Rx.shape[0], groups, W.shape[0])
+    cs = max(1, _chunk_size(Rx.shape[0], groups, W.shape[0]) // (max_order + 1))
     band = margin / alpha
+    P_all = torch.as_tensor(power(walls, tx, rx, max_order, alpha), dtype=DTYPE) if cut > 0 else None
     out = dict(path_evals=0, interactions=0, active=0, active_interactions=0, tests=0, unsaturated=0)
+    nW = W.shape[0]
+    jidx = torch.arange(nW)
     with torch.no_grad():
         for s in range(0, Rx.shape[0], cs):
             rxc = Rx[s:s + cs]
             for k, seq in groups.items():
-                _, info = _group_terms(W, T, rxc, seq, alpha, "sigmoid", DEFAULT_DMIN, True)
+                c_, info = _group_terms(W, T, rxc, seq, alpha, "sigmoid", DEFAULT_DMIN, True)
                 X = info["X"]
                 Cn = seq.shape[0]
                 logf = torch.zeros(rxc.shape[0], Cn, dtype=DTYPE)
                 for i, (t, u) in info["params"].items():
                     logf = logf + _log_inside(t, alpha) + _log_inside(u, alpha)
                 act = info["valid"] & (logf > active_log_floor)
+                dd = torch.clamp(info["d2"], min=DEFAULT_DMIN * DEFAULT_DMIN)
+                if cut > 0:
+                    lim = cut * P_all[s:s + cs][:, None] * dd          # [Rc, C] cut on V
+                    act = act & (torch.exp(logf) > lim)
                 out["path_evals"] += rxc.shape[0] * Cn
                 out["interactions"] += rxc.shape[0] * Cn * k
                 out["active"] += int(act.sum())
                 out["active_interactions"] += int(act.sum()) * k
-                jidx = torch.arange(W.shape[0])
+                # per (wall, leg) in visiting order: in-band flags and smoothed factors
+                live_l, q_l = [], []
                 for l in range(k + 1):
                     D = (X[l + 1] - X[l])[:, :, None, :]
                     w0 = a[None, None] - X[l][:, :, None, :]
                     den = _cross(D, e[None, None])
-                    excl = torch.zeros(Cn, W.shape[0], dtype=torch.bool)
+                    excl = torch.zeros(Cn, nW, dtype=torch.bool)
                     if l >= 1:
                         excl |= seq[:, l - 1][:, None] == jidx[None]
                     if l + 1 <= k:
@@ -410,5 +424,17 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
                     live = use & (den != 0) & ((tau - 0.5).abs() < 0.5 + band) & \
                         ((ups - 0.5).abs() < 0.5 + band)
                     out["tests"] += int(use.sum())
-                    out["unsaturated"] += int(live.sum())
+                    live_l.append(live)
+                    if cut > 0:
+                        q = -torch.expm1(_log_inside(tau, alpha) + _log_inside(ups, alpha))
+                        q_l.append(torch.where(use & (den != 0), q, torch.ones_like(q)))
+                if cut <= 0:
+                    out["unsaturated"] += int(sum(int(v.sum()) for v in live_l))
+                    continue
+                # V before each test: F times the factors of earlier (wall, leg) tests
+                Lv = torch.stack(live_l, dim=-1).reshape(rxc.shape[0], Cn, -1)   # [Rc, C, W (k+1)]
+                Q = torch.stack(q_l, dim=-1).reshape(rxc.shape[0], Cn, -1)
+                Vb = torch.exp(logf)[..., None] * torch.cumprod(
+                    torch.cat([torch.ones_like(Q[..., :1]), Q[..., :-1]], dim=-1), dim=-1)
+                out["unsaturated"] += int((Lv & (Vb > lim[..., None])).sum())
     return out

@@ -77,6 +77,7 @@ _SIGS = {
                       c_void_p, c_size_t, c_void_p], c_int32),
     "drt_set_cache_limit": ([ctypes.c_int64], c_int32),
     "drt_set_screen": ([c_int32], c_int32),
+    "drt_set_cut": ([c_int32], c_int32),
     "drt_cache_layout": ([ctypes.POINTER(DrtScene), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], c_int32),
     "drt_forward_backward": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_void_p, c_void_p,

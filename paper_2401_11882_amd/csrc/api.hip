@@ -1,4 +1,5 @@
 // C ABI of the tracer library: argument checks, workspace layout, launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -34,6 +35,7 @@ int g_cchunk_override = 0;
 // Largest contribution cache placed in a workspace (bytes); 0 disables it.
 int64_t g_cache_limit = 32LL << 30;
 int g_screen = 1;
+int g_cut = 1;
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -112,7 +114,10 @@ Plan make_plan(const drt_scene* s) {
   off = align_up(off + sizeof(float) * (size_t)p.ncol * (size_t)(p.n_tiles > 0 ? p.n_tiles : 1));
   // contribution cache: a wavefront meets at most ceil(C / (nw*cchunk)) chunks
   const int64_t n_cand = count_candidates(s->n_walls, s->max_order);
-  const int64_t per_wave = (n_cand + (int64_t)p.nw * p.cchunk - 1) / ((int64_t)p.nw * p.cchunk) * p.cchunk;
+  // the forward visits the orders 0 and 1 first, then the rest: each part is
+  // split into chunks over the wavefronts
+  const int64_t n1 = std::min<int64_t>(n_cand, 1 + s->n_walls), span = (int64_t)p.nw * p.cchunk;
+  const int64_t per_wave = ((n1 + span - 1) / span + (n_cand - n1 + span - 1) / span) * p.cchunk;
   const int64_t slots = (int64_t)p.n_tiles * p.nw;
   p.box_stride = 6 * (s->max_order + 1);
   const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int) + (int64_t)p.box_stride * sizeof(float);
@@ -148,6 +153,7 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.n_cand = (int)count_candidates(s->n_walls, s->max_order);
   A.cchunk = p.cchunk;
   A.screen = g_screen;
+  A.cut = g_cut ? drt::kCut : 0.0f;
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
   const bool hard = s->smoothing == DRT_HARD_SIGMOID;
@@ -240,6 +246,7 @@ __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char
 
 __attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void) { return g_cache_limit; }
 __attribute__((visibility("hidden"))) int drt_internal_screen(void) { return g_screen; }
+__attribute__((visibility("hidden"))) int drt_internal_cut(void) { return g_cut; }
 
 int drt_abi_version(void) { return DRT_ABI_VERSION; }
 
@@ -274,6 +281,12 @@ int drt_set_cache_limit(int64_t bytes) {
 int drt_set_screen(int32_t enabled) {
   if (enabled != 0 && enabled != 1) return fail(DRT_EINVAL, "screen flag %d must be 0 or 1", enabled);
   g_screen = enabled;
+  return DRT_OK;
+}
+
+int drt_set_cut(int32_t enabled) {
+  if (enabled != 0 && enabled != 1) return fail(DRT_EINVAL, "cut flag %d must be 0 or 1", enabled);
+  g_cut = enabled;
   return DRT_OK;
 }
 

@@ -16,6 +16,7 @@
 extern "C" __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char* msg);
 extern "C" __attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void);
 extern "C" __attribute__((visibility("hidden"))) int drt_internal_screen(void);
+extern "C" __attribute__((visibility("hidden"))) int drt_internal_cut(void);
 
 namespace {
 
@@ -111,7 +112,10 @@ int apply_config(drt_plan* p, const drt_plan_config& c) {
   const int bpc = c.blocks_per_cu <= 0 ? maxb : std::min(c.blocks_per_cu, maxb);
   const int blocks = bpc * p->n_cu;
   // contribution cache: one region per wavefront slot of the persistent grid
-  const int64_t per_wave = (p->max_cand + (int64_t)c.nw * c.cchunk - 1) / ((int64_t)c.nw * c.cchunk) * c.cchunk;
+  // the forward visits the orders 0 and 1 first, then the rest, each part in
+  // chunks over the wavefronts: at most one extra chunk per wavefront
+  const int64_t per_wave =
+      ((p->max_cand + (int64_t)c.nw * c.cchunk - 1) / ((int64_t)c.nw * c.cchunk) + 1) * c.cchunk;
   const int64_t slots = (int64_t)blocks * c.nw;
   const int box_stride = 6 * (p->max_order + 1);
   const int64_t entry = 64 * (int64_t)sizeof(float) + (int64_t)sizeof(int) + (int64_t)box_stride * sizeof(float);
@@ -193,6 +197,7 @@ drt::BatchArgs make_args(const drt_plan* p, const drt_batch* b, int loss_kind, f
   B.cache_cap = p->cache_cap;
   B.cchunk = p->cfg.cchunk;
   B.screen = drt_internal_screen();
+  B.cut = drt_internal_cut() ? drt::kCut : 0.0f;
   B.mode = b->smoothing == DRT_HARD_SIGMOID ? 1 : 0;
   B.box_lds = drt::batched_box_lds(p->cfg.nw, p->max_walls, p->max_order) ? 1 : 0;
   B.tile_w = p->cfg.tile_w;

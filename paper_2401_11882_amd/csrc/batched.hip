@@ -54,6 +54,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
   extern __shared__ float smem[];
   __shared__ int item_sh;
   __shared__ float gsh[kWave];
+  __shared__ float base[NW][kWave];  // each wavefront's power sum over the orders 0 and 1
   const int ncol_max = 2 + 4 * B.max_walls;
   float* accs = smem;                        // [NW][ncol_max]
   float* red = smem + NW * ncol_max;         // [NW][2][64]
@@ -107,20 +108,33 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
     float sum = 0.0f, comp = 0.0f;
     int nst = 0;
     const RxBox box = rx_box(rxx, rxy, live);
-    for_screened(S.walls, W, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box, S.cull_c,
-                    boxes, [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
-                   const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
-                   kahan_add(sum, comp, v);
-                   if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
-                     if (nst < B.cache_cap) {
-                       cache_c[(size_t)nst * kWave + lane] = v;
-                       if (lane == 0) cache_idx[nst] = c;
-                       if (boxes && lane < B.box_stride)
-                         B.cache_box[((size_t)slot * B.cache_cap + nst) * B.box_stride + lane] = boxes[lane * kWave + j];
-                     }
-                     ++nst;
-                   }
-                 });
+    // contribution cut against the orders 0 and 1 of every wavefront plus
+    // this wavefront's running sum (see k_forward)
+    float cut_base = 0.0f, own1 = 0.0f;
+    auto visit = [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
+      const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
+                                                B.cut * (cut_base + (sum - comp) - own1));
+      kahan_add(sum, comp, v);
+      if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
+        if (nst < B.cache_cap) {
+          cache_c[(size_t)nst * kWave + lane] = v;
+          if (lane == 0) cache_idx[nst] = c;
+          if (boxes && lane < B.box_stride)
+            B.cache_box[((size_t)slot * B.cache_cap + nst) * B.box_stride + lane] = boxes[lane * kWave + j];
+        }
+        ++nst;
+      }
+    };
+    const int n1 = min(n_cand, 1 + W);
+    for_screened(S.walls, W, 0, n1, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box, S.cull_c, boxes,
+                 visit);
+    own1 = sum - comp;
+    base[wave][lane] = own1;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
+    for_screened(S.walls, W, n1, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box, S.cull_c,
+                 boxes, visit);
     red[(wave * 2 + 0) * kWave + lane] = sum;
     red[(wave * 2 + 1) * kWave + lane] = comp;
     __syncthreads();
@@ -170,12 +184,20 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
         candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
       }
     } else {
+      // re-evaluation of this wavefront's share as the forward split it, the
+      // cut against its own running sum
+      float rs = 0.0f, rc = 0.0f;
+      const int n1 = min(n_cand, 1 + W);
       const int stride = NW * B.cchunk;
-      for (int c0 = wave * B.cchunk; c0 < n_cand; c0 += stride) {
-        const int c1 = min(c0 + B.cchunk, n_cand);
-        for (int c = c0; c < c1; ++c) {
-          const Cand cd = decode_candidate(c, W);
-          candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
+      for (int part = 0; part < 2; ++part) {
+        const int b0 = part ? n1 : 0, b1 = part ? n_cand : n1;
+        for (int c0 = b0 + wave * B.cchunk; c0 < b1; c0 += stride) {
+          const int c1 = min(c0 + B.cchunk, b1);
+          for (int c = c0; c < c1; ++c) {
+            const Cand cd = decode_candidate(c, W);
+            kahan_add(rs, rc,
+                      candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, B.cut * (rs - rc)));
+          }
         }
       }
     }

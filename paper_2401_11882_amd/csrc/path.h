@@ -375,7 +375,7 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
 // they are formed from the live lanes' legs.
 template <int K, int MODE>
 __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>& P, float V,
-                                              const float* boxes = nullptr, int j = 0) {
+                                              const float* boxes = nullptr, int j = 0, float vcut = 0.0f) {
   LegGeom L[K + 1];
   leg_geoms<K>(P, L);
   LegBox B[K + 1];
@@ -413,7 +413,9 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
         upd = true;
       }
     }
-    // once every lane's product is exactly 0 no further factor can change it
+    // a lane whose product fell to its cut contributes nothing; once every
+    // lane's product is 0 no further factor can change it
+    V = V > vcut ? V : 0.0f;
     return ballot(upd) == 0 || ballot(V != 0.0f) != 0;
   });
   return V;
@@ -437,7 +439,7 @@ __device__ __forceinline__ float path_power(const SceneView& S, const Cand& cd, 
 template <int K, int MODE>
 __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                 const float* Iy, float txx, float txy, float rxx, float rxy,
-                                                bool live, const float* boxes, int j) {
+                                                bool live, const float* boxes, int j, float scut) {
   Path<K> P;
   path_walls<K>(cd, P);
   P.Ix[0] = txx;
@@ -448,11 +450,13 @@ __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& 
     P.Iy[i + 1] = Iy[i];
   }
   if (!back_trace<K, true, MODE>(S, rxx, rxy, live, P)) return 0.0f;
-  if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all<K, MODE>(S, P, P.F, boxes, j);
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
-  const float d2 = fmaf(ex, ex, ey * ey);
-  return V / fmaxf(d2, S.dmin2);
+  const float dd = fmaxf(fmaf(ex, ex, ey * ey), S.dmin2);
+  const float vcut = scut * dd;  // the contribution V / dd is below the cut once V <= vcut
+  P.F = P.F > vcut ? P.F : 0.0f;
+  if (ballot(P.F != 0.0f) == 0) return 0.0f;
+  const float V = obstruct_all<K, MODE>(S, P, P.F, boxes, j, vcut);
+  return V / dd;
 }
 
 // Per-wave accumulator layout: [0,1] = d/dtx, [2 + 4j + c] = d/d walls[j][c].
@@ -673,18 +677,22 @@ __device__ __forceinline__ void path_adjoint_core(const SceneView& S, const Path
 
 // Adjoint of one candidate, re-evaluating its forward value first.
 template <int K, int MODE>
-__device__ __forceinline__ void path_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
-                                             float rxx, float rxy, bool live, float g, float* acc,
-                                             int lane, LaneGrad& G) {
+__device__ __forceinline__ float path_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
+                                              float rxx, float rxy, bool live, float g, float* acc,
+                                              int lane, LaneGrad& G, float scut) {
   Path<K> P;
-  if (!setup_path<K, true, MODE>(S, cd, txx, txy, rxx, rxy, live, P)) return;
-  if (ballot(P.F != 0.0f && g != 0.0f) == 0) return;
-  const float V = obstruct_all<K, MODE>(S, P, P.F);
+  if (!setup_path<K, true, MODE>(S, cd, txx, txy, rxx, rxy, live, P)) return 0.0f;
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
-  const float d2 = fmaf(ex, ex, ey * ey);
-  const float Wl = g * (V / fmaxf(d2, S.dmin2));
-  if (ballot(Wl != 0.0f) == 0) return;
-  path_adjoint_core<K, MODE>(S, P, Wl, rxx, rxy, acc, lane, G);
+  const float dd = fmaxf(fmaf(ex, ex, ey * ey), S.dmin2);
+  const float vcut = scut * dd;
+  P.F = P.F > vcut ? P.F : 0.0f;
+  // lanes with g = 0 need neither their contribution nor their gradient
+  if (ballot(P.F != 0.0f && g != 0.0f) == 0) return 0.0f;
+  const float V = obstruct_all<K, MODE>(S, P, P.F, nullptr, 0, vcut);
+  const float c = V / dd;
+  const float Wl = g * c;
+  if (ballot(Wl != 0.0f) != 0) path_adjoint_core<K, MODE>(S, P, Wl, rxx, rxy, acc, lane, G);
+  return c;
 }
 
 // Adjoint of one candidate whose contribution c is already known.
@@ -711,24 +719,25 @@ __device__ __forceinline__ float candidate_power(const SceneView& S, const Cand&
 template <int MODE>
 __device__ __forceinline__ float candidate_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                      const float* Iy, float txx, float txy, float rxx,
-                                                     float rxy, bool live, const float* boxes, int j) {
+                                                     float rxy, bool live, const float* boxes, int j,
+                                                     float scut) {
   switch (cd.k) {
-    case 0: return path_power_img<0, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
-    case 1: return path_power_img<1, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
-    case 2: return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
-    default: return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
+    case 0: return path_power_img<0, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
+    case 1: return path_power_img<1, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
+    case 2: return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
+    default: return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
   }
 }
 
 template <int MODE>
-__device__ __forceinline__ void candidate_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
-                                                  float rxx, float rxy, bool live, float g, float* acc,
-                                                  int lane, LaneGrad& G) {
+__device__ __forceinline__ float candidate_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
+                                                   float rxx, float rxy, bool live, float g, float* acc,
+                                                   int lane, LaneGrad& G, float scut) {
   switch (cd.k) {
-    case 0: path_adjoint<0, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
-    case 1: path_adjoint<1, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
-    case 2: path_adjoint<2, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
-    default: path_adjoint<3, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G); break;
+    case 0: return path_adjoint<0, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
+    case 1: return path_adjoint<1, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
+    case 2: return path_adjoint<2, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
+    default: return path_adjoint<3, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
   }
 }
 

@@ -225,22 +225,23 @@ __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim
 
 // Calls fn(c, cd, Ix, Iy, j) (wave-uniform arguments: index, decoded walls,
 // images I_1..I_K, the lane that screened it) for every candidate of this
-// wavefront's share that survives the screen, in increasing candidate order.
-// The share: chunks of `cchunk` consecutive candidates, chunk q going to
-// wavefront q mod nw.  With `boxes` (this wavefront's LDS area of
-// 6 (K + 1) x 64 floats), every candidate's leg boxes are stored there.
+// wavefront's share of [c_begin, n_cand) that survives the screen, in
+// increasing candidate order.  The share: chunks of `cchunk` consecutive
+// candidates from c_begin on, chunk q going to wavefront q mod nw.  With
+// `boxes` (this wavefront's LDS area of 6 (K + 1) x 64 floats), every
+// candidate's leg boxes are stored there.
 template <class Fn>
-__device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, int n_cand, float lim,
+__device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, int c_begin, int n_cand, float lim,
                                              bool test, int wave, int nw, int cchunk, float txx, float txy,
                                              const RxBox& B, float cull_c, float* boxes, Fn&& fn) {
   if (B.empty) return;
   const int lane = __lane_id();
   for (int p0 = 0;; p0 += kWave) {
     const int q0 = p0 / cchunk;
-    if ((wave + nw * q0) * cchunk + (p0 - q0 * cchunk) >= n_cand) break;
+    if (c_begin + (wave + nw * q0) * cchunk + (p0 - q0 * cchunk) >= n_cand) break;
     const int p = p0 + lane;
     const int pq = p / cchunk;
-    const int c = (wave + nw * pq) * cchunk + (p - pq * cchunk);
+    const int c = c_begin + (wave + nw * pq) * cchunk + (p - pq * cchunk);
     Cand cd{0, -1, -1, -1};
     float Ix[3] = {0.0f, 0.0f, 0.0f}, Iy[3] = {0.0f, 0.0f, 0.0f};
     bool keep = false;

@@ -69,6 +69,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
                                                         float* __restrict__ loss_part, int loss_kind,
                                                         float log_eps) {
   __shared__ float red[NW][2][kWave];
+  __shared__ float base[NW][kWave];  // each wavefront's power sum over the orders 0 and 1
   extern __shared__ float fwd_boxes[];  // [NW][6 (max_order + 1)][64] leg boxes of screened candidates
   const SceneView S = view_of(A);
   const int lane = threadIdx.x & (kWave - 1);
@@ -88,20 +89,34 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   float sum = 0.0f, comp = 0.0f;
   const RxBox box = rx_box(rxx, rxy, live);
   float* boxes = fwd_boxes + wave * 6 * (A.max_order + 1) * kWave;
-  for_screened(S.walls, A.n_walls, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
-                  S.cull_c, boxes, [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
-                 const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j);
-                 kahan_add(sum, comp, v);
-                 if (cache_c && ballot(v != 0.0f) != 0) {
-                   if (nst < A.cache_cap) {
-                     cache_c[(size_t)nst * kWave + lane] = v;
-                     if (lane == 0) cache_idx[nst] = c;
-                     if (lane < A.box_stride)
-                       A.cache_box[((size_t)slot * A.cache_cap + nst) * A.box_stride + lane] = boxes[lane * kWave + j];
-                   }
-                   ++nst;
-                 }
-               });
+  // The contribution cut compares each candidate with a lower bound of the
+  // lane's P(r): first the orders 0 and 1 (shared by the wavefronts through
+  // LDS once all have them), then this wavefront's own running sum on top.
+  float cut_base = 0.0f, own1 = 0.0f;
+  auto visit = [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
+    const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
+                                              A.cut * (cut_base + (sum - comp) - own1));
+    kahan_add(sum, comp, v);
+    if (cache_c && ballot(v != 0.0f) != 0) {
+      if (nst < A.cache_cap) {
+        cache_c[(size_t)nst * kWave + lane] = v;
+        if (lane == 0) cache_idx[nst] = c;
+        if (lane < A.box_stride)
+          A.cache_box[((size_t)slot * A.cache_cap + nst) * A.box_stride + lane] = boxes[lane * kWave + j];
+      }
+      ++nst;
+    }
+  };
+  const int n1 = min(A.n_cand, 1 + A.n_walls);
+  for_screened(S.walls, A.n_walls, 0, n1, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box, S.cull_c,
+               boxes, visit);
+  own1 = sum - comp;
+  base[wave][lane] = own1;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
+  for_screened(S.walls, A.n_walls, n1, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
+               S.cull_c, boxes, visit);
   if (cache_c && lane == 0) A.cache_n[slot] = nst <= A.cache_cap ? nst : -1;
   red[wave][0][lane] = sum;
   red[wave][1][lane] = comp;
@@ -172,12 +187,20 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
         candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
       }
     } else {
+      // re-evaluation of this wavefront's share as the forward split it (the
+      // orders 0 and 1, then the rest), the cut against its own running sum
+      float sum = 0.0f, comp = 0.0f;
+      const int n1 = min(A.n_cand, 1 + A.n_walls);
       const int stride = NW * A.cchunk;
-      for (int c0 = wave * A.cchunk; c0 < A.n_cand; c0 += stride) {
-        const int c1 = min(c0 + A.cchunk, A.n_cand);
-        for (int c = c0; c < c1; ++c) {
-          const Cand cd = decode_candidate(c, A.n_walls);
-          candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G);
+      for (int part = 0; part < 2; ++part) {
+        const int b0 = part ? n1 : 0, b1 = part ? A.n_cand : n1;
+        for (int c0 = b0 + wave * A.cchunk; c0 < b1; c0 += stride) {
+          const int c1 = min(c0 + A.cchunk, b1);
+          for (int c = c0; c < c1; ++c) {
+            const Cand cd = decode_candidate(c, A.n_walls);
+            kahan_add(sum, comp,
+                      candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, A.cut * (sum - comp)));
+          }
         }
       }
     }

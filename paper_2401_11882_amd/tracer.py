@@ -117,6 +117,11 @@ def set_screen(enabled: bool) -> None:
     check(lib().drt_set_screen(1 if enabled else 0))
 
 
+def set_cut(enabled: bool) -> None:
+    """Contribution cut on/off (process-wide; on by default); see drt_set_cut."""
+    check(lib().drt_set_cut(1 if enabled else 0))
+
+
 def cache_lists(scene: Scene) -> list[list[int]]:
     """Per wavefront slot, the candidates the last seeded forward recorded as
     nonzero (None for a slot that overflowed); reads the shared workspace."""

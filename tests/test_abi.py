@@ -133,6 +133,7 @@ def test_call_validation_before_launch():
     empty = _scene(n_rx=0, rx_dev=None, rx_grid_nx=0)
     assert L.drt_forward(ctypes.byref(empty), 3, 1e-6, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL
     assert L.drt_set_screen(2) == _lib.DRT_EINVAL
+    assert L.drt_set_cut(-1) == _lib.DRT_EINVAL
     # launch config knob
     assert L.drt_set_launch_config(3, 0) == _lib.DRT_EINVAL
     assert L.drt_set_launch_config(0, -1) == _lib.DRT_EINVAL

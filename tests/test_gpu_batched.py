@@ -130,6 +130,27 @@ def test_batched_screen_exact():
         assert torch.equal(x, y)
 
 
+def test_batched_cut_within_bound():
+    """Batched contribution cut: power within C 2^-44 P (+ FP32 rounding) of the
+    uncut power, gradients to FP32 accuracy."""
+    batched, tr = _mods()
+    scenes = _small_mixed() + WL.batch_scenes(8, side_cap=32)
+    out = {}
+    try:
+        for on in (True, False):
+            tr.set_cut(on)
+            plan = batched.BatchPlan(scenes, 2)
+            out[on] = [t.clone() for t in plan.run()]
+            plan.close()
+    finally:
+        tr.set_cut(True)
+    C = max(tr.num_candidates(int(s.walls.shape[0]), 2) for s in scenes)
+    for x, y in zip(out[True], out[False]):
+        if x.numel() == 0:
+            continue
+        torch.testing.assert_close(x, y, rtol=max(C * 2.0 ** -44, 1e-4), atol=1e-5 * float(y.abs().max()))
+
+
 def test_autotune_and_cache(tmp_path):
     batched, tr = _mods()
     scenes = WL.batch_scenes(24, side_cap=32)

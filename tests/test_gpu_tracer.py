@@ -228,6 +228,35 @@ def test_screen_drops_only_zero_candidates(case):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("case", ["box64_a10", "box64_a100", "box64_a1000", "order3"])
+def test_contribution_cut_within_bound(case):
+    """The contribution cut drops, per receiver, terms that add up to at most
+    C 2^-44 P(r) (C candidates): the power with the cut stays within that bound
+    (plus FP32 rounding) of the uncut power, and the gradients agree to FP32
+    accuracy.  The cut never raises a power."""
+    tr = _tr()
+    if case == "order3":
+        s = WL.scene_32_order3(grid_n=64)
+    else:
+        s = WL.scene_64(grid_n=128, alpha=float(case.split("_a")[1]))
+    sc = _scene(s)
+    res = {}
+    try:
+        for on in (True, False):
+            tr.set_cut(on)
+            out = tr.forward_backward(sc, loss="neg_mean_log", want_rx=True)
+            res[on] = [t.clone() for t in out]
+    finally:
+        tr.set_cut(True)
+    C = tr.num_candidates(int(s.walls.shape[0]), int(s.max_order))
+    Pc, Pe = res[True][0].double(), res[False][0].double()
+    assert bool((Pc <= Pe * (1 + 1e-6)).all())
+    bound = C * 2.0 ** -44 + 2e-6
+    assert float(((Pe - Pc).abs() / Pe.clamp_min(1e-30)).max()) <= bound
+    for x, y in zip(res[True][2:], res[False][2:]):
+        torch.testing.assert_close(x, y, rtol=1e-4, atol=1e-5 * float(y.abs().max()))
+
+
 def test_deterministic_repeat():
     tr = _tr()
     s = WL.scene_random_box(2, 16, 32, 2, 100.0, seed=4)
