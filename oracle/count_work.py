@@ -29,7 +29,10 @@ from paper_2401_11882_amd import workloads as WL  # noqa: E402
 # work whose result can change the output is counted: an obstruction test
 # whose smoothed factor is 1.0f in FP32 (saturated) and the obstruction tests
 # of a pair whose interaction factor is exactly 0 count nothing, however an
-# implementation proves them away.
+# implementation proves them away.  In 2D, a pair or test whose contribution
+# is bounded by 2^-44 P(r) (the receiver's full power) counts nothing either:
+# the kernels skip only work bounded by 2^-44 times a lower bound of P(r),
+# so the model never credits work they do not do.
 WEIGHTS = {
     "fwd_per_path_eval": 13,           # |r - I_k|^2, floor, divide, compensated sum
     "fwd_per_interaction": 20,         # back-trace step (needed to decide the factor)
@@ -71,13 +74,16 @@ def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--sample", type=int, default=256)
     ap.add_argument("--alphas", default="10,100,1000")
+    ap.add_argument("--cut", type=float, default=2.0 ** -44,
+                    help="2D contribution cut factor: pairs and tests that can change P(r) by at most cut P(r) "
+                         "count nothing (the kernels drop only what lies below cut times a lower bound of P)")
     args = ap.parse_args()
     out = {"workload": "box + 64 segments, 256x256 receivers, order <= 2 (4,625 candidates)",
-           "sample_receivers": args.sample, "weights": WEIGHTS, "per_alpha": {}}
+           "sample_receivers": args.sample, "cut": args.cut, "weights": WEIGHTS, "per_alpha": {}}
     for a in [float(x) for x in args.alphas.split(",")]:
         s = WL.scene_64(alpha=a)
         idx = np.random.default_rng(11882).choice(s.n_rx, size=args.sample, replace=False)
-        c = T.work_counts(s.walls, s.tx, s.rx[idx], s.max_order, a)
+        c = T.work_counts(s.walls, s.tx, s.rx[idx], s.max_order, a, cut=args.cut)
         out["per_alpha"][str(int(a))] = model(c, WEIGHTS)
         print(a, json.dumps(out["per_alpha"][str(int(a))]), flush=True)
     s3 = WL.scene3d_32()
