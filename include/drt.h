@@ -142,7 +142,9 @@ int drt_set_cache_limit(int64_t bytes);
 int drt_set_screen(int32_t enabled);
 
 /* Contribution cut on (1, default) or off (0), for the 2D calls (single
-   scene and batched).  With the cut on, a receiver drops a candidate as soon
+   scene and batched) and the 3D calls with the sigmoid smoothing (hard-sigmoid
+   factors are already exactly 0 beyond a band of 3/alpha; those calls never
+   cut).  With the cut on, a receiver drops a candidate as soon
    as the candidate's contribution is provably at most 2^-44 times a lower
    bound of that receiver's power: the sum of its order-0 and order-1
    contributions plus the running sum of the candidates already evaluated by

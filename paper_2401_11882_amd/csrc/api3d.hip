@@ -1,5 +1,6 @@
 // C ABI of the 3D tracer (scenes of parallelogram panels): argument checks,
 // workspace layout, launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,6 +14,7 @@
 extern "C" __attribute__((visibility("hidden"))) int drt_internal_fail(int code, const char* msg);
 extern "C" __attribute__((visibility("hidden"))) int64_t drt_internal_cache_limit(void);
 extern "C" __attribute__((visibility("hidden"))) int drt_internal_screen(void);
+extern "C" __attribute__((visibility("hidden"))) int drt_internal_cut(void);
 
 namespace {
 
@@ -100,9 +102,11 @@ Plan3 make_plan3(const drt3_scene* s) {
   off = align_up(off + sizeof(float) * (size_t)p.ncol * T1);
   p.off_tmp = off;
   off = align_up(off + sizeof(float) * drt::kPanelGrad * P1);
-  // contribution cache: a wavefront meets at most ceil(C / nw) candidates
+  // contribution cache: a wavefront meets at most ceil(n1 / nw) + ceil((C - n1) / nw)
+  // candidates (orders 0-1, n1 = 1 + P of them, then the rest)
   const int64_t n_cand = count_candidates(s->n_panels, s->max_order);
-  const int64_t per_wave = (n_cand + p.nw - 1) / p.nw;
+  const int64_t n1 = std::min<int64_t>(n_cand, 1 + (int64_t)s->n_panels);
+  const int64_t per_wave = (n1 + p.nw - 1) / p.nw + (n_cand - n1 + p.nw - 1) / p.nw;
   const int64_t slots = (int64_t)p.n_tiles * p.nw;
   p.mask_nb = s->n_panels > 0 ? (s->n_panels + drt::kWave - 1) / drt::kWave : 1;
   p.mask_stride = (s->max_order + 1) * p.mask_nb;
@@ -137,6 +141,7 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   A.mode = hard ? 1 : 0;
   A.cull_c = (hard ? drt::kHardCullMargin : drt::kCullMargin) / s->alpha;
   A.screen = drt_internal_screen();
+  A.cut = drt_internal_cut() ? drt::kCut : 0.0f;
   A.tx = s->tx_dev;
   A.rx = s->rx_dev;
   A.n_panels = s->n_panels;

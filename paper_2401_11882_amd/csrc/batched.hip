@@ -125,16 +125,19 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
         ++nst;
       }
     };
-    const int n1 = min(n_cand, 1 + W);
-    for_screened(S.walls, W, 0, n1, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box, S.cull_c, boxes,
-                 visit);
-    own1 = sum - comp;
-    base[wave][lane] = own1;
-    __syncthreads();
+    const int n1 = uses_cut<MODE>() ? min(n_cand, 1 + W) : 0;
+#pragma nounroll
+    for (int ph = uses_cut<MODE>() ? 0 : 1; ph < 2; ++ph) {
+      for_screened(S.walls, W, ph ? n1 : 0, ph ? n_cand : n1, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx,
+                   txy, box, S.cull_c, boxes, visit);
+      if (ph == 0) {
+        own1 = sum - comp;
+        base[wave][lane] = own1;
+        __syncthreads();
 #pragma unroll
-    for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
-    for_screened(S.walls, W, n1, n_cand, S.dead_lim, B.screen != 0, wave, NW, B.cchunk, txx, txy, box, S.cull_c,
-                 boxes, visit);
+        for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
+      }
+    }
     red[(wave * 2 + 0) * kWave + lane] = sum;
     red[(wave * 2 + 1) * kWave + lane] = comp;
     __syncthreads();
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
       // re-evaluation of this wavefront's share as the forward split it, the
       // cut against its own running sum
       float rs = 0.0f, rc = 0.0f;
-      const int n1 = min(n_cand, 1 + W);
+      const int n1 = uses_cut<MODE>() ? min(n_cand, 1 + W) : 0;
       const int stride = NW * B.cchunk;
       for (int part = 0; part < 2; ++part) {
         const int b0 = part ? n1 : 0, b1 = part ? n_cand : n1;

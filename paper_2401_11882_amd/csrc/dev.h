@@ -99,6 +99,14 @@ __device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f
 // C = 45,397), far below the FP32 rounding of P itself.
 constexpr float kCut = 0x1p-44f;
 
+// The cut serves the sigmoid smoothing.  Hard-sigmoid factors are already
+// exactly 0 beyond a band of 3 / alpha, so those kernels are built without
+// the cut and visit candidates in plain order (no first phase of orders 0-1).
+template <int MODE>
+constexpr bool uses_cut() {
+  return MODE == kSigmoid;
+}
+
 // Lane l's 64-bit value (l wave-uniform).
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);

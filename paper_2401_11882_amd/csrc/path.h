@@ -415,7 +415,7 @@ __device__ __forceinline__ float obstruct_all(const SceneView& S, const Path<K>&
     }
     // a lane whose product fell to its cut contributes nothing; once every
     // lane's product is 0 no further factor can change it
-    V = V > vcut ? V : 0.0f;
+    if constexpr (uses_cut<MODE>()) V = V > vcut ? V : 0.0f;
     return ballot(upd) == 0 || ballot(V != 0.0f) != 0;
   });
   return V;
@@ -451,12 +451,18 @@ __device__ __forceinline__ float path_power_img(const SceneView& S, const Cand& 
   }
   if (!back_trace<K, true, MODE>(S, rxx, rxy, live, P)) return 0.0f;
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
-  const float dd = fmaxf(fmaf(ex, ex, ey * ey), S.dmin2);
-  const float vcut = scut * dd;  // the contribution V / dd is below the cut once V <= vcut
-  P.F = P.F > vcut ? P.F : 0.0f;
-  if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all<K, MODE>(S, P, P.F, boxes, j, vcut);
-  return V / dd;
+  if constexpr (!uses_cut<MODE>()) {
+    if (ballot(P.F != 0.0f) == 0) return 0.0f;
+    const float V = obstruct_all<K, MODE>(S, P, P.F, boxes, j);
+    return V / fmaxf(fmaf(ex, ex, ey * ey), S.dmin2);
+  } else {
+    const float dd = fmaxf(fmaf(ex, ex, ey * ey), S.dmin2);
+    const float vcut = scut * dd;  // the contribution V / dd is below the cut once V <= vcut
+    P.F = P.F > vcut ? P.F : 0.0f;
+    if (ballot(P.F != 0.0f) == 0) return 0.0f;
+    const float V = obstruct_all<K, MODE>(S, P, P.F, boxes, j, vcut);
+    return V / dd;
+  }
 }
 
 // Per-wave accumulator layout: [0,1] = d/dtx, [2 + 4j + c] = d/d walls[j][c].
@@ -685,7 +691,7 @@ __device__ __forceinline__ float path_adjoint(const SceneView& S, const Cand& cd
   const float ex = rxx - P.Ix[K], ey = rxy - P.Iy[K];
   const float dd = fmaxf(fmaf(ex, ex, ey * ey), S.dmin2);
   const float vcut = scut * dd;
-  P.F = P.F > vcut ? P.F : 0.0f;
+  if constexpr (uses_cut<MODE>()) P.F = P.F > vcut ? P.F : 0.0f;
   // lanes with g = 0 need neither their contribution nor their gradient
   if (ballot(P.F != 0.0f && g != 0.0f) == 0) return 0.0f;
   const float V = obstruct_all<K, MODE>(S, P, P.F, nullptr, 0, vcut);

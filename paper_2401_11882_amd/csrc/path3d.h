@@ -354,7 +354,7 @@ __device__ __forceinline__ void visit_panels(const Scene3View& S, const Path3<K>
 
 template <int K, int MODE>
 __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<K>& P, float V,
-                                               uint64_t* mask_out = nullptr) {
+                                               uint64_t* mask_out = nullptr, float vcut = 0.0f) {
   const bool act = P.F != 0.0f;
   LegBox3 B[K + 1];
   if (S.boxes) {
@@ -380,7 +380,9 @@ __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<
         upd = true;
       }
     }
-    // once every lane's product is exactly 0 no further factor can change it
+    // a lane whose product fell to its cut contributes nothing; once every
+    // lane's product is 0 no further factor can change it
+    if constexpr (uses_cut<MODE>()) V = V > vcut ? V : 0.0f;
     return ballot(upd) == 0 || ballot(V != 0.0f) != 0;
   }, mask_out);
   return V;
@@ -388,14 +390,23 @@ __device__ __forceinline__ float obstruct_all3(const Scene3View& S, const Path3<
 
 template <int K, int MODE>
 __device__ __forceinline__ float path_power3(const Scene3View& S, const Cand& cd, float tx, float ty, float tz,
-                                             float rx, float ry, float rz, bool live, uint64_t* mask_out) {
+                                             float rx, float ry, float rz, bool live, uint64_t* mask_out,
+                                             float scut) {
   Path3<K> P;
   if (!setup3<K, true, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, P)) return 0.0f;
-  if (ballot(P.F != 0.0f) == 0) return 0.0f;
-  const float V = obstruct_all3<K, MODE>(S, P, P.F, mask_out);
   const float ex = rx - P.Ix[K], ey = ry - P.Iy[K], ez = rz - P.Iz[K];
-  const float d2 = dot3(ex, ey, ez, ex, ey, ez);
-  return V / fmaxf(d2, S.dmin2);
+  if constexpr (!uses_cut<MODE>()) {
+    if (ballot(P.F != 0.0f) == 0) return 0.0f;
+    const float V = obstruct_all3<K, MODE>(S, P, P.F, mask_out);
+    return V / fmaxf(dot3(ex, ey, ez, ex, ey, ez), S.dmin2);
+  } else {
+    const float dd = fmaxf(dot3(ex, ey, ez, ex, ey, ez), S.dmin2);
+    const float vcut = scut * dd;  // the contribution V / dd is below the cut once V <= vcut
+    P.F = P.F > vcut ? P.F : 0.0f;
+    if (ballot(P.F != 0.0f) == 0) return 0.0f;
+    const float V = obstruct_all3<K, MODE>(S, P, P.F, mask_out, vcut);
+    return V / dd;
+  }
 }
 
 // Per-wave accumulator layout: [0..2] = d/dtx, [3 + 13 j + f] = d/d record of
@@ -649,16 +660,17 @@ __device__ __forceinline__ void path_adjoint3_known(const Scene3View& S, const C
 }
 
 // Contribution of candidate cd at this lane; with mask_out, its culling masks
-// are kept there (see visit_panels).
+// are kept there (see visit_panels).  A lane drops the candidate (returns 0)
+// once its contribution is provably <= scut (the contribution cut).
 template <int MODE>
 __device__ __forceinline__ float candidate_power3(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                   float tz, float rx, float ry, float rz, bool live,
-                                                  uint64_t* mask_out = nullptr) {
+                                                  uint64_t* mask_out = nullptr, float scut = 0.0f) {
   switch (cd.k) {
-    case 0: return path_power3<0, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
-    case 1: return path_power3<1, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
-    case 2: return path_power3<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
-    default: return path_power3<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out);
+    case 0: return path_power3<0, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
+    case 1: return path_power3<1, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
+    case 2: return path_power3<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
+    default: return path_power3<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
   }
 }
 

@@ -192,16 +192,16 @@ __device__ __forceinline__ bool screen_candidate3(const PanelRec* panels, float 
 }
 
 // Calls fn(c, cd) (wave-uniform) for every candidate of this wavefront's
-// share (c = wave + nw p, p = 0, 1, ...) that survives the screen, in
-// increasing order.
+// share of [c_begin, n_cand) (c = c_begin + wave + nw p, p = 0, 1, ...) that
+// survives the screen, in increasing order.
 template <class Fn>
-__device__ __forceinline__ void for_screened3(const PanelRec* panels, int n_panels, int n_cand, float lim, bool test,
-                                              int wave, int nw, float tx, float ty, float tz, const RxBox3& B,
-                                              Fn&& fn) {
+__device__ __forceinline__ void for_screened3(const PanelRec* panels, int n_panels, int c_begin, int n_cand,
+                                              float lim, bool test, int wave, int nw, float tx, float ty, float tz,
+                                              const RxBox3& B, Fn&& fn) {
   if (B.empty) return;
   const int lane = __lane_id();
-  for (int p0 = 0; wave + nw * p0 < n_cand; p0 += kWave) {
-    const int c = wave + nw * (p0 + lane);
+  for (int p0 = 0; c_begin + wave + nw * p0 < n_cand; p0 += kWave) {
+    const int c = c_begin + wave + nw * (p0 + lane);
     Cand cd{0, -1, -1, -1};
     bool keep = false;
     if (c < n_cand) {

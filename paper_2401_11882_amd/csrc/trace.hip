@@ -107,16 +107,21 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
       ++nst;
     }
   };
-  const int n1 = min(A.n_cand, 1 + A.n_walls);
-  for_screened(S.walls, A.n_walls, 0, n1, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box, S.cull_c,
-               boxes, visit);
-  own1 = sum - comp;
-  base[wave][lane] = own1;
-  __syncthreads();
+  // phase 0: candidates [0, n1) (orders 0-1), phase 1: [n1, C); one copy of
+  // the candidate code serves both (the loop is not unrolled)
+  const int n1 = uses_cut<MODE>() ? min(A.n_cand, 1 + A.n_walls) : 0;
+#pragma nounroll
+  for (int ph = uses_cut<MODE>() ? 0 : 1; ph < 2; ++ph) {
+    for_screened(S.walls, A.n_walls, ph ? n1 : 0, ph ? A.n_cand : n1, S.dead_lim, A.screen != 0, wave, NW,
+                 A.cchunk, txx, txy, box, S.cull_c, boxes, visit);
+    if (ph == 0) {
+      own1 = sum - comp;
+      base[wave][lane] = own1;
+      __syncthreads();
 #pragma unroll
-  for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
-  for_screened(S.walls, A.n_walls, n1, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
-               S.cull_c, boxes, visit);
+      for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
+    }
+  }
   if (cache_c && lane == 0) A.cache_n[slot] = nst <= A.cache_cap ? nst : -1;
   red[wave][0][lane] = sum;
   red[wave][1][lane] = comp;
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
       // re-evaluation of this wavefront's share as the forward split it (the
       // orders 0 and 1, then the rest), the cut against its own running sum
       float sum = 0.0f, comp = 0.0f;
-      const int n1 = min(A.n_cand, 1 + A.n_walls);
+      const int n1 = uses_cut<MODE>() ? min(A.n_cand, 1 + A.n_walls) : 0;
       const int stride = NW * A.cchunk;
       for (int part = 0; part < 2; ++part) {
         const int b0 = part ? n1 : 0, b1 = part ? A.n_cand : n1;

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
                                                          float* __restrict__ seed, float* __restrict__ loss_part,
                                                          int loss_kind, float log_eps) {
   __shared__ float red[NW][2][kWave];
+  __shared__ float base[NW][kWave];  // per-wave sums of orders 0-1
   __shared__ uint64_t mrec[NW][16];  // culling masks of the candidate being evaluated
   const Scene3View S = view3_of(A);
   const int lane = threadIdx.x & (kWave - 1);
@@ -113,21 +114,43 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   const RxBox3 box = rx_box3(rx, ry, rz, live);
   // parameter range beyond which an interaction factor is exactly 0
   const float lim = (MODE == kHardSigmoid ? kHardBandMargin / A.alpha : 128.0f / A.a2) * 1.00001f;
-  for_screened3(A.panels, A.n_panels, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box,
-                [&](int c, const Cand& cd) {
-                  const float v =
-                      candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr);
-                  kahan_add(sum, comp, v);
-                  if (cache_c && ballot(v != 0.0f) != 0) {
-                    if (nst < A.cache_cap) {
-                      cache_c[(size_t)nst * kWave + lane] = v;
-                      if (lane == 0) cache_idx[nst] = c;
-                      if (lane < A.mask_stride)
-                        A.cache_mask[((size_t)slot * A.cache_cap + nst) * A.mask_stride + lane] = mrec[wave][lane];
-                    }
-                    ++nst;
-                  }
-                });
+  // Contribution cut: every term is >= 0, so the orders 0-1 of all wavefronts
+  // (summed through LDS after the first phase) plus this wavefront's running
+  // sum of the later candidates bound P(r) from below.
+  float cut_base = 0.0f, own1 = 0.0f;
+  auto visit = [&](int c, const Cand& cd) {
+    const float v = candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr,
+                                           A.cut * (cut_base + (sum - comp) - own1));
+    kahan_add(sum, comp, v);
+    if (cache_c && ballot(v != 0.0f) != 0) {
+      if (nst < A.cache_cap) {
+        cache_c[(size_t)nst * kWave + lane] = v;
+        if (lane == 0) cache_idx[nst] = c;
+        if (lane < A.mask_stride)
+          A.cache_mask[((size_t)slot * A.cache_cap + nst) * A.mask_stride + lane] = mrec[wave][lane];
+      }
+      ++nst;
+    }
+  };
+  // phase 0: candidates [0, n1) (orders 0-1), phase 1: [n1, C); one copy of
+  // the candidate code serves both (the loop is not unrolled)
+  if constexpr (!uses_cut<MODE>()) {
+    for_screened3(A.panels, A.n_panels, 0, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box, visit);
+  } else {
+    const int n1 = min(A.n_cand, 1 + A.n_panels);
+#pragma nounroll
+    for (int ph = 0; ph < 2; ++ph) {
+      for_screened3(A.panels, A.n_panels, ph ? n1 : 0, ph ? A.n_cand : n1, lim, A.screen != 0, wave, NW, tx, ty,
+                    tz, box, visit);
+      if (ph == 0) {
+        own1 = sum - comp;
+        base[wave][lane] = own1;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
+      }
+    }
+  }
   if (cache_c && lane == 0) A.cache_n[slot] = nst <= A.cache_cap ? nst : -1;
   red[wave][0][lane] = sum;
   red[wave][1][lane] = comp;
@@ -190,13 +213,28 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
             lane < A.mask_stride ? A.cache_mask[((size_t)slot * A.cache_cap + p) * A.mask_stride + lane] : 0;
         candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, &masks);
       }
-    } else {
+    } else if constexpr (!uses_cut<MODE>()) {
       for (int c = wave; c < A.n_cand; c += NW) {
         const Cand cd = decode_candidate(c, A.n_panels);
-        const float v = candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live);
-        const float Wl = g * v;
+        const float Wl = g * candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live);
         if (ballot(Wl != 0.0f) == 0) continue;
         candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
+      }
+    } else {
+      // re-evaluation over the forward's share of candidates (orders 0-1,
+      // then the rest), cut against this wavefront's own running sum
+      const int n1 = min(A.n_cand, 1 + A.n_panels);
+      float rs = 0.0f, rc = 0.0f;
+      for (int part = 0; part < 2; ++part) {
+        const int c0 = part == 0 ? 0 : n1, c1 = part == 0 ? n1 : A.n_cand;
+        for (int c = c0 + wave; c < c1; c += NW) {
+          const Cand cd = decode_candidate(c, A.n_panels);
+          const float v = candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, nullptr, A.cut * (rs - rc));
+          kahan_add(rs, rc, v);
+          const float Wl = g * v;
+          if (ballot(Wl != 0.0f) == 0) continue;
+          candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
+        }
       }
     }
   }

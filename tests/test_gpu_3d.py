@@ -176,6 +176,37 @@ def test_panel_culling_changes_no_bit(alpha):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("alpha", [10.0, 100.0])
+def test_contribution_cut_within_bound_3d(alpha):
+    """3D contribution cut: the power stays within C 2^-44 P(r) (+ FP32
+    rounding) of the uncut power and never above it; gradients (tx, panels,
+    receivers) agree to FP32 accuracy.  The overflow path of the contribution
+    cache (re-evaluation) is covered too."""
+    from paper_2401_11882_amd import tracer as tr
+    tr3 = _tr3()
+    s = WL.scene3d_room(9, 12, 16, 2, alpha, seed=21)
+    sc = _scene(s)
+    C = tr.num_candidates(s.panels.shape[0], 2)   # same count for panels as for walls
+    res = {}
+    try:
+        for on in (True, False):
+            tr.set_cut(on)
+            res[on] = [t.clone() for t in tr3.forward_backward(sc, loss="neg_mean_log", want_rx=True)]
+        tr.set_cut(True)
+        tr.set_cache_limit(1 << 16)   # most wavefronts overflow and re-evaluate
+        res["reeval"] = [t.clone() for t in tr3.forward_backward(sc, loss="neg_mean_log", want_rx=True)]
+    finally:
+        tr.set_cut(True)
+        tr.set_cache_limit(32 << 30)
+    Pc, Pe = res[True][0].double(), res[False][0].double()
+    assert bool((Pc <= Pe * (1 + 1e-6)).all())
+    assert float(((Pe - Pc).abs() / Pe.clamp_min(1e-30)).max()) <= C * 2.0 ** -44 + 2e-6
+    assert torch.equal(res["reeval"][0], res[True][0])
+    for other in (res[False], res["reeval"]):
+        for x, y in zip(res[True][2:], other[2:]):
+            torch.testing.assert_close(x, y, rtol=1e-4, atol=1e-5 * float(y.abs().max()))
+
+
 def test_maximum_panel_count_sampled():
     """DRT3_MAX_PANELS panels (room + 250 rectangles, four 64-panel batches in
     the culling masks), order <= 1, a 16 x 16 grid: sampled receivers and a

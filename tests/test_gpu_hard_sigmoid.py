@@ -128,3 +128,20 @@ def test_batched_matches_single():
     _, kap = PU.kappa(s.walls, s.tx, s.rx[::37], 2, 50.0, P0=P_o, mode=HS)
     rs, _ = plan.scene_slice(3)
     PU.check_power(P[rs].cpu().numpy()[::37], P_o, kap, "batched hard")
+
+
+def test_cut_switch_leaves_hard_sigmoid_unchanged():
+    """The contribution cut applies to the sigmoid smoothing only: with the
+    hard sigmoid every output is bitwise the same with the cut on and off."""
+    tr = _tr()
+    s = WL.scene_64(grid_n=128, alpha=50.0)
+    sc = _scene(s)
+    res = {}
+    try:
+        for on in (True, False):
+            tr.set_cut(on)
+            res[on] = [t.clone() for t in tr.forward_backward(sc, loss="neg_mean_log", want_rx=True)]
+    finally:
+        tr.set_cut(True)
+    for x, y in zip(res[True], res[False]):
+        assert torch.equal(x, y)
