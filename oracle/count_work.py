@@ -29,8 +29,8 @@ from paper_2401_11882_amd import workloads as WL  # noqa: E402
 # work whose result can change the output is counted: an obstruction test
 # whose smoothed factor is 1.0f in FP32 (saturated) and the obstruction tests
 # of a pair whose interaction factor is exactly 0 count nothing, however an
-# implementation proves them away.  In 2D, a pair or test whose contribution
-# is bounded by 2^-44 P(r) (the receiver's full power) counts nothing either:
+# implementation proves them away.  A pair or test whose contribution is
+# bounded by 2^-44 P(r) (the receiver's full power) counts nothing either:
 # the kernels skip only work bounded by 2^-44 times a lower bound of P(r),
 # so the model never credits work they do not do.
 WEIGHTS = {
@@ -75,7 +75,7 @@ def main() -> None:
     ap.add_argument("--sample", type=int, default=256)
     ap.add_argument("--alphas", default="10,100,1000")
     ap.add_argument("--cut", type=float, default=2.0 ** -44,
-                    help="2D contribution cut factor: pairs and tests that can change P(r) by at most cut P(r) "
+                    help="contribution cut factor: pairs and tests that can change P(r) by at most cut P(r) "
                          "count nothing (the kernels drop only what lies below cut times a lower bound of P)")
     args = ap.parse_args()
     out = {"workload": "box + 64 segments, 256x256 receivers, order <= 2 (4,625 candidates)",
@@ -88,7 +88,7 @@ def main() -> None:
         print(a, json.dumps(out["per_alpha"][str(int(a))]), flush=True)
     s3 = WL.scene3d_32()
     idx = np.random.default_rng(11882).choice(s3.n_rx, size=args.sample, replace=False)
-    c3 = T3.work_counts(s3.panels, s3.tx, s3.rx[idx], s3.max_order, s3.alpha)
+    c3 = T3.work_counts(s3.panels, s3.tx, s3.rx[idx], s3.max_order, s3.alpha, cut=args.cut)
     out["scene3d"] = {"workload": "room + 32 rectangles (38 panels), 256x256 receivers, order <= 2 (1,445 candidates)",
                       "weights": WEIGHTS_3D, "per_alpha": {str(int(s3.alpha)): model(c3, WEIGHTS_3D)}}
     print("3d", json.dumps(out["scene3d"]["per_alpha"]), flush=True)
