@@ -144,17 +144,17 @@ int drt_set_screen(int32_t enabled);
 /* Contribution cut on (1, default) or off (0), for the 2D calls (single
    scene and batched) and the 3D calls with the sigmoid smoothing (hard-sigmoid
    factors are already exactly 0 beyond a band of 3/alpha; those calls never
-   cut).  With the cut on, a receiver drops a candidate as soon
-   as the candidate's contribution is provably at most 2^-44 times a lower
-   bound of that receiver's power: the sum of its order-0 and order-1
-   contributions plus the running sum of the candidates already evaluated by
-   the same wavefront (every term is >= 0).  The forward may stop a
-   candidate's obstruction tests there; the dropped terms of a receiver add up
-   to at most C 2^-44 P(r) for C candidates (3e-10 P at C = 4,625), far below
-   the FP32 rounding of P.  Decisions depend only on the receiver, the
-   candidate order and the launch shape, so results stay deterministic; the
-   adjoint differentiates what the forward summed.  Turning the cut off gives
-   the exact (uncut) sums, to verify the bound.  Process-wide. */
+   cut).  With the cut on, a receiver drops a candidate as soon as the
+   candidate's contribution is provably at most 2^-24 / C times a lower bound
+   of that receiver's power, C being the scene's candidate count; the bound is
+   the sum of its order-0 and order-1 contributions plus the running sum of the
+   candidates already evaluated by the same wavefront (every term is >= 0).
+   The forward may stop a candidate's obstruction tests there.  The dropped
+   terms of a receiver add up to at most 2^-24 P(r): no more than one FP32
+   rounding of P.  Decisions depend only on the receiver, the candidate order
+   and the launch shape, so results stay deterministic; the adjoint
+   differentiates what the forward summed.  Turning the cut off gives the
+   exact (uncut) sums, to verify the bound.  Process-wide. */
 int drt_set_cut(int32_t enabled);
 
 /* Workspace bytes that drt_forward / drt_backward / drt_forward_backward

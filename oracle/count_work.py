@@ -30,9 +30,10 @@ from paper_2401_11882_amd import workloads as WL  # noqa: E402
 # whose smoothed factor is 1.0f in FP32 (saturated) and the obstruction tests
 # of a pair whose interaction factor is exactly 0 count nothing, however an
 # implementation proves them away.  A pair or test whose contribution is
-# bounded by 2^-44 P(r) (the receiver's full power) counts nothing either:
-# the kernels skip only work bounded by 2^-44 times a lower bound of P(r),
-# so the model never credits work they do not do.
+# bounded by 2^-24 P(r) / C (P the receiver's full power, C the scene's
+# candidate count) counts nothing either: the kernels skip only work bounded
+# by 2^-24 / C times a lower bound of P(r), so the model never credits work
+# they do not do.
 WEIGHTS = {
     "fwd_per_path_eval": 13,           # |r - I_k|^2, floor, divide, compensated sum
     "fwd_per_interaction": 20,         # back-trace step (needed to decide the factor)
@@ -57,6 +58,11 @@ WEIGHTS_3D = {
 }
 
 
+def n_candidates(n: int, max_order: int) -> int:
+    """Interaction sequences of length <= max_order over n surfaces, no surface twice in a row."""
+    return 1 + sum(n * (n - 1) ** (k - 1) for k in range(1, max_order + 1))
+
+
 def model(counts: dict, W: dict) -> dict:
     n = counts["path_evals"]
     per = {k: v / n for k, v in counts.items()}
@@ -74,21 +80,23 @@ def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--sample", type=int, default=256)
     ap.add_argument("--alphas", default="10,100,1000")
-    ap.add_argument("--cut", type=float, default=2.0 ** -44,
-                    help="contribution cut factor: pairs and tests that can change P(r) by at most cut P(r) "
-                         "count nothing (the kernels drop only what lies below cut times a lower bound of P)")
+    ap.add_argument("--cut-total", type=float, default=2.0 ** -24,
+                    help="contribution cut: pairs and tests that can change P(r) by at most cut_total P(r) / C "
+                         "count nothing (the kernels drop only what lies below that times a lower bound of P)")
     args = ap.parse_args()
     out = {"workload": "box + 64 segments, 256x256 receivers, order <= 2 (4,625 candidates)",
-           "sample_receivers": args.sample, "cut": args.cut, "weights": WEIGHTS, "per_alpha": {}}
+           "sample_receivers": args.sample, "cut_total": args.cut_total, "weights": WEIGHTS, "per_alpha": {}}
     for a in [float(x) for x in args.alphas.split(",")]:
         s = WL.scene_64(alpha=a)
         idx = np.random.default_rng(11882).choice(s.n_rx, size=args.sample, replace=False)
-        c = T.work_counts(s.walls, s.tx, s.rx[idx], s.max_order, a, cut=args.cut)
+        c = T.work_counts(s.walls, s.tx, s.rx[idx], s.max_order, a,
+                          cut=args.cut_total / n_candidates(s.walls.shape[0], s.max_order))
         out["per_alpha"][str(int(a))] = model(c, WEIGHTS)
         print(a, json.dumps(out["per_alpha"][str(int(a))]), flush=True)
     s3 = WL.scene3d_32()
     idx = np.random.default_rng(11882).choice(s3.n_rx, size=args.sample, replace=False)
-    c3 = T3.work_counts(s3.panels, s3.tx, s3.rx[idx], s3.max_order, s3.alpha, cut=args.cut)
+    c3 = T3.work_counts(s3.panels, s3.tx, s3.rx[idx], s3.max_order, s3.alpha,
+                        cut=args.cut_total / n_candidates(s3.panels.shape[0], s3.max_order))
     out["scene3d"] = {"workload": "room + 32 rectangles (38 panels), 256x256 receivers, order <= 2 (1,445 candidates)",
                       "weights": WEIGHTS_3D, "per_alpha": {str(int(s3.alpha)): model(c3, WEIGHTS_3D)}}
     print("3d", json.dumps(out["scene3d"]["per_alpha"]), flush=True)

@@ -153,7 +153,7 @@ drt::TraceArgs make_args(const drt_scene* s, const Plan& p, void* ws) {
   A.n_cand = (int)count_candidates(s->n_walls, s->max_order);
   A.cchunk = p.cchunk;
   A.screen = g_screen;
-  A.cut = g_cut ? drt::kCut : 0.0f;
+  A.cut = drt::cut_factor(g_cut != 0, A.n_cand);
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
   const bool hard = s->smoothing == DRT_HARD_SIGMOID;

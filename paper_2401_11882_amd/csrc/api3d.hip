@@ -141,7 +141,7 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   A.mode = hard ? 1 : 0;
   A.cull_c = (hard ? drt::kHardCullMargin : drt::kCullMargin) / s->alpha;
   A.screen = drt_internal_screen();
-  A.cut = drt_internal_cut() ? drt::kCut : 0.0f;
+  A.cut = drt::cut_factor(drt_internal_cut() != 0, (int)count_candidates(s->n_panels, s->max_order));
   A.tx = s->tx_dev;
   A.rx = s->rx_dev;
   A.n_panels = s->n_panels;

@@ -197,7 +197,7 @@ drt::BatchArgs make_args(const drt_plan* p, const drt_batch* b, int loss_kind, f
   B.cache_cap = p->cache_cap;
   B.cchunk = p->cfg.cchunk;
   B.screen = drt_internal_screen();
-  B.cut = drt_internal_cut() ? drt::kCut : 0.0f;
+  B.cut = drt_internal_cut() ? 1.0f : 0.0f;
   B.mode = b->smoothing == DRT_HARD_SIGMOID ? 1 : 0;
   B.box_lds = drt::batched_box_lds(p->cfg.nw, p->max_walls, p->max_order) ? 1 : 0;
   B.tile_w = p->cfg.tile_w;

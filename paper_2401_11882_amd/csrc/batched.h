@@ -37,7 +37,7 @@ struct BatchArgs {
   int cache_cap;
   int cchunk;
   int screen;                  // candidate screen on / off
-  float cut;                   // contribution cut factor (kCut, or 0 = off)
+  float cut;                   // 1: contribution cut on (factor per scene), 0: off
   int mode;                    // 0 sigmoid, 1 hard sigmoid
   int box_lds;                 // 1: screened candidates' leg boxes kept in LDS
   int tile_w;                  // receivers per tile row on grid scenes (8, 16, 32)

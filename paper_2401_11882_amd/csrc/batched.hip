@@ -96,6 +96,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
       term = (k == 1) ? W : term * (W - 1);
       n_cand += term;
     }
+    const float cutf = cut_factor(B.cut != 0.0f, n_cand);
     for (int i = threadIdx.x; i < NW * ncol; i += NW * kWave) accs[(i / ncol) * ncol_max + (i % ncol)] = 0.0f;
 
     const int m = batch_rx_of_lane(tile, lane, B.grid_nx[s], B.tile_w);
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
     float cut_base = 0.0f, own1 = 0.0f;
     auto visit = [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
       const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
-                                                B.cut * (cut_base + (sum - comp) - own1));
+                                                cutf * (cut_base + (sum - comp) - own1));
       kahan_add(sum, comp, v);
       if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
         if (nst < B.cache_cap) {
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
           for (int c = c0; c < c1; ++c) {
             const Cand cd = decode_candidate(c, W);
             kahan_add(rs, rc,
-                      candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, B.cut * (rs - rc)));
+                      candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, cutf * (rs - rc)));
           }
         }
       }

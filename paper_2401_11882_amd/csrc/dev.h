@@ -93,11 +93,16 @@ constexpr int kHardSigmoid = 1;
 __device__ __forceinline__ float med01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
 // Contribution cut: a lane drops a candidate as soon as its contribution is
-// provably at most kCut times the lane's running power sum (a lower bound of
-// its P(r), every term being >= 0).  The dropped terms of a receiver add up to
-// at most C kCut P(r) for C candidates (3e-10 P at C = 4,625, 3e-9 P at
-// C = 45,397), far below the FP32 rounding of P itself.
-constexpr float kCut = 0x1p-44f;
+// provably at most kCutTotal / C times the lane's running power sum (a lower
+// bound of its P(r), every term being >= 0), C the scene's candidate count.
+// The dropped terms of a receiver then add up to at most kCutTotal P(r) =
+// 2^-24 P(r), no more than one FP32 rounding of P.
+constexpr float kCutTotal = 0x1p-24f;
+
+// Per-candidate cut factor of a scene with n_cand candidates (0: cut off).
+__host__ __device__ inline float cut_factor(bool on, int n_cand) {
+  return (on && n_cand > 0) ? kCutTotal / (float)n_cand : 0.0f;
+}
 
 // The cut serves the sigmoid smoothing.  Hard-sigmoid factors are already
 // exactly 0 beyond a band of 3 / alpha, so those kernels are built without

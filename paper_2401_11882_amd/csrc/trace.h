@@ -20,7 +20,7 @@ struct TraceArgs {
   int n_cand;
   int cchunk;            // candidates per chunk handed to one wavefront
   int screen;            // 1: drop candidates that are exactly 0 over a wavefront's receiver box
-  float cut;             // contribution cut factor (kCut, or 0 = off)
+  float cut;             // contribution cut factor (kCutTotal / C, or 0 = off)
   int mode;              // 0 sigmoid, 1 hard sigmoid
   int max_order;
   float alpha;

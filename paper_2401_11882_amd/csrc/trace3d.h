@@ -14,7 +14,7 @@ struct Trace3Args {
   const PanelBox* boxes;   // culling boxes [n_panels], NULL: no culling
   float cull_c;            // 20 / alpha: culling extension of legs and panels
   int screen;              // 1: drop candidates that are exactly 0 over a wavefront's receiver box
-  float cut;               // contribution cut factor (kCut, or 0 = off)
+  float cut;               // contribution cut factor (kCutTotal / C, or 0 = off)
   int mode;                // 0 sigmoid, 1 hard sigmoid
   const float* tx;         // [3]
   const float* rx;         // [n_rx][3]

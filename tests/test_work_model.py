@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _check_cut_monotone(count):
     base = count(0.0)
     tiny = count(1e-300)
-    cut = count(2.0 ** -44)
+    cut = count(2.0 ** -24 / 4625)
     big = count(1e-6)
     for k in ("path_evals", "interactions", "active", "active_interactions"):
         assert tiny[k] == base[k]
@@ -42,8 +42,9 @@ def test_cut_only_removes_work_3d():
 def test_stored_model_matches_its_weights():
     with open(os.path.join(ROOT, "bench_work_model.json")) as f:
         m = json.load(f)
-    assert m["cut"] == pytest.approx(2.0 ** -44)
-    from oracle.count_work import WEIGHTS, WEIGHTS_3D, model
+    assert m["cut_total"] == pytest.approx(2.0 ** -24)
+    from oracle.count_work import WEIGHTS, WEIGHTS_3D, model, n_candidates
+    assert n_candidates(68, 2) == 4625 and n_candidates(38, 2) == 1445
     for key, W, sec in (("100", WEIGHTS, m["per_alpha"]), ("100", WEIGHTS_3D, m["scene3d"]["per_alpha"])):
         rec = sec[key]
         again = model(rec["counts"], W)
