@@ -32,19 +32,20 @@ UNPACKED_FP32_TFLOPS = 78.6     # the same without packed FP32: 256 CU x 64 lane
 # The sources the single-scene 2D tracer kernels (k_forward, k_backward) are
 # built from: counter figures are valid only while these are unchanged.
 TRACER_SOURCES = ("dev.h", "path.h", "screen.h", "trace.h", "trace.hip")
+TRACER3D_SOURCES = ("dev.h", "path3d.h", "screen3.h", "trace3d.h", "trace3d.hip")
 
 
-def source_hash() -> str:
+def source_hash(names=TRACER_SOURCES) -> str:
     """sha256 over the tracer kernels' HIP sources; counter figures are valid for this hash only."""
     import hashlib
     h = hashlib.sha256()
-    for name in TRACER_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2401_11882_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_counters(tag: str, kernel: str):
+def measured_counters(tag: str, kernel: str, sources=TRACER_SOURCES):
     """The committed rocprofv3 PMC summary of one kernel (HBM bytes per launch,
     executed FP32 FLOPs per launch, ...), or None when the kernels changed
     since those counters were taken."""
@@ -53,15 +54,26 @@ def measured_counters(tag: str, kernel: str):
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("source_sha256") != source_hash():
+    if t.get("source_sha256") != source_hash(sources):
         return None
     return t["kernels"].get(kernel)
 
 
-def measured_traffic(tag: str, kernel: str):
+def measured_traffic(tag: str, kernel: str, sources=TRACER_SOURCES):
     """HBM bytes per launch, or None (see measured_counters)."""
-    k = measured_counters(tag, kernel)
+    k = measured_counters(tag, kernel, sources)
     return None if k is None else int(k["hbm_bytes"])
+
+
+def copy_calibration(dev, mib: int) -> None:
+    """One plain device copy of mib MiB, the reference the HBM counters are scaled by."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(alpha: float, n_rx: int):
@@ -280,7 +292,8 @@ def extra_3d(dev, steps: int = 10, smoothing: str = "sigmoid"):
                               else ("k_forward3", fwd, pa["fwd_flops_per_path_eval"]))
             achieved = per * s.n_rx * n_cand / (kms * 1e-3) / 1e12
             out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                               "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                               "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                               "traffic": measured_traffic("scene3d_32_alpha100", name, TRACER3D_SOURCES),
                                "kernel": name, "kernel_ms": round(kms, 4), "flops_per_path_eval": round(per, 2)}
     return out
 
@@ -317,6 +330,8 @@ def main() -> int:
             print(f"unknown extra {args.extra!r}; choose from {sorted(fns)}", file=sys.stderr)
             return 2
         print(json.dumps({args.extra: fns[args.extra]()}), flush=True)
+        if args.copy_calib_mb > 0:
+            copy_calibration(dev, args.copy_calib_mb)
         return 0
 
     import numpy as np
@@ -368,12 +383,7 @@ def main() -> int:
     value = pe_per_step * args.steps / total_s
 
     if args.copy_calib_mb > 0:
-        n = args.copy_calib_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        copy_calibration(dev, args.copy_calib_mb)
 
     # algorithmic FLOPs per path evaluation (oracle-derived counts, bench_work_model.json)
     roofline = None
