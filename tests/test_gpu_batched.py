@@ -153,6 +153,30 @@ def test_batched_cut_within_bound():
         torch.testing.assert_close(x, y, rtol=1e-4, atol=1e-5 * float(y.abs().max()))
 
 
+def test_batched_cache_overflow_reevaluates():
+    """A contribution cache too small for the lists: the wavefronts that
+    overflow re-evaluate their share in the adjoint.  Power and loss are
+    bitwise those of a plan with room for every list; gradients agree to FP32
+    accuracy (re-evaluation bounds P(r) for the cut by its own running sum)."""
+    batched, tr = _mods()
+    scenes = _small_mixed() + WL.batch_scenes(6, side_cap=32)
+    ref_plan = batched.BatchPlan(scenes, 2)
+    ref = [t.clone() for t in ref_plan.run()]
+    ref_plan.close()
+    try:
+        tr.set_cache_limit(8 << 20)
+        plan = batched.BatchPlan(scenes, 2)
+        cap = plan.info()["cache_cap"]
+        out = [t.clone() for t in plan.run()]
+        plan.close()
+    finally:
+        tr.set_cache_limit(32 << 30)
+    assert 0 < cap < 64
+    assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+    for x, y in zip(out[2:], ref[2:]):
+        torch.testing.assert_close(x, y, rtol=1e-5, atol=1e-6 * float(y.abs().max()))
+
+
 def test_autotune_and_cache(tmp_path):
     batched, tr = _mods()
     scenes = WL.batch_scenes(24, side_cap=32)
