@@ -58,7 +58,7 @@ def test_free_space_and_single_mirror_closed_forms():
 
 
 @pytest.mark.parametrize("K", [0, 1, 2, 3])
-@pytest.mark.parametrize("alpha", [10.0, 100.0])
+@pytest.mark.parametrize("alpha", [10.0, 100.0, 1000.0])
 def test_room_scenes_all_orders(K, alpha):
     tr = _tr3()
     s = WL.scene3d_room(9, 2 if K < 3 else 0, 16, K, alpha, seed=40 + K)
@@ -189,7 +189,7 @@ def test_panel_culling_changes_no_bit(alpha):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("alpha", [10.0, 100.0])
+@pytest.mark.parametrize("alpha", [10.0, 100.0, 1000.0])
 def test_contribution_cut_within_bound_3d(alpha):
     """3D contribution cut: the power stays within 2^-24 P(r) (+ FP32
     rounding) of the uncut power and never above it; gradients (tx, panels,
