@@ -294,7 +294,13 @@ def extra_3d(dev, steps: int = 10, smoothing: str = "sigmoid"):
             out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                                "traffic": measured_traffic("scene3d_32_alpha100", name, TRACER3D_SOURCES),
-                               "kernel": name, "kernel_ms": round(kms, 4), "flops_per_path_eval": round(per, 2)}
+                               "kernel": name, "kernel_ms": round(kms, 4), "flops_per_path_eval": round(per, 2),
+                               "frac_of_unpacked_peak": round(achieved / UNPACKED_FP32_TFLOPS, 4)}
+            ctr = measured_counters("scene3d_32_alpha100", name, TRACER3D_SOURCES)
+            if ctr is not None and ctr.get("executed_fp32_flops"):
+                ex = ctr["executed_fp32_flops"] / (kms * 1e-3) / 1e12
+                out["roofline"]["executed_tflops"] = round(ex, 3)
+                out["roofline"]["executed_frac"] = round(ex / PEAK_FP32_TFLOPS, 4)
     return out
 
 
