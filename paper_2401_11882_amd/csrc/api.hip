@@ -112,12 +112,12 @@ Plan make_plan(const drt_scene* s) {
   off = align_up(off + sizeof(float) * (size_t)(s->n_rx > 0 ? s->n_rx : 1));
   p.off_grad = off;
   off = align_up(off + sizeof(float) * (size_t)p.ncol * (size_t)(p.n_tiles > 0 ? p.n_tiles : 1));
-  // contribution cache: a wavefront meets at most ceil(C / (nw*cchunk)) chunks
+  // contribution cache: the forward visits the candidates in at most three
+  // phases, each split into chunks over the wavefronts, so a wavefront meets
+  // at most ceil(C / (nw cchunk)) + 3 chunks
   const int64_t n_cand = count_candidates(s->n_walls, s->max_order);
-  // the forward visits the orders 0 and 1 first, then the rest: each part is
-  // split into chunks over the wavefronts
-  const int64_t n1 = std::min<int64_t>(n_cand, 1 + s->n_walls), span = (int64_t)p.nw * p.cchunk;
-  const int64_t per_wave = ((n1 + span - 1) / span + (n_cand - n1 + span - 1) / span) * p.cchunk;
+  const int64_t span = (int64_t)p.nw * p.cchunk;
+  const int64_t per_wave = ((n_cand + span - 1) / span + 3) * p.cchunk;
   const int64_t slots = (int64_t)p.n_tiles * p.nw;
   p.box_stride = 6 * (s->max_order + 1);
   const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int) + (int64_t)p.box_stride * sizeof(float);

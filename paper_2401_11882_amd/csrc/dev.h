@@ -112,6 +112,23 @@ constexpr bool uses_cut() {
   return MODE == kSigmoid;
 }
 
+// Candidate phases of the 2D kernels with the cut: the orders 0-1
+// [0, end0), then the order 2 [end0, end1) when the scene also has order-3
+// candidates, then the rest [end1, n_cand).  After each phase but the last
+// the wavefronts of a workgroup add up their sums, the base of the bound.
+struct CutPhases {
+  int end0, end1, n;
+};
+
+__host__ __device__ inline CutPhases cut_phases(int n_walls, int max_order, int n_cand) {
+  CutPhases p;
+  p.end0 = n_cand < 1 + n_walls ? n_cand : 1 + n_walls;
+  const int e2 = p.end0 + n_walls * (n_walls - 1);
+  p.end1 = (max_order >= 3 && e2 < n_cand) ? e2 : n_cand;
+  p.n = p.end1 < n_cand ? 3 : 2;
+  return p;
+}
+
 // Lane l's 64-bit value (l wave-uniform).
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);

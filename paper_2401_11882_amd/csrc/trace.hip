@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
                                                         float* __restrict__ loss_part, int loss_kind,
                                                         float log_eps) {
   __shared__ float red[NW][2][kWave];
-  __shared__ float base[NW][kWave];  // each wavefront's power sum over the orders 0 and 1
+  __shared__ float base[2][NW][kWave];  // each wavefront's power sum at the end of a phase
   extern __shared__ float fwd_boxes[];  // [NW][6 (max_order + 1)][64] leg boxes of screened candidates
   const SceneView S = view_of(A);
   const int lane = threadIdx.x & (kWave - 1);
@@ -90,12 +90,13 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   const RxBox box = rx_box(rxx, rxy, live);
   float* boxes = fwd_boxes + wave * 6 * (A.max_order + 1) * kWave;
   // The contribution cut compares each candidate with a lower bound of the
-  // lane's P(r): first the orders 0 and 1 (shared by the wavefronts through
-  // LDS once all have them), then this wavefront's own running sum on top.
-  float cut_base = 0.0f, own1 = 0.0f;
+  // lane's P(r): the sum over all wavefronts at the end of the previous phase
+  // (orders 0-1, then order 2 for order-3 scenes; shared through LDS), plus
+  // this wavefront's own running sum since then.
+  float cut_base = 0.0f, own_sync = 0.0f;
   auto visit = [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
     const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
-                                              A.cut * (cut_base + (sum - comp) - own1));
+                                              A.cut * (cut_base + (sum - comp) - own_sync));
     kahan_add(sum, comp, v);
     if (cache_c && ballot(v != 0.0f) != 0) {
       if (nst < A.cache_cap) {
@@ -107,19 +108,28 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
       ++nst;
     }
   };
-  // phase 0: candidates [0, n1) (orders 0-1), phase 1: [n1, C); one copy of
-  // the candidate code serves both (the loop is not unrolled)
-  const int n1 = uses_cut<MODE>() ? min(A.n_cand, 1 + A.n_walls) : 0;
+  if constexpr (!uses_cut<MODE>()) {
+    for_screened(S.walls, A.n_walls, 0, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
+                 S.cull_c, boxes, visit);
+  } else {
+    // one copy of the candidate code serves every phase (the loop is not
+    // unrolled); base is double-buffered, so one barrier per phase suffices
+    const CutPhases cp = cut_phases(A.n_walls, A.max_order, A.n_cand);
 #pragma nounroll
-  for (int ph = uses_cut<MODE>() ? 0 : 1; ph < 2; ++ph) {
-    for_screened(S.walls, A.n_walls, ph ? n1 : 0, ph ? A.n_cand : n1, S.dead_lim, A.screen != 0, wave, NW,
-                 A.cchunk, txx, txy, box, S.cull_c, boxes, visit);
-    if (ph == 0) {
-      own1 = sum - comp;
-      base[wave][lane] = own1;
-      __syncthreads();
+    for (int ph = 0; ph < cp.n; ++ph) {
+      const int b0 = ph == 0 ? 0 : (ph == 1 ? cp.end0 : cp.end1);
+      const int b1 = ph == 0 ? cp.end0 : (ph == 1 ? cp.end1 : A.n_cand);
+      for_screened(S.walls, A.n_walls, b0, b1, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
+                   S.cull_c, boxes, visit);
+      if (ph + 1 < cp.n) {
+        own_sync = sum - comp;
+        base[ph & 1][wave][lane] = own_sync;
+        __syncthreads();
+        float t = 0.0f;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) cut_base += base[w][lane];
+        for (int w = 0; w < NW; ++w) t += base[ph & 1][w][lane];
+        cut_base = t;
+      }
     }
   }
   if (cache_c && lane == 0) A.cache_n[slot] = nst <= A.cache_cap ? nst : -1;
@@ -192,13 +202,15 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
         candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
       }
     } else {
-      // re-evaluation of this wavefront's share as the forward split it (the
-      // orders 0 and 1, then the rest), the cut against its own running sum
+      // re-evaluation of this wavefront's share as the forward split it into
+      // phases, the cut against its own running sum
       float sum = 0.0f, comp = 0.0f;
-      const int n1 = uses_cut<MODE>() ? min(A.n_cand, 1 + A.n_walls) : 0;
+      const CutPhases cp = cut_phases(A.n_walls, A.max_order, A.n_cand);
+      const int nph = uses_cut<MODE>() ? cp.n : 1;
       const int stride = NW * A.cchunk;
-      for (int part = 0; part < 2; ++part) {
-        const int b0 = part ? n1 : 0, b1 = part ? A.n_cand : n1;
+      for (int part = 0; part < nph; ++part) {
+        const int b0 = part == 0 ? 0 : (part == 1 ? cp.end0 : cp.end1);
+        const int b1 = !uses_cut<MODE>() ? A.n_cand : (part == 0 ? cp.end0 : (part == 1 ? cp.end1 : A.n_cand));
         for (int c0 = b0 + wave * A.cchunk; c0 < b1; c0 += stride) {
           const int c1 = min(c0 + A.cchunk, b1);
           for (int c = c0; c < c1; ++c) {
