@@ -176,11 +176,13 @@ def test_grid_and_linear_mapping_agree_bitwise():
     assert torch.equal(Pa, Pb)
 
 
-def test_contribution_cache_reuse_and_overflow():
+@pytest.mark.parametrize("K", [2, 3])
+def test_contribution_cache_reuse_and_overflow(K):
     """Adjoint from recorded contributions == adjoint that re-evaluates; a cache
-    too small for the lists falls back to re-evaluation with the same result."""
+    too small for the lists falls back to re-evaluation with the same result.
+    K = 3 covers the three candidate phases of order-3 scenes."""
     tr = _tr()
-    s = WL.scene_random_box(2, 12, 16, 2, 100.0, seed=8)
+    s = WL.scene_random_box(2, 12, 16, K, 100.0, seed=8)
     sc = _scene(s)
     P, L, seed = tr.forward(sc, loss="neg_mean_log", want_seed=True)
     a = tr.backward(sc, seed, want_rx=True, reuse_forward=True)
