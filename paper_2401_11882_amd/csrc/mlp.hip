@@ -252,7 +252,17 @@ __global__ void k_sum_slices(const float* __restrict__ part, int n_slices, int n
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float s = 0.0f;
-  for (int z = 0; z < n_slices; ++z) s += part[(size_t)z * n + i];
+  int z = 0;
+  // eight loads in flight, then the adds in slice order (the order of a
+  // plain loop, so the sum is the same)
+  for (; z + 8 <= n_slices; z += 8) {
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = part[(size_t)(z + q) * n + i];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += v[q];
+  }
+  for (; z < n_slices; ++z) s += part[(size_t)z * n + i];
   out[i] = s;
 }
 
