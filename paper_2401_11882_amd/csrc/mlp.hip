@@ -206,7 +206,25 @@ __global__ __launch_bounds__(256) void k_colsum_part(const bf16* __restrict__ X,
   const int m0 = blockIdx.x * kColChunk, m1 = min(M, m0 + kColChunk);
   float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   if (col0 < N) {
-    for (int m = m0 + rl; m < m1; m += 8) {
+    int m = m0 + rl;
+    // four rows' loads in flight, then their products in row order (the
+    // order of the plain loop below)
+    for (; m + 24 < m1; m += 32) {
+      uint4 raw[4];
+      float w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        raw[q] = *reinterpret_cast<const uint4*>(X + (size_t)(m + 8 * q) * N + col0);
+        w[q] = wt ? wt[m + 8 * q] : 1.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bf16* x = reinterpret_cast<const bf16*>(&raw[q]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] = fmaf((float)x[k], w[q], s[k]);
+      }
+    }
+    for (; m < m1; m += 8) {
       const uint4 raw = *reinterpret_cast<const uint4*>(X + (size_t)m * N + col0);
       const bf16* x = reinterpret_cast<const bf16*>(&raw);
       const float w = wt ? wt[m] : 1.0f;
@@ -235,8 +253,18 @@ __global__ __launch_bounds__(256) void k_colsum_fold(const float* __restrict__ p
   const int c = threadIdx.x & 31, q = threadIdx.x >> 5;
   const int col = blockIdx.x * 32 + c;
   float s = 0.0f;
-  if (col < N)
-    for (int z = q; z < chunks; z += 8) s += part[(size_t)z * N + col];
+  if (col < N) {
+    int z = q;
+    // eight loads in flight, then the adds in chunk order
+    for (; z + 56 < chunks; z += 64) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = part[(size_t)(z + 8 * j) * N + col];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; z < chunks; z += 8) s += part[(size_t)z * N + col];
+  }
   sh[q][c] = s;
   __syncthreads();
   if (q == 0 && col < N) {
