@@ -234,6 +234,8 @@ def extra_surrogate():
             "speedup_at_1pct": round(r["speedup"], 3), "speedup_is_lower_bound": r["speedup_is_lower_bound"],
             "exact_step_ratio": round(r["exact_step_ratio"], 3),
             "plain_s": [round(p["t_total"], 3) for p in r["plain"]], "surrogate_s": round(r["surrogate"]["t_total"], 3),
+            "surrogate_scan_s": round(r["surrogate"]["t_scan"], 3),
+            "surrogate_exact_steps": r["surrogate"].get("exact_steps"),
             "surrogate_reached": r["surrogate"]["reached"], "plain_reached": [p["reached"] for p in r["plain"]],
             "F_star": r["F_star"], "F_surrogate": r["surrogate"]["F"], "F_plain": [p["F"] for p in r["plain"]],
             "datagen_s": round(r["datagen_s"], 3), "train_s": round(r["train_s"], 3),
