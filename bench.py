@@ -146,7 +146,7 @@ def extra_order3_loop(dev):
 
 
 def extra_hard_sigmoid(dev, steps: int = 10):
-    """Sec. III-B says the hard sigmoid is much cheaper to evaluate than the
+    """Sec. IV-B says the hard sigmoid is much cheaper to evaluate than the
     sigmoid: the same fwd + adjoint step on the 64-segment scene with each."""
     import torch
 
@@ -214,7 +214,7 @@ def extra_alpha_sweep(dev, steps: int = 10):
 
 
 def extra_placement():
-    """Sec. VI: success rate of annealed versus unsmoothed transmitter placement."""
+    """Sec. VII: success rate of annealed versus unsmoothed transmitter placement."""
     import torch
 
     from paper_2401_11882_amd import placement
@@ -243,7 +243,7 @@ def extra_surrogate():
 
 
 def extra_3d(dev, steps: int = 10, smoothing: str = "sigmoid"):
-    """Sec. V: the method in three dimensions.  Room (6 panels) + 32 random
+    """Sec. VI: the method in three dimensions.  Room (6 panels) + 32 random
     rectangles, 256^2 receivers at mid-height, order <= 2 (1,445 panel
     sequences), alpha = 100: forward, then the adjoint from the recorded
     contributions, as in the main step."""

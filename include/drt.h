@@ -6,13 +6,13 @@
  *
  * What one call computes, for every receiver r and every path candidate
  * sigma = (sigma_1..sigma_k), 0 <= k <= max_order, an ordered list of walls
- * with no wall repeated back to back (Sec. IV, "exhaustive list of path
+ * with no wall repeated back to back (Sec. V, "exhaustive list of path
  * candidates" from a full visibility matrix):
  *   1. the image method in the relaxed scene of infinite wall lines
- *      (Sec. IV and Sec. IV-B): images I_0 = tx, I_i = mirror of I_{i-1}
+ *      (Sec. V and Sec. V-B): images I_0 = tx, I_i = mirror of I_{i-1}
  *      across the line of sigma_i; back-trace X_{k+1} = r, X_i = a + t_i e
  *      = X_{i+1} + u_i (I_i - X_{i+1});
- *   2. the continuous validity of Sec. IV-A, with every comparison
+ *   2. the continuous validity of Sec. V-A, with every comparison
  *      x0 > x1 replaced by s(x0 - x1; alpha), s = sigmoid(alpha x)
  *      (Eq. 3, Eq. 4) or the hard sigmoid relu6(alpha x + 3) / 6 (Eq. 5-6),
  *      AND as a product and NOT as 1 - s:
@@ -22,10 +22,10 @@
  *   3. the received power of Eq. 7 with the dyadic coefficient set to the
  *      identity, summed incoherently:
  *        P(r) = sum_sigma V / max(|r - I_k|^2, d_min^2);
- *   4. the loss L = -F of Sec. II, and its gradients with respect to the
+ *   4. the loss L = -F of Sec. III, and its gradients with respect to the
  *      transmitter, every wall endpoint and (optionally) every receiver, by
  *      a hand-written adjoint (the paper obtains them by automatic
- *      differentiation, Sec. I and Sec. II).
+ *      differentiation, Sec. I and Sec. III).
  *
  * Conventions shared by every entry point
  *   - Pointers named *_dev are DEVICE pointers, owned by the caller; the
@@ -79,7 +79,7 @@ typedef enum drt_loss {
   DRT_LOSS_NONE = 0,               /* no loss, no seed */
   DRT_LOSS_SUM_POWER = 1,          /* L = sum_r P(r) */
   DRT_LOSS_NEG_MEAN_LOG_POWER = 2, /* L = -(1/R) sum_r log(P(r) + log_eps) */
-  DRT_LOSS_NEG_MIN_POWER = 3       /* L = -min_r P(r): the objective of Eq. 8 (Sec. VI), to be
+  DRT_LOSS_NEG_MIN_POWER = 3       /* L = -min_r P(r): the objective of Eq. 8 (Sec. VII), to be
                                       maximised, as a loss; dL/dP = -1 at the lowest receiver
                                       index attaining the minimum, 0 elsewhere.  Needs n_rx >= 1
                                       (batched: 1 <= n_rx <= 64 in every scene). */
@@ -112,7 +112,7 @@ const char* drt_status_string(int status);
 /* Message of the last failed call on this thread ("" if none). */
 const char* drt_last_error(void);
 
-/* Number of candidates 1 + sum_{k=1..K} W (W-1)^(k-1) (Sec. IV); host only.
+/* Number of candidates 1 + sum_{k=1..K} W (W-1)^(k-1) (Sec. V); host only.
    Returns DRT_EINVAL for out-of-range arguments. */
 int drt_num_candidates(int32_t n_walls, int32_t max_order, int64_t* count);
 
@@ -134,7 +134,7 @@ int drt_set_cache_limit(int64_t bytes);
    wavefront first tests 64 candidates at a time against the bounding box of
    its receivers and drops those whose interaction factor is provably
    exactly 0 at every receiver of the box (a back-trace parameter beyond the
-   range where exp(-alpha x) overflows FP32; Sec. IV-A, Eq. 3-4).  The same
+   range where exp(-alpha x) overflows FP32; Sec. V-A, Eq. 3-4).  The same
    switch controls the panel culling of the 3D calls (obstruction tests whose
    factor is exactly 1 in every lane are not evaluated).  Neither changes any
    result beyond the summation order of zero terms; turning them off exists
@@ -223,7 +223,7 @@ int drt_adam_points(int32_t n_points, float* x_dev, const float* grad_dev, float
                     int32_t* step_dev, float lr, float b1, float b2, float eps, float lo, float hi,
                     void* stream);
 
-/* Geometric sharpness schedule of the transmitter optimisation (Sec. VI,
+/* Geometric sharpness schedule of the transmitter optimisation (Sec. VII,
    Fig. 5: alpha grows geometrically from its first to its last value over
    the iterations).  Writes alpha_i = a_first (a_last / a_first)^(i/(n_iter-1))
    with i = min(*step_dev, n_iter - 1) into alpha_dev[0..n), reading the step
@@ -387,7 +387,7 @@ int drt_log_targets(const float* power_dev, int64_t n, float eps, float* y_dev, 
 int drt_valu_peak(double* fma_tflops, double* exp_tlanes);
 
 /* ------------------------------------------------------------------------
- * Scenes in three dimensions (Sec. V: the method makes no assumption on
+ * Scenes in three dimensions (Sec. VI: the method makes no assumption on
  * the number of dimensions)
  *
  * The walls become planar parallelogram panels {a + beta (b - a) +
@@ -398,7 +398,7 @@ int drt_valu_peak(double* fma_tflops, double* exp_tlanes);
  * (beta_i, gamma_i); an interaction's factor is in(beta) in(gamma) in(u);
  * panel j obstructs a leg with 1 - in(upsilon) in(beta) in(gamma), upsilon
  * the leg parameter of the plane crossing and (beta, gamma) its panel
- * coordinates (Sec. IV-A with Eq. 3-4, or the hard sigmoid of Eq. 5-6).  A panel of
+ * coordinates (Sec. V-A with Eq. 3-4, or the hard sigmoid of Eq. 5-6).  A panel of
  * zero area contributes no path and never obstructs; a back-trace parallel
  * to a plane gives no path; a leg parallel to a plane is not obstructed by
  * it.  Power, losses, error handling, determinism, graph capture, receiver

@@ -1,7 +1,7 @@
 """FP64 reference of the transmitter optimisation with an annealed sharpness
 (TEST INFRASTRUCTURE ONLY; nothing in the product path imports it).
 
-Sec. VI places one transmitter to serve several receivers by maximising
+Sec. VII places one transmitter to serve several receivers by maximising
 Eq. 8, F(tx) = min_i P_Rx_i(tx), with a gradient method, and raises the
 sharpness alpha after every iteration along a geometric progression from 1 to
 100 over the iterations (Fig. 5 lists alpha at four iterations).  Here the

@@ -6,19 +6,19 @@ only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 
 What it computes, following the paper (arXiv 2401.11882):
 
-* Smoothing (Sec. III, Eq. 3 and Eq. 4): a comparison ``x0 > x1`` becomes
+* Smoothing (Sec. IV, Eq. 3 and Eq. 4): a comparison ``x0 > x1`` becomes
   ``s(x0 - x1; alpha)`` with ``s(x; alpha) = sigmoid(alpha * x)``
   (mode "sigmoid") or the hard sigmoid of Eq. 5-6,
   ``relu6(alpha x + 3) / 6`` (mode "hard_sigmoid").  The unsmoothed
   reference (mode "hard") uses the unit step of Eq. 1 instead.
-* Candidates (Sec. IV): every ordered sequence of walls of length 0..K with no
+* Candidates (Sec. V): every ordered sequence of walls of length 0..K with no
   wall repeated back to back (full visibility matrix, box walls included).
-* Path in the relaxed scene (Sec. IV and Sec. IV-B): the image method over
+* Path in the relaxed scene (Sec. V and Sec. V-B): the image method over
   infinite wall lines.  Images ``I_0 = tx`` and ``I_i`` = mirror of ``I_{i-1}``
   across the line of wall ``sigma_i``; back-trace from ``X_{k+1} = r``: ``X_i``
   is where the line from ``X_{i+1}`` to ``I_i`` meets the line of ``sigma_i``,
   at ``X_i = a + t_i e = X_{i+1} + u_i (I_i - X_{i+1})``.
-* Continuous validity (Sec. IV-A): each hard check is a comparison, smoothed.
+* Continuous validity (Sec. V-A): each hard check is a comparison, smoothed.
   ``inside(x) = s(x) * s(1 - x)`` (Boolean AND as a product).  Interaction i:
   ``inside(t_i) * inside(u_i)`` (point on its segment, and the point lies
   between the previous point and the image, i.e. a true reflection).
@@ -28,10 +28,10 @@ What it computes, following the paper (arXiv 2401.11882):
   (NOT as one minus).  ``V`` is the product of all factors.
 * Received power (Eq. 7 with the dyadic coefficient set to the identity, an
   incoherent sum): ``P(r) = sum_paths V / max(|r - I_k|^2, d_min^2)``.
-* Objective (Sec. II): ``L = -F``; here ``L_log = -(1/R) sum_r log(P(r)+eps)``,
-  ``L_sum = sum_r P(r)``, or ``L_min = -min_r P(r)`` (Eq. 8, Sec. VI).
+* Objective (Sec. III): ``L = -F``; here ``L_log = -(1/R) sum_r log(P(r)+eps)``,
+  ``L_sum = sum_r P(r)``, or ``L_min = -min_r P(r)`` (Eq. 8, Sec. VII).
 * Gradients: torch autograd (reverse mode) over the same fp64 expressions, in
-  the role the paper gives to automatic differentiation (Sec. I, Sec. II).
+  the role the paper gives to automatic differentiation (Sec. I, Sec. III).
 
 Degenerate cases: a zero-length wall cannot mirror (its candidates contribute
 0); a back-trace with the line parallel to the wall gives an invalid path
@@ -58,7 +58,7 @@ DEFAULT_LOG_EPS = 1e-6
 
 
 # --------------------------------------------------------------------------
-# Smoothing functions (Sec. III)
+# Smoothing functions (Sec. IV)
 # --------------------------------------------------------------------------
 
 def unit_step(x):
@@ -96,7 +96,7 @@ def _cross(u, v):
 
 
 # --------------------------------------------------------------------------
-# Candidates (Sec. IV)
+# Candidates (Sec. V)
 # --------------------------------------------------------------------------
 
 def candidates(n_walls: int, max_order: int) -> list[tuple[int, ...]]:
@@ -123,7 +123,7 @@ def _groups(n_walls: int, max_order: int):
 
 
 # --------------------------------------------------------------------------
-# Image method (Sec. IV, Sec. IV-B)
+# Image method (Sec. V, Sec. V-B)
 # --------------------------------------------------------------------------
 
 def images(walls, src, seq):
@@ -263,7 +263,7 @@ def loss_value(P, kind: str, log_eps: float = DEFAULT_LOG_EPS) -> float:
     if kind == "neg_mean_log":
         return float(-np.mean(np.log(P + log_eps)))
     if kind == "neg_min":
-        # Eq. 8 (Sec. VI): F = min over receivers, maximised; as a loss, -F
+        # Eq. 8 (Sec. VII): F = min over receivers, maximised; as a loss, -F
         return float(-np.min(P))
     raise ValueError(kind)
 

@@ -5,17 +5,17 @@ only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` use it.  It shares no code with the HIP path.
 
 The paper states that its framework makes no assumption on the number of
-dimensions and that a 3D implementation is straightforward (Sec. V).  Here the
+dimensions and that a 3D implementation is straightforward (Sec. VI).  Here the
 walls of the 2D method become planar parallelogram panels
 ``{a + beta (b - a) + gamma (c - a) : beta, gamma in [0, 1]}`` (corner a,
 adjacent corners b and c), and every step keeps its 2D meaning:
 
 * images: mirror across the panel's plane, normal n = (b - a) x (c - a)
-  (Sec. IV, image method);
+  (Sec. V, image method);
 * back-trace from X_{k+1} = r towards I_i: the line meets the plane at
   X_i = X_{i+1} + u_i (I_i - X_{i+1}); (beta_i, gamma_i) are X_i's panel
   coordinates; the interaction factor is in(beta) in(gamma) in(u) with
-  in(x) = s(x) s(1 - x) (Sec. IV-A: inside the panel, and a true
+  in(x) = s(x) s(1 - x) (Sec. V-A: inside the panel, and a true
   reflection);
 * obstruction of a leg [X_l, X_{l+1}] by panel j (not one of the leg's own
   end panels): the leg meets the plane at leg parameter upsilon, the hit
@@ -37,7 +37,7 @@ import numpy as np
 import torch
 import torch.nn.functional as F
 
-from .tracer import candidates  # the candidate enumeration is dimension-free (Sec. IV)
+from .tracer import candidates  # the candidate enumeration is dimension-free (Sec. V)
 from .tracer import hard_sigmoid  # Eq. 5-6
 
 DTYPE = torch.float64

@@ -85,7 +85,7 @@ __device__ __forceinline__ float uniformf(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
-// Smoothing of the comparisons (Sec. III-B): sigmoid (Eq. 4) or hard sigmoid
+// Smoothing of the comparisons (Sec. IV-B): sigmoid (Eq. 4) or hard sigmoid
 // (Eq. 5-6, relu6(alpha x + 3) / 6 = clamp(x alpha / 6 + 1/2, 0, 1)).
 constexpr int kSigmoid = 0;
 constexpr int kHardSigmoid = 1;

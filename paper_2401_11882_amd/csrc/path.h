@@ -3,9 +3,9 @@
 // batched kernels.  One lane = one receiver; the candidate and the wall under
 // test are wave-uniform.
 //
-// Method (arXiv 2401.11882): image method in the relaxed scene (Sec. IV,
-// Sec. IV-B); every validity comparison x0 > x1 smoothed as
-// s(x0 - x1) = sigmoid(alpha (x0 - x1)) (Sec. IV-A, Eq. 3, Eq. 4); power
+// Method (arXiv 2401.11882): image method in the relaxed scene (Sec. V,
+// Sec. V-B); every validity comparison x0 > x1 smoothed as
+// s(x0 - x1) = sigmoid(alpha (x0 - x1)) (Sec. V-A, Eq. 3, Eq. 4); power
 // V / max(|r - I_k|^2, d_min^2) per path (Eq. 7 with identity coefficient).
 //
 // Exactness of the skips used below (none changes the FP32 result):

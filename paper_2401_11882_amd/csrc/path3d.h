@@ -7,10 +7,10 @@
 // n . a, and the vectors m1 = ((c - a) x n) s, m2 = (n x (b - a)) s with
 // beta = (x - a) . m1 and gamma = (x - a) . m2 for x in its plane.  Every
 // step is the 2D step with the wall replaced by the panel (the method does
-// not depend on the dimension, Sec. V): mirror across the plane, back-trace
+// not depend on the dimension, Sec. VI): mirror across the plane, back-trace
 // to the plane, the validity of an interaction in(beta) in(gamma) in(u) and
 // the obstruction factor 1 - in(upsilon) in(beta) in(gamma), with in(x) =
-// s(alpha x) s(alpha (1 - x)) and s the sigmoid (Sec. IV-A, Eq. 3-4).
+// s(alpha x) s(alpha (1 - x)) and s the sigmoid (Sec. V-A, Eq. 3-4).
 //
 // The adjoint accumulates, per panel, the gradients with respect to the
 // record's a, n, m1, m2 and s (13 numbers); a final kernel maps them to the

@@ -1,7 +1,7 @@
 """Transmitter optimisation by gradient steps on the smoothed power map.
 
-Sec. II frames the problem as minimising L = -F over parameters (here the
-transmitter position) with a gradient method; Sec. VI optimises the
+Sec. III frames the problem as minimising L = -F over parameters (here the
+transmitter position) with a gradient method; Sec. VII optimises the
 transmitter position.  One step = the fused forward + adjoint
 (drt_forward_backward) followed by an Adam update of tx (drt_adam_tx), both
 on the device; the step is captured once in a HIP graph and replayed, with

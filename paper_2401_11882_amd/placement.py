@@ -1,4 +1,4 @@
-"""Transmitter placement with an annealed sharpness (Sec. VI).
+"""Transmitter placement with an annealed sharpness (Sec. VII).
 
 The paper places one transmitter to serve several receivers by maximising
 Eq. 8, F(tx) = min_i P_Rx_i(tx), by gradient steps, raising alpha after every

@@ -5,8 +5,8 @@ receiver grids and the random tensors of the learned surrogate. It holds none
 of the tracer's arithmetic, so both the FP64 oracle and the HIP path read the
 exact same FP32 arrays from it.
 
-Scene family (the paper's experiments use small synthetic 2D layouts, Sec. V
-and Sec. VI; no public dataset exists, so these stand in):
+Scene family (the paper's experiments use small synthetic 2D layouts, Sec. VI
+and Sec. VII; no public dataset exists, so these stand in):
 
 * The unit-square box is always present as walls 0..3 (bottom, right, top,
   left), each running counter-clockwise.
@@ -139,7 +139,7 @@ def batch_scenes(n_scenes: int = 512, lo: int = 8, hi: int = 128,
 
 
 def placement_problem(scene: int, n_rx: int, alpha: float = 1.0) -> Scene:
-    """One transmitter-placement problem (Sec. VI): box + 2..5 interior segments
+    """One transmitter-placement problem (Sec. VII): box + 2..5 interior segments
     of length U(0.2, 0.5), n_rx receivers ~U[0.05, 0.95]^2 and a start
     position tx ~U[0.05, 0.95]^2; line of sight only (order 0), as in the
     paper's example.  Receivers are scattered (grid_n = 0)."""

@@ -1,7 +1,7 @@
 """Brute-force path finder for tiny scenes, independent of the image method.
 
 For a wall sequence (consecutive repeats allowed) the interaction points are
-found by Fermat's principle (Sec. IV-B names Fermat path tracing as one of the
+found by Fermat's principle (Sec. V-B names Fermat path tracing as one of the
 path finders): minimise the total path length over the wall-LINE parameters
 t_i (P_i = a_i + t_i e_i).  The length is a sum of norms of affine maps of t,
 hence convex, so damped Newton reaches its unique stationary point.

@@ -1,4 +1,4 @@
-"""Transmitter placement (Sec. VI): min objective, schedule, Adam on points and
+"""Transmitter placement (Sec. VII): min objective, schedule, Adam on points and
 the annealed loop, HIP path against the FP64 reference."""
 import numpy as np
 import pytest

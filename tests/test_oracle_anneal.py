@@ -1,4 +1,4 @@
-"""Pins of the FP64 reference of the transmitter-placement application (Sec. VI).
+"""Pins of the FP64 reference of the transmitter-placement application (Sec. VII).
 
 * the alpha schedule against the values printed in the Fig. 5 caption
   (tests/golden/paper_figures.txt);
@@ -90,7 +90,7 @@ def test_annealing_leaves_the_zero_gradient_region():
     """Problem 7 with two receivers starts where one receiver is shadowed: the
     unsmoothed objective is 0 with a zero gradient there, so Adam does not move;
     annealing alpha from 1 to 100 over 100 iterations reaches the optimum found
-    by a 64 x 64 scan of the unsmoothed objective (Sec. VI, Fig. 4-5)."""
+    by a 64 x 64 scan of the unsmoothed objective (Sec. VII, Fig. 4-5)."""
     s = WL.placement_problem(7, 2)
     assert _hard_objective(s, s.tx) == 0.0
     h_hard, _ = A.optimize(s.walls, s.rx, s.tx, 0, 100, 0.01, np.full(100, 1e6))

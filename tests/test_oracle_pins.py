@@ -1,14 +1,14 @@
 """Pins of the FP64 oracle against facts that do not come from the oracle itself.
 
 * values the paper prints (Fig. 2, Fig. 5) -- tests/golden/paper_figures.txt
-* the smoothing contract C1-C4 and Eq. 2 (Sec. III-A)
+* the smoothing contract C1-C4 and Eq. 2 (Sec. IV-A)
 * closed forms: free-space LOS, LOS inside the box with hand-derived
   crossing parameters, one reflection on a long wall (image distance)
 * reciprocity of image distances (mirrors are involutive isometries)
 * alpha -> infinity convergence to the hard-indicator result (Eq. 2)
 * brute force on tiny scenes with an independent Fermat path finder and
   orientation predicates
-* zero-gradient removal inside a hard shadow (Sec. I, Sec. VI)
+* zero-gradient removal inside a hard shadow (Sec. I, Sec. VII)
 * translation / rotation / scaling invariants of the gradient
 * autograd vs central finite differences
 """
@@ -139,7 +139,7 @@ def test_los_inside_box_closed_form():
 @pytest.mark.parametrize("alpha", [10.0, 100.0, 1000.0])
 def test_single_reflection_long_wall(alpha):
     """One wall (-1e3,0)->(1e3,0), tx and rx above it: the order-1 path has the
-    mirror distance and closed-form t, u (Sec. IV-B image method)."""
+    mirror distance and closed-form t, u (Sec. V-B image method)."""
     wall = np.array([[-1e3, 0.0, 1e3, 0.0]])
     tx = np.array([0.3, 0.2])
     rng = np.random.default_rng(1)
