@@ -205,6 +205,26 @@ int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_ep
                          float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,
                          void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   computation as drt_forward_backward, with the workspace taken from a
+   64 MiB scratch array that the library holds in each device's memory for
+   the life of the process (no hipMalloc, hipFree or allocating call, no
+   workspace argument).  Arguments, outputs and errors as drt_forward_backward;
+   a scene whose workspace without the contribution cache exceeds 64 MiB
+   (about n_rx x (4 + n_walls / 4) bytes: seed, loss and gradient partials) is rejected with
+   DRT_EINVAL before anything is enqueued.  The contribution cache gets the
+   rest of the array, so wavefronts that overflow it re-evaluate (power is
+   bitwise that of drt_forward_backward; gradients agree to FP32 accuracy,
+   bitwise with drt_set_cut(0)).  Every call on one device shares that
+   device's array: calls that overlap on one device (another stream, another
+   thread) race and give wrong results; serialise them.  The first call on a
+   device looks up the array's address there (host-side, no allocation). */
+int drt_forward_backward_noalloc(const drt_scene* scene, int32_t loss_kind, float log_eps,
+                                 float* power_dev, float* loss_dev,
+                                 float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,
+                                 void* stream);
+
 /* One Adam step on the transmitter (torch's Adam with bias correction)
    followed by clamping every coordinate to [lo, hi].
    tx_dev [2] in/out; grad_dev [2] in; m_dev, v_dev [2] in/out (start at 0);

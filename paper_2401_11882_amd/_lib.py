@@ -82,6 +82,8 @@ _SIGS = {
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], c_int32),
     "drt_forward_backward": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
+    "drt_forward_backward_noalloc": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
     "drt_adam_tx": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,
                      c_float, c_float, c_float, c_void_p], c_int32),
     "drt_adam_points": ([c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,

@@ -4,11 +4,17 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/drt.h"
 #include "dev.h"
 #include "trace.h"
+
+// Scratch of the allocation-free entry point drt_forward_backward_noalloc
+// (64 MiB per device; see scratch_of_current_device).
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -95,7 +101,8 @@ int check_scene(const drt_scene* s) {
   return DRT_OK;
 }
 
-Plan make_plan(const drt_scene* s) {
+// cache_limit: largest contribution cache placed in the workspace (bytes).
+Plan make_plan(const drt_scene* s, int64_t cache_limit) {
   Plan p{};
   p.n_tiles = (s->n_rx + drt::kWave - 1) / drt::kWave;
   p.nw = pick_nw(p.n_tiles, s->n_walls, s->max_order);
@@ -122,8 +129,8 @@ Plan make_plan(const drt_scene* s) {
   p.box_stride = 6 * (s->max_order + 1);
   const int64_t entry = (int64_t)drt::kWave * sizeof(float) + sizeof(int) + (int64_t)p.box_stride * sizeof(float);
   int64_t cap = per_wave;
-  if (slots > 0 && g_cache_limit > 0) {
-    const int64_t fit = (g_cache_limit - slots * (int64_t)sizeof(int)) / (slots * entry);
+  if (slots > 0 && cache_limit > 0) {
+    const int64_t fit = (cache_limit - slots * (int64_t)sizeof(int)) / (slots * entry);
     if (fit < cap) cap = fit;
   } else {
     cap = 0;
@@ -234,6 +241,57 @@ int enqueue_backward(const drt_scene* s, const Plan& p, const drt::TraceArgs& A,
   return DRT_OK;
 }
 
+int check_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_eps, const float* power_dev,
+                           const float* grad_tx_dev, const float* grad_walls_dev) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if ((rc = check_loss(loss_kind, log_eps))) return rc;
+  if (loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "forward_backward needs a loss_kind");
+  if (loss_kind == DRT_LOSS_NEG_MIN_POWER && scene->n_rx < 1) return fail(DRT_EINVAL, "min loss needs n_rx >= 1");
+  if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
+  if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
+  if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
+  return DRT_OK;
+}
+
+// Forward, seed (kept in the workspace) and adjoint from the recorded contributions.
+int enqueue_forward_backward(const drt_scene* scene, const Plan& p, int32_t loss_kind, float log_eps,
+                             float* power_dev, float* loss_dev, float* grad_tx_dev, float* grad_walls_dev,
+                             float* grad_rx_dev, void* ws, hipStream_t st) {
+  const drt::TraceArgs A = make_args(scene, p, ws);
+  float* seed = reinterpret_cast<float*>(static_cast<char*>(ws) + p.off_seed);
+  int rc = enqueue_forward(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed, ws, st);
+  if (rc) return rc;
+  return enqueue_backward(scene, p, A, seed, grad_tx_dev, grad_walls_dev, grad_rx_dev, 1, ws, st);
+}
+
+// Scratch memory of drt_forward_backward_noalloc: a device array that every
+// GPU the library runs on holds for the life of the process.  Host code must
+// never pass the array's name to a kernel (on the host it is only a stand-in
+// for the symbol); it uses the address hipGetSymbolAddress returns for the
+// current device, looked up once per device.  Nothing in it needs to start
+// at zero: every kernel writes what it later reads within the same call.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DRT_EINVAL, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(DRT_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DRT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -302,7 +360,7 @@ int drt_workspace_size(const drt_scene* scene, size_t* bytes) {
   int rc = check_scene(scene);
   if (rc) return rc;
   if (!bytes) return fail(DRT_EINVAL, "bytes is NULL");
-  *bytes = make_plan(scene).total;
+  *bytes = make_plan(scene, g_cache_limit).total;
   return DRT_OK;
 }
 
@@ -311,7 +369,7 @@ int drt_cache_layout(const drt_scene* scene, int64_t* slots, int64_t* capacity, 
   int rc = check_scene(scene);
   if (rc) return rc;
   if (!slots || !capacity || !off_idx || !off_n) return fail(DRT_EINVAL, "NULL output pointer");
-  const Plan p = make_plan(scene);
+  const Plan p = make_plan(scene, g_cache_limit);
   *slots = (int64_t)p.n_tiles * p.nw;
   *capacity = p.cache_cap;
   *off_idx = (int64_t)p.off_cache_idx;
@@ -327,7 +385,7 @@ int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps, float*
   if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
   if (seed_dev && loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "seed_dev needs a loss_kind");
   if (loss_kind == DRT_LOSS_NEG_MIN_POWER && scene->n_rx < 1) return fail(DRT_EINVAL, "min loss needs n_rx >= 1");
-  const Plan p = make_plan(scene);
+  const Plan p = make_plan(scene, g_cache_limit);
   if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
   const drt::TraceArgs A = make_args(scene, p, ws_dev);
   return enqueue_forward(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed_dev, ws_dev,
@@ -343,7 +401,7 @@ int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t fl
   if (scene->n_rx > 0 && !grad_power_dev) return fail(DRT_EINVAL, "grad_power_dev is NULL");
   if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
   if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
-  const Plan p = make_plan(scene);
+  const Plan p = make_plan(scene, g_cache_limit);
   if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
   const drt::TraceArgs A = make_args(scene, p, ws_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -359,22 +417,34 @@ int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t fl
 int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
                          float* loss_dev, float* grad_tx_dev, float* grad_walls_dev,
                          float* grad_rx_dev, void* ws_dev, size_t ws_bytes, void* stream) {
-  int rc = check_scene(scene);
+  int rc = check_forward_backward(scene, loss_kind, log_eps, power_dev, grad_tx_dev, grad_walls_dev);
   if (rc) return rc;
-  if ((rc = check_loss(loss_kind, log_eps))) return rc;
-  if (loss_kind == DRT_LOSS_NONE) return fail(DRT_EINVAL, "forward_backward needs a loss_kind");
-  if (loss_kind == DRT_LOSS_NEG_MIN_POWER && scene->n_rx < 1) return fail(DRT_EINVAL, "min loss needs n_rx >= 1");
-  if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
-  if (!grad_tx_dev) return fail(DRT_EINVAL, "grad_tx_dev is NULL");
-  if (scene->n_walls > 0 && !grad_walls_dev) return fail(DRT_EINVAL, "grad_walls_dev is NULL");
-  const Plan p = make_plan(scene);
+  const Plan p = make_plan(scene, g_cache_limit);
   if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
-  const drt::TraceArgs A = make_args(scene, p, ws_dev);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  float* seed = reinterpret_cast<float*>(static_cast<char*>(ws_dev) + p.off_seed);
-  rc = enqueue_forward(scene, p, A, loss_kind, log_eps, power_dev, loss_dev, seed, ws_dev, st);
+  return enqueue_forward_backward(scene, p, loss_kind, log_eps, power_dev, loss_dev, grad_tx_dev, grad_walls_dev,
+                                  grad_rx_dev, ws_dev, static_cast<hipStream_t>(stream));
+}
+
+int drt_forward_backward_noalloc(const drt_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
+                                 float* loss_dev, float* grad_tx_dev, float* grad_walls_dev,
+                                 float* grad_rx_dev, void* stream) {
+  int rc = check_forward_backward(scene, loss_kind, log_eps, power_dev, grad_tx_dev, grad_walls_dev);
   if (rc) return rc;
-  return enqueue_backward(scene, p, A, seed, grad_tx_dev, grad_walls_dev, grad_rx_dev, 1, ws_dev, st);
+  // everything but the contribution cache must fit; the cache gets what is left
+  const Plan bare = make_plan(scene, 0);
+  if (bare.total > kScratchBytes)
+    return fail(DRT_EINVAL,
+                "scene needs %zu bytes of scratch (n_walls=%d, n_rx=%d); the allocation-free entry point holds "
+                "%zu: use drt_forward_backward with a caller workspace",
+                bare.total, scene->n_walls, scene->n_rx, kScratchBytes);
+  int64_t room = (int64_t)(kScratchBytes - bare.total) - 4 * (int64_t)kAlign;
+  if (room > g_cache_limit) room = g_cache_limit;
+  Plan p = make_plan(scene, room > 0 ? room : 0);
+  if (p.total > kScratchBytes) p = bare;
+  void* ws = nullptr;
+  if ((rc = scratch_of_current_device(&ws))) return rc;
+  return enqueue_forward_backward(scene, p, loss_kind, log_eps, power_dev, loss_dev, grad_tx_dev, grad_walls_dev,
+                                  grad_rx_dev, ws, static_cast<hipStream_t>(stream));
 }
 
 int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev, int32_t* step_dev,

@@ -195,6 +195,28 @@ def forward_backward(scene: Scene, loss: str = "neg_mean_log", log_eps: float = 
     return out
 
 
+def forward_backward_noalloc(scene: Scene, loss: str = "neg_mean_log", log_eps: float = DEFAULT_LOG_EPS,
+                             want_rx: bool = False, out=None, stream=None):
+    """As forward_backward, through drt_forward_backward_noalloc: the library's
+    per-device scratch array serves as the workspace (no workspace tensor).
+    Calls that overlap on one device race; ``out`` as in forward_backward."""
+    if loss == "none":
+        raise ValueError("forward_backward needs a loss")
+    sc = scene.c_struct()
+    if out is None:
+        dev = scene.device
+        out = (torch.empty(scene.n_rx, dtype=torch.float32, device=dev),
+               torch.empty(1, dtype=torch.float32, device=dev),
+               torch.empty(2, dtype=torch.float32, device=dev),
+               torch.empty(scene.n_walls, 4, dtype=torch.float32, device=dev),
+               torch.empty(scene.n_rx, 2, dtype=torch.float32, device=dev) if want_rx else None)
+    P, L, gtx, gw, grx = out
+    check(lib().drt_forward_backward_noalloc(ctypes.byref(sc), _lib.LOSS[loss], float(log_eps), _ptr(P), _ptr(L),
+                                             _ptr(gtx), _ptr(gw if scene.n_walls else None), _ptr(grx),
+                                             stream_handle(stream)))
+    return out
+
+
 def adam_tx(tx, grad, m, v, step, lr=1e-2, b1=0.9, b2=0.999, eps=1e-8, lo=1e-3, hi=1.0 - 1e-3,
             stream=None) -> None:
     for t, nm in ((tx, "tx"), (grad, "grad"), (m, "m"), (v, "v")):

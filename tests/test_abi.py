@@ -216,3 +216,24 @@ def test_valu_peak_rejects_null_outputs():
     d = ctypes.c_double()
     assert L.drt_valu_peak(None, ctypes.byref(d)) == _lib.DRT_EINVAL
     assert L.drt_valu_peak(ctypes.byref(d), None) == _lib.DRT_EINVAL
+
+
+def test_noalloc_validation_before_any_device_call():
+    """The allocation-free entry point checks its arguments and the scratch
+    size on the host: these calls fail before the first HIP call."""
+    L = _lib.lib()
+    sc = _scene()
+    # loss_kind NONE, NULL outputs
+    assert L.drt_forward_backward_noalloc(ctypes.byref(sc), 0, 1e-6, BOGUS, None, BOGUS, BOGUS, None,
+                                          None) == _lib.DRT_EINVAL
+    assert L.drt_forward_backward_noalloc(ctypes.byref(sc), 2, 1e-6, None, None, BOGUS, BOGUS, None,
+                                          None) == _lib.DRT_EINVAL
+    assert L.drt_forward_backward_noalloc(ctypes.byref(sc), 2, 1e-6, BOGUS, None, None, BOGUS, None,
+                                          None) == _lib.DRT_EINVAL
+    assert L.drt_forward_backward_noalloc(None, 2, 1e-6, BOGUS, None, BOGUS, BOGUS, None, None) == _lib.DRT_EINVAL
+    # gradient partials of 16,384 tiles x 4,098 columns exceed the 64 MiB scratch
+    big = _scene(n_walls=1024, n_rx=1 << 20, rx_grid_nx=1024, max_order=1)
+    assert L.drt_forward_backward_noalloc(ctypes.byref(big), 2, 1e-6, BOGUS, None, BOGUS, BOGUS, None,
+                                          None) == _lib.DRT_EINVAL
+    msg = L.drt_last_error().decode()
+    assert "allocation-free" in msg and "drt_forward_backward" in msg
