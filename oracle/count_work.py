@@ -25,36 +25,37 @@ from oracle import tracer as T  # noqa: E402
 from oracle import tracer3d as T3  # noqa: E402
 from paper_2401_11882_amd import workloads as WL  # noqa: E402
 
-# FLOPs per operation (FMA = 2, add/mul/compare = 1, exp2/rcp = 1).  Only
-# work whose result can change the output is counted: an obstruction test
-# whose smoothed factor is 1.0f in FP32 (saturated) and the obstruction tests
-# of a pair whose interaction factor is exactly 0 count nothing, however an
-# implementation proves them away.  A pair or test whose contribution is
-# bounded by 2^-24 P(r) / C (P the receiver's full power, C the scene's
-# candidate count) counts nothing either: the kernels skip only work bounded
-# by 2^-24 / C times a lower bound of P(r), so the model never credits work
-# they do not do.
+# FLOPs per operation (FMA = 2, add/mul/compare = 1, exp2/rcp = 1), credited
+# by one rule: only an active pair's work counts (oracle.tracer.work_counts:
+# valid, interaction factor nonzero in FP32, bound F / max(d^2, d_min^2) of
+# its contribution above 2^-24 P(r) / C, P the receiver's full power and C the
+# scene's candidate count), and of its obstruction tests only the unsaturated
+# ones (a saturated factor is 1.0f in FP32).  Work an implementation spends
+# to prove a pair or a test away (screens, back-traces of pairs whose factor
+# is 0, band checks) is not credited.  An active pair's tests are all
+# credited, also those a kernel skips once the pair's running product has
+# fallen below the cut, so this is the method's work on the pairs that can
+# contribute, not a count of what a kernel executes: it is reported beside
+# the executed-FLOP counters as context.
 WEIGHTS = {
-    "fwd_per_path_eval": 13,           # |r - I_k|^2, floor, divide, compensated sum
-    "fwd_per_interaction": 20,         # back-trace step (needed to decide the factor)
-    "fwd_per_active_interaction": 20,  # in(t) in(u): 4 exp, reciprocal, products
-    "fwd_per_unsaturated": 44,         # den, tau/ups (18) + reciprocal, 4 exp, stable 1 - in*in (26)
-    "bwd_per_active_path_eval": 12,    # dL/dc, |r - I_k|^2 adjoint
-    "bwd_per_active_interaction": 80,  # back-trace + mirror adjoint, in(t) in(u) and its derivative
-    "bwd_per_unsaturated": 94,         # the test's values (44) + dlog q/d(tau, ups) and the chain (50)
+    "fwd_per_active_pair": 13,          # |r - I_k|^2, floor, divide, compensated sum
+    "fwd_per_active_interaction": 40,   # back-trace step (20) + in(t) in(u): 4 exp, reciprocal, products (20)
+    "fwd_per_unsaturated": 44,          # den, tau/ups (18) + reciprocal, 4 exp, stable 1 - in*in (26)
+    "bwd_per_active_pair": 12,          # dL/dc, |r - I_k|^2 adjoint
+    "bwd_per_active_interaction": 80,   # back-trace + mirror adjoint, in(t) in(u) and its derivative
+    "bwd_per_unsaturated": 94,          # the test's values (44) + dlog q/d(tau, ups) and the chain (50)
 }
 
 
 # The same accounting for panels in 3D (dot products of three, one more
 # panel coordinate and one more smoothed comparison per test).
 WEIGHTS_3D = {
-    "fwd_per_path_eval": 14,           # |r - I_k|^2, floor, divide, compensated sum
-    "fwd_per_interaction": 36,         # back-trace step to the plane, panel coordinates
-    "fwd_per_active_interaction": 28,  # in(beta) in(gamma) in(u): 6 exp, products, reciprocal
-    "fwd_per_unsaturated": 76,         # plane crossing and band tests (42), three n_x and the factor (34)
-    "bwd_per_active_path_eval": 14,    # dL/dc, |r - I_k|^2 adjoint
+    "fwd_per_active_pair": 14,          # |r - I_k|^2, floor, divide, compensated sum
+    "fwd_per_active_interaction": 64,   # back-trace to the plane, panel coordinates (36) + 3 factors (28)
+    "fwd_per_unsaturated": 76,          # plane crossing and band tests (42), three n_x and the factor (34)
+    "bwd_per_active_pair": 14,          # dL/dc, |r - I_k|^2 adjoint
     "bwd_per_active_interaction": 141,  # derivatives of the three factors, back-trace and mirror adjoint
-    "bwd_per_unsaturated": 176,        # the test's values (72) + three log-derivatives and the chain (104)
+    "bwd_per_unsaturated": 176,         # the test's values (72) + three log-derivatives and the chain (104)
 }
 
 
@@ -66,12 +67,9 @@ def n_candidates(n: int, max_order: int) -> int:
 def model(counts: dict, W: dict) -> dict:
     n = counts["path_evals"]
     per = {k: v / n for k, v in counts.items()}
-    fwd = (W["fwd_per_path_eval"] + W["fwd_per_interaction"] * per["interactions"] +
-           W["fwd_per_active_interaction"] * per["active_interactions"] +
+    fwd = (W["fwd_per_active_pair"] * per["active"] + W["fwd_per_active_interaction"] * per["active_interactions"] +
            W["fwd_per_unsaturated"] * per["unsaturated"])
-    # reverse sweep from the recorded contributions
-    bwd = (W["bwd_per_active_path_eval"] * per["active"] +
-           W["bwd_per_active_interaction"] * per["active_interactions"] +
+    bwd = (W["bwd_per_active_pair"] * per["active"] + W["bwd_per_active_interaction"] * per["active_interactions"] +
            W["bwd_per_unsaturated"] * per["unsaturated"])
     return {"counts": counts, "per_path_eval": per, "fwd_flops_per_path_eval": fwd, "bwd_flops_per_path_eval": bwd}
 
@@ -81,8 +79,8 @@ def main() -> None:
     ap.add_argument("--sample", type=int, default=256)
     ap.add_argument("--alphas", default="10,100,1000")
     ap.add_argument("--cut-total", type=float, default=2.0 ** -24,
-                    help="contribution cut: pairs and tests that can change P(r) by at most cut_total P(r) / C "
-                         "count nothing (the kernels drop only what lies below that times a lower bound of P)")
+                    help="contribution cut: pairs that can change P(r) by at most cut_total P(r) / C count "
+                         "nothing (the kernels drop only what lies below that times a lower bound of P)")
     args = ap.parse_args()
     out = {"workload": "box + 64 segments, 256x256 receivers, order <= 2 (4,625 candidates)",
            "sample_receivers": args.sample, "cut_total": args.cut_total, "weights": WEIGHTS, "per_alpha": {}}

@@ -354,26 +354,27 @@ def path_details(walls, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_D
 
 def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
                 active_log_floor: float = -88.72, cut: float = 0.0):
-    """Algorithmic work of the method at these receivers (instrumentation).
+    """Algorithmic work of the method at these receivers (instrumentation;
+    parity unpinned against the paper, which counts no work).
 
-    Counts, over all (receiver, candidate) pairs ("path evaluations"):
-      * ``path_evals`` and ``interactions`` (reflections evaluated);
-      * ``active``: pairs whose product of interaction factors is above
-        exp(active_log_floor) -- below it the product of the four
-        (1 + exp) terms exceeds the FP32 range, the factor is exactly 0 in
-        FP32 and the obstruction tests of that pair contribute nothing --
-        and, with ``cut`` > 0, whose contribution bound F / max(d^2, d_min^2)
-        exceeds cut * P(r);
+    One rule decides what is credited, with no reference to the order in
+    which an implementation visits walls or candidates: a (receiver,
+    candidate) pair is *active* when it is valid, its interaction factor F
+    (the product of in(t_i) in(u_i)) exceeds exp(active_log_floor) (below, F
+    is exactly 0 in FP32, and so is every later product) and, with ``cut`` >
+    0, the bound F / max(d^2, d_min^2) of its contribution, known before any
+    obstruction test, exceeds cut * P(r).  A pair's back-trace, interaction
+    factors and obstruction tests are all credited when it is active and not
+    at all otherwise.  Counts:
+
+      * ``path_evals`` and ``interactions`` (k per pair): all pairs;
+      * ``active`` and ``active_interactions``: active pairs and their k;
       * ``tests``: obstruction tests of active pairs (a leg is not tested
         against its own end walls);
-      * ``unsaturated``: tests of active pairs whose tau and upsilon both lie
-        within margin/alpha of [0, 1] (outside that band the smoothed factor
-        is within 2^-25 of 1 and rounds to 1 in FP32) and, with ``cut`` > 0,
-        that come while the pair's product so far V (walls in increasing
-        order, legs in order within a wall) still exceeds
-        cut * P(r) max(d^2, d_min^2): a pair below that can no longer change
-        P(r) by more than cut * P(r);
-      * ``active_interactions``: interactions of active pairs.
+      * ``unsaturated``: those tests whose leg parameter and wall parameter
+        both lie within margin/alpha of [0, 1] (outside, the smoothed factor
+        is within 2^-25 of 1 and rounds to 1 in FP32) and whose leg is not
+        parallel to the wall.
     """
     W = _as64(walls).reshape(-1, 4)
     T = _as64(tx).reshape(2)
@@ -391,23 +392,21 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
         for s in range(0, Rx.shape[0], cs):
             rxc = Rx[s:s + cs]
             for k, seq in groups.items():
-                c_, info = _group_terms(W, T, rxc, seq, alpha, "sigmoid", DEFAULT_DMIN, True)
+                _, info = _group_terms(W, T, rxc, seq, alpha, "sigmoid", DEFAULT_DMIN, True)
                 X = info["X"]
                 Cn = seq.shape[0]
                 logf = torch.zeros(rxc.shape[0], Cn, dtype=DTYPE)
                 for i, (t, u) in info["params"].items():
                     logf = logf + _log_inside(t, alpha) + _log_inside(u, alpha)
-                act = info["valid"] & (logf > active_log_floor)
-                dd = torch.clamp(info["d2"], min=DEFAULT_DMIN * DEFAULT_DMIN)
+                ok = info["valid"] & (logf > active_log_floor)
                 if cut > 0:
-                    lim = cut * P_all[s:s + cs][:, None] * dd          # [Rc, C] cut on V
-                    act = act & (torch.exp(logf) > lim)
+                    dd = torch.clamp(info["d2"], min=DEFAULT_DMIN * DEFAULT_DMIN)
+                    ok = ok & (torch.exp(logf) / dd > cut * P_all[s:s + cs][:, None])
+                n_ok = int(ok.sum())
                 out["path_evals"] += rxc.shape[0] * Cn
                 out["interactions"] += rxc.shape[0] * Cn * k
-                out["active"] += int(act.sum())
-                out["active_interactions"] += int(act.sum()) * k
-                # per (wall, leg) in visiting order: in-band flags and smoothed factors
-                live_l, q_l = [], []
+                out["active"] += n_ok
+                out["active_interactions"] += n_ok * k
                 for l in range(k + 1):
                     D = (X[l + 1] - X[l])[:, :, None, :]
                     w0 = a[None, None] - X[l][:, :, None, :]
@@ -417,24 +416,12 @@ def work_counts(walls, tx, rx, max_order, alpha, margin: float = 18.0,
                         excl |= seq[:, l - 1][:, None] == jidx[None]
                     if l + 1 <= k:
                         excl |= seq[:, l][:, None] == jidx[None]
-                    use = (~excl[None]) & act[:, :, None]
+                    use = (~excl[None]) & ok[:, :, None]
                     den_s = torch.where(den != 0, den, torch.ones_like(den))
                     tau = _cross(w0, D) / den_s
                     ups = _cross(w0, e[None, None]) / den_s
                     live = use & (den != 0) & ((tau - 0.5).abs() < 0.5 + band) & \
                         ((ups - 0.5).abs() < 0.5 + band)
                     out["tests"] += int(use.sum())
-                    live_l.append(live)
-                    if cut > 0:
-                        q = -torch.expm1(_log_inside(tau, alpha) + _log_inside(ups, alpha))
-                        q_l.append(torch.where(use & (den != 0), q, torch.ones_like(q)))
-                if cut <= 0:
-                    out["unsaturated"] += int(sum(int(v.sum()) for v in live_l))
-                    continue
-                # V before each test: F times the factors of earlier (wall, leg) tests
-                Lv = torch.stack(live_l, dim=-1).reshape(rxc.shape[0], Cn, -1)   # [Rc, C, W (k+1)]
-                Q = torch.stack(q_l, dim=-1).reshape(rxc.shape[0], Cn, -1)
-                Vb = torch.exp(logf)[..., None] * torch.cumprod(
-                    torch.cat([torch.ones_like(Q[..., :1]), Q[..., :-1]], dim=-1), dim=-1)
-                out["unsaturated"] += int((Lv & (Vb > lim[..., None])).sum())
+                    out["unsaturated"] += int(live.sum())
     return out

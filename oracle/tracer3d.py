@@ -232,18 +232,19 @@ def path_details(panels, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_
 
 def work_counts(panels, tx, rx, max_order: int, alpha: float, margin: float = 18.0,
                 active_log_floor: float = -88.72, cut: float = 0.0):
-    """Algorithmic work of the 3D method at these receivers (instrumentation).
+    """Algorithmic work of the 3D method at these receivers (instrumentation;
+    parity unpinned against the paper, which counts no work).
 
-    Counts over all (receiver, candidate) pairs, as the 2D reference's
-    work_counts: ``path_evals``, ``interactions``, ``active`` pairs (product of
-    interaction factors above exp(active_log_floor), below which it is 0 in
-    FP32, and with ``cut`` > 0 a contribution bound F / max(d^2, d_min^2)
-    above cut * P(r)), ``active_interactions``, ``tests`` (obstruction tests
-    of active pairs, a leg's own end panels excluded) and ``unsaturated``
-    tests (leg parameter and both panel coordinates within margin/alpha of
-    [0, 1]; outside, the factor rounds to 1 in FP32; with ``cut`` > 0 only
-    while the pair's product so far, panels in increasing order and legs in
-    order within a panel, exceeds cut * P(r) max(d^2, d_min^2)).
+    The rule of the 2D reference's work_counts: a pair is *active* when it is
+    valid, its interaction factor F (the product of in(beta) in(gamma) in(u)
+    over its interactions) exceeds exp(active_log_floor) and, with ``cut`` >
+    0, F / max(d^2, d_min^2) exceeds cut * P(r); its back-trace, interaction
+    factors and obstruction tests are credited only then.  Counts:
+    ``path_evals``, ``interactions`` (all pairs), ``active``,
+    ``active_interactions``, ``tests`` (obstruction tests of active pairs, a
+    leg's own end panels excluded) and ``unsaturated`` tests (leg parameter
+    and both panel coordinates within margin/alpha of [0, 1], the plane not
+    parallel to the leg).
     """
     Pn = _as64(panels).reshape(-1, 9)
     T = _as64(tx).reshape(3)
@@ -271,16 +272,15 @@ def work_counts(panels, tx, rx, max_order: int, alpha: float, margin: float = 18
                 logf = torch.zeros(rxc.shape[0], Cn, dtype=DTYPE)
                 for i, (beta, gamma, u) in info["params"].items():
                     logf = logf + _log_inside(beta, alpha) + _log_inside(gamma, alpha) + _log_inside(u, alpha)
-                act = info["valid"] & (logf > active_log_floor)
+                ok = info["valid"] & (logf > active_log_floor)
                 if cut > 0:
                     dd = torch.clamp(info["d2"], min=DEFAULT_DMIN * DEFAULT_DMIN)
-                    lim = cut * P_all[s:s + cs][:, None] * dd          # [Rc, C] cut on the product V
-                    act = act & (torch.exp(logf) > lim)
+                    ok = ok & (torch.exp(logf) / dd > cut * P_all[s:s + cs][:, None])
+                n_ok = int(ok.sum())
                 out["path_evals"] += rxc.shape[0] * Cn
                 out["interactions"] += rxc.shape[0] * Cn * k
-                out["active"] += int(act.sum())
-                out["active_interactions"] += int(act.sum()) * k
-                live_l, q_l = [], []
+                out["active"] += n_ok
+                out["active_interactions"] += n_ok * k
                 for l in range(k + 1):
                     P0 = X[l]
                     D = (X[l + 1] - P0)[:, :, None, :]
@@ -291,7 +291,7 @@ def work_counts(panels, tx, rx, max_order: int, alpha: float, margin: float = 18
                         excl |= seq[:, l - 1][:, None] == jidx[None]
                     if l + 1 <= k:
                         excl |= seq[:, l][:, None] == jidx[None]
-                    use = (~excl[None]) & act[:, :, None] & (nn[None, None] > 0)
+                    use = (~excl[None]) & ok[:, :, None] & (nn[None, None] > 0)
                     den_s = torch.where(den != 0, den, torch.ones_like(den))
                     ups = _dot(w0, n[None, None]) / den_s
                     H = P0[:, :, None, :] + ups[..., None] * D
@@ -300,17 +300,5 @@ def work_counts(panels, tx, rx, max_order: int, alpha: float, margin: float = 18
                     live = use & (den != 0) & ((ups - 0.5).abs() < 0.5 + band) & \
                         ((beta - 0.5).abs() < 0.5 + band) & ((gamma - 0.5).abs() < 0.5 + band)
                     out["tests"] += int(use.sum())
-                    live_l.append(live)
-                    if cut > 0:
-                        q = -torch.expm1(_log_inside(ups, alpha) + _log_inside(beta, alpha) + _log_inside(gamma, alpha))
-                        q_l.append(torch.where(use & (den != 0), q, torch.ones_like(q)))
-                if cut <= 0:
-                    out["unsaturated"] += sum(int(v.sum()) for v in live_l)
-                    continue
-                # V before each test: F times the factors of the earlier (panel, leg) tests
-                Lv = torch.stack(live_l, dim=-1).reshape(rxc.shape[0], Cn, -1)   # [Rc, C, P (k+1)]
-                Q = torch.stack(q_l, dim=-1).reshape(rxc.shape[0], Cn, -1)
-                Vb = torch.exp(logf)[..., None] * torch.cumprod(
-                    torch.cat([torch.ones_like(Q[..., :1]), Q[..., :-1]], dim=-1), dim=-1)
-                out["unsaturated"] += int((Lv & (Vb > lim[..., None])).sum())
+                    out["unsaturated"] += int(live.sum())
     return out

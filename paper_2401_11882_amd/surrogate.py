@@ -278,19 +278,43 @@ def search(surr: Surrogate, walls, rx_exact, tx_grid_n: int, rx_scan_n: int, top
             best = (tx_b, F_b)
         if target is not None and best[1] >= target:
             break
-    return {"tx": best[0], "F": best[1], "t_scan": t_scan, "t_total": time.perf_counter() - t0,
-            "starts_tried": tried, "exact_steps": used_total, "Fhat_top": float(Fhat[order[0]])}
+    t_total = time.perf_counter() - t0
+    # the surrogate's error on the objective, in log-power units: at the top
+    # scanned start (against the exact F over the scan's receiver grid) and at
+    # the refined transmitter (against the exact F over rx_exact)
+    top = txg[order[0]].cpu().numpy()
+    F_top = exact_mean_log(walls, top, rxs, max_order, alpha, grid_nx=rx_scan_n)
+    Fhat_top = float(Fhat[order[0]]) * surr.y_std + surr.y_mean
+    Fhat_best = float(surr.scan(torch.tensor(np.asarray(best[0], dtype=np.float32)[None], device=dev),
+                                rx_exact)[0]) * surr.y_std + surr.y_mean
+    return {"tx": best[0], "F": best[1], "t_scan": t_scan, "t_total": t_total,
+            "starts_tried": tried, "exact_steps": used_total,
+            "tx_top": [float(x) for x in top], "Fhat_top": Fhat_top, "F_top": F_top,
+            "abs_err_top": abs(Fhat_top - F_top), "Fhat_best": Fhat_best, "abs_err_best": abs(Fhat_best - best[1])}
+
+
+def exact_mean_log(walls, tx, rx, max_order, alpha, grid_nx=0) -> float:
+    """The exact smoothed objective F = mean log(P + 1e-6) over rx at one tx."""
+    sc = tr.Scene(walls, torch.as_tensor(np.asarray(tx, dtype=np.float32), device=rx.device), rx, max_order, alpha,
+                  grid_nx=grid_nx)
+    return exact_objective(sc)
 
 
 def experiment(seed: int = 0, n_tx: int = 2442, n_rx: int = 4096, epochs: int = 20, holdout_tx: int = 122,
-               n_starts: int = 48, plain_seeds: int = 3, verbose: bool = False):
+               n_starts: int = 400, plain_seeds: int = 3, verbose: bool = False):
     """The surrogate study on the 64-segment scene (alpha 100, order <= 2, 256^2
     receivers): data generation, training, held-out error, F* by the exhaustive
     reference, then the time to reach F >= F* + log 0.99 with plain exact-tracer
     Adam from seeded random starts (``plain_seeds`` independent start sets of up
-    to ``n_starts`` each) versus the surrogate scan + exact refinement.  A plain
-    run that does not reach the target counts with its whole time, so the
-    reported speedup is then a lower bound."""
+    to ``n_starts`` each) versus the surrogate scan + exact refinement.
+
+    ``speedup`` (search time, plain over surrogate, as the protocol defines it:
+    data generation and training excluded) is reported only when the median
+    plain run reached the target; otherwise it is None and
+    ``speedup_lower_bound`` holds the ratio with the plain runs' whole time.
+    The one-off cost of the surrogate (data generation + training) is given
+    with the end-to-end time of one surrogate search and the number of searches
+    on this scene after which the surrogate route is ahead."""
     dev = torch.device("cuda")
     s = WL.scene_64()
     walls = torch.tensor(s.walls, device=dev)
@@ -331,7 +355,13 @@ def experiment(seed: int = 0, n_tx: int = 2442, n_rx: int = 4096, epochs: int = 
                      for kk, vv in p.items()} for p in plains]
     t_plain = float(np.median([p["t_total"] for p in plains]))
     out["plain_reached"] = sum(p["reached"] for p in plains)
-    out["speedup"] = t_plain / sur["t_total"]
-    out["speedup_is_lower_bound"] = out["plain_reached"] < (plain_seeds + 1) // 2
+    median_reached = out["plain_reached"] >= (plain_seeds + 1) // 2
+    ratio = t_plain / sur["t_total"]
+    out["speedup"] = ratio if (median_reached and out["surrogate"]["reached"]) else None
+    out["speedup_lower_bound"] = ratio if (not median_reached and out["surrogate"]["reached"]) else None
     out["exact_step_ratio"] = float(np.median([p["exact_steps"] for p in plains])) / max(1, sur["exact_steps"])
+    once = out["datagen_s"] + out["train_s"]
+    out["surrogate_end_to_end_s"] = once + sur["t_total"]
+    gain = t_plain - sur["t_total"]
+    out["break_even_searches"] = (float(np.ceil(once / gain)) if (median_reached and gain > 0) else None)
     return out
