@@ -90,13 +90,19 @@ typedef struct drt_scene {
   const float* walls_dev;  /* [n_walls][4]; the box walls are ordinary walls */
   int32_t n_walls;         /* 0 .. DRT_MAX_WALLS (0 = free space, LOS only) */
   const float* tx_dev;     /* [2] transmitter */
-  const float* rx_dev;     /* [n_rx][2] receivers */
+  const float* rx_dev;     /* [n_rx][2] receivers, or NULL for the receiver
+                              grid: the cell centres ((i + 1/2) / nx,
+                              (j + 1/2) / ny) of an nx x ny grid over [0, 1]^2,
+                              index m = j nx + i, nx = rx_grid_nx,
+                              ny = n_rx / nx, computed in FP64 and rounded
+                              once to FP32 (the grid needs rx_grid_nx > 0) */
   int32_t n_rx;            /* >= 0 */
-  int32_t rx_grid_nx;      /* 0, or the row length when rx is a row-major
-                              grid (index j*nx + i) with nx % 8 == 0 and
-                              n_rx % (8*nx) == 0: then each wavefront takes an
-                              8x8 block of neighbouring receivers.  Only the
-                              work order changes, never the result. */
+  int32_t rx_grid_nx;      /* 0, or the row length when the receivers form a
+                              row-major grid (index j*nx + i) with nx % 8 == 0
+                              and n_rx % (8*nx) == 0: then each wavefront
+                              takes an 8x8 block of neighbouring receivers.
+                              With rx_dev given only the work order changes,
+                              never the result. */
   int32_t max_order;       /* K, 0 .. DRT_MAX_ORDER */
   float alpha;             /* smoothing sharpness, finite and > 0 (Eq. 3) */
   int32_t smoothing;       /* drt_smoothing */
@@ -135,10 +141,13 @@ int drt_set_cache_limit(int64_t bytes);
    its receivers and drops those whose interaction factor is provably
    exactly 0 at every receiver of the box (a back-trace parameter beyond the
    range where exp(-alpha x) overflows FP32; Sec. V-A, Eq. 3-4).  The same
-   switch controls the panel culling of the 3D calls (obstruction tests whose
-   factor is exactly 1 in every lane are not evaluated).  Neither changes any
-   result beyond the summation order of zero terms; turning them off exists
-   to verify that.  Process-wide. */
+   switch controls the wall culling of the 2D calls (single scene and
+   batched: a (wall, leg) test is skipped when a separating-axis test proves
+   the wall's band-extended segment misses the leg's box, so its factor is
+   exactly 1 in every lane) and the panel culling of the 3D calls.  None of
+   them changes any result beyond the summation order of zero terms; with the
+   switch off every (wall, leg) test is evaluated, which exists to verify
+   that.  Process-wide. */
 int drt_set_screen(int32_t enabled);
 
 /* Contribution cut on (1, default) or off (0), for the 2D calls (single
@@ -224,6 +233,30 @@ int drt_forward_backward_noalloc(const drt_scene* scene, int32_t loss_kind, floa
                                  float* power_dev, float* loss_dev,
                                  float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,
                                  void* stream);
+
+/* Forward pass with Fermat path tracing instead of the image method
+   (Sec. V-B names both as path finders).  For every candidate of order 1 or
+   2 the interaction points on the wall lines are found by damped Newton on
+   the path length (Fermat's principle), max_iter steps at most per stage of
+   a continuation that smooths the length's kinks (a leg of zero length) away
+   and then restores them; line-of-sight paths are as in drt_forward.  The
+   finder's convergence check compares the MPT loss L (the squared residual
+   of the law of reflection summed over the interactions: 0 on a valid path,
+   4 (d . n)^2 on a straight pass through a wall line) with 0, smoothed as
+   s(1 - L / conv_eps) with the scene's sharpness and smoothing (Sec. V-B).
+   It takes the place of the image method's side factor in(u); the other
+   factors are as in drt_forward (Sec. V-A): V = prod_i in(t_i) s(1 - L /
+   conv_eps) prod over legs of the obstruction factors, power
+   sum V / max(l^2, d_min^2) with l the path length.
+   max_iter in [1, 64] (16 is ample); conv_eps > 0 (1e-4 rejects passes
+   steeper than about 0.3 degrees).  scene->max_order <= 2 (DRT_ENOTSUP
+   otherwise); loss_kind NONE, SUM_POWER or NEG_MEAN_LOG_POWER; power_dev
+   out [n_rx], loss_dev out [1] or NULL; workspace as drt_workspace_size.
+   No contribution cut, cache or candidate screen: every candidate is
+   evaluated.  Forward only (no adjoint). */
+int drt_forward_fermat(const drt_scene* scene, int32_t max_iter, float conv_eps, int32_t loss_kind,
+                       float log_eps, float* power_dev, float* loss_dev, void* ws_dev, size_t ws_bytes,
+                       void* stream);
 
 /* One Adam step on the transmitter (torch's Adam with bias correction)
    followed by clamping every coordinate to [lo, hi].

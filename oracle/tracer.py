@@ -330,7 +330,8 @@ def forward_backward(walls, tx, rx, max_order, alpha, kind="neg_mean_log",
 def path_details(walls, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_DMIN):
     """Per-candidate details at one receiver (for tests).
 
-    Returns a list of dicts: seq, c, V, points X_1..X_k, valid, d2.
+    Returns a list of dicts: seq, c, V, points X_1..X_k, their wall and side
+    parameters t, u, valid, d2.
     """
     W = _as64(walls).reshape(-1, 4)
     T = _as64(tx).reshape(2)
@@ -346,6 +347,8 @@ def path_details(walls, tx, r, max_order, alpha, mode="sigmoid", d_min=DEFAULT_D
                     "V": float(info["V"][0, ci]),
                     "valid": bool(info["valid"][0, ci]),
                     "points": [info["X"][i][0, ci].numpy().copy() for i in range(1, k + 1)],
+                    "t": [float(info["params"][i][0][0, ci]) for i in range(1, k + 1)],
+                    "u": [float(info["params"][i][1][0, ci]) for i in range(1, k + 1)],
                     "image": info["I"][k][ci].numpy().copy(),
                     "d2": float(info["d2"][0, ci]),
                 })

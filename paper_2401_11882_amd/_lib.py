@@ -84,6 +84,8 @@ _SIGS = {
                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p], c_int32),
     "drt_forward_backward_noalloc": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
+    "drt_forward_fermat": ([ctypes.POINTER(DrtScene), c_int32, c_float, c_int32, c_float, c_void_p, c_void_p,
+                            c_void_p, c_size_t, c_void_p], c_int32),
     "drt_adam_tx": ([c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,
                      c_float, c_float, c_float, c_void_p], c_int32),
     "drt_adam_points": ([c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float,

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdrt.so")
-SOURCES = ["api.hip", "trace.hip", "adam.hip", "api_batched.hip", "batched.hip", "api_mlp.hip", "mlp.hip", "api3d.hip", "trace3d.hip", "probe.hip"]
+SOURCES = ["api.hip", "trace.hip", "adam.hip", "api_batched.hip", "batched.hip", "api_mlp.hip", "mlp.hip", "api3d.hip", "trace3d.hip", "probe.hip", "fermat.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

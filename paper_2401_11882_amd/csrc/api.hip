@@ -82,7 +82,8 @@ int check_scene(const drt_scene* s) {
   if (s->n_walls > 0 && !s->walls_dev) return fail(DRT_EINVAL, "walls_dev is NULL");
   if (!s->tx_dev) return fail(DRT_EINVAL, "tx_dev is NULL");
   if (s->n_rx < 0) return fail(DRT_EINVAL, "n_rx=%d is negative", s->n_rx);
-  if (s->n_rx > 0 && !s->rx_dev) return fail(DRT_EINVAL, "rx_dev is NULL");
+  if (s->n_rx > 0 && !s->rx_dev && s->rx_grid_nx <= 0)
+    return fail(DRT_EINVAL, "rx_dev is NULL and rx_grid_nx is 0 (no receiver array and no grid)");
   if (s->max_order < 0 || s->max_order > DRT_MAX_ORDER)
     return fail(DRT_EINVAL, "max_order=%d outside [0, %d]", s->max_order, DRT_MAX_ORDER);
   if (!std::isfinite(s->alpha) || !(s->alpha > 0.0f))
@@ -445,6 +446,43 @@ int drt_forward_backward_noalloc(const drt_scene* scene, int32_t loss_kind, floa
   if ((rc = scratch_of_current_device(&ws))) return rc;
   return enqueue_forward_backward(scene, p, loss_kind, log_eps, power_dev, loss_dev, grad_tx_dev, grad_walls_dev,
                                   grad_rx_dev, ws, static_cast<hipStream_t>(stream));
+}
+
+int drt_forward_fermat(const drt_scene* scene, int32_t max_iter, float conv_eps, int32_t loss_kind,
+                       float log_eps, float* power_dev, float* loss_dev, void* ws_dev, size_t ws_bytes,
+                       void* stream) {
+  int rc = check_scene(scene);
+  if (rc) return rc;
+  if (scene->max_order > 2) return fail(DRT_ENOTSUP, "Fermat path tracing covers max_order <= 2 (got %d)",
+                                        scene->max_order);
+  if (max_iter < 1 || max_iter > 64) return fail(DRT_EINVAL, "max_iter=%d outside [1, 64]", max_iter);
+  if (!std::isfinite(conv_eps) || !(conv_eps > 0.0f)) return fail(DRT_EINVAL, "conv_eps must be finite and > 0");
+  if ((rc = check_loss(loss_kind, log_eps))) return rc;
+  if (loss_kind == DRT_LOSS_NEG_MIN_POWER) return fail(DRT_ENOTSUP, "loss_kind NEG_MIN_POWER not offered here");
+  if (scene->n_rx > 0 && !power_dev) return fail(DRT_EINVAL, "power_dev is NULL");
+  const Plan p = make_plan(scene, g_cache_limit);
+  if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
+  const drt::TraceArgs A = make_args(scene, p, ws_dev);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws_dev);
+  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls, A.cull_c,
+                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls),
+                                        reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
+  if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
+  float* loss_part = reinterpret_cast<float*>(w + p.off_loss);
+  if (p.n_tiles > 0) {
+    e = drt::launch_forward_fermat(A, p.n_tiles, p.nw, power_dev, loss_part, loss_kind, log_eps, max_iter,
+                                   1.0f / conv_eps, st);
+    if (e != hipSuccess) return hip_fail(e, "Fermat forward launch");
+  }
+  if (loss_kind != DRT_LOSS_NONE && loss_dev) {
+    const double scale = loss_kind == DRT_LOSS_NEG_MEAN_LOG_POWER
+                             ? (scene->n_rx > 0 ? -1.0 / (double)scene->n_rx : 0.0)
+                             : 1.0;
+    e = drt::launch_reduce_scalar(loss_part, p.n_tiles, scale, loss_dev, st);
+    if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
+  }
+  return DRT_OK;
 }
 
 int drt_adam_tx(float* tx_dev, const float* grad_dev, float* m_dev, float* v_dev, int32_t* step_dev,

@@ -54,15 +54,18 @@ struct drt_mlp {
   drt::MlpLayout L{};
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *Bf = nullptr;
   int* step = nullptr;
-  __bf16 *wbf = nullptr, *wtbf = nullptr, *X0 = nullptr, *H = nullptr, *dZ0 = nullptr, *dZ1 = nullptr;
+  __bf16 *wbf = nullptr, *wtbf = nullptr, *H = nullptr, *dZ0 = nullptr, *dZ1 = nullptr;
+  // transposed copies for the weight gradients: X0^T [128][max_batch],
+  // H_l^T [256][max_batch] (l = 0..3), dZ^T [256][max_batch]
+  __bf16 *X0T = nullptr, *HT = nullptr, *dZT = nullptr;
   float *yhat = nullptr, *gvec = nullptr, *loss_part = nullptr, *dw_part = nullptr, *col_part = nullptr;
 };
 
 namespace {
 
 void free_mlp(drt_mlp* h) {
-  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->X0, h->H, h->dZ0, h->dZ1,
-                  h->yhat, h->gvec, h->loss_part, h->dw_part, h->col_part};
+  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->H, h->dZ0, h->dZ1,
+                  h->X0T, h->HT, h->dZT, h->yhat, h->gvec, h->loss_part, h->dw_part, h->col_part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -75,32 +78,31 @@ __bf16* Hl(drt_mlp* h, int l) { return h->H + (size_t)l * h->max_batch * drt::kM
     if (e_ != hipSuccess) return failf(DRT_EHIP, "%s: %s", what, hipGetErrorString(e_)); \
   } while (0)
 
-// Hidden layers on n rows whose features are in X0: H_l = relu(X_l W_l + b_l).
-int enqueue_hidden(drt_mlp* h, int n, hipStream_t st) {
-  for (int l = 0; l < drt::kMlpHidden; ++l) {
-    drt::GemmArgs g{};
-    g.A = l == 0 ? h->X0 : Hl(h, l - 1);
-    g.lda = h->L.fan_in[l];
-    g.B = h->wtbf + h->L.bf_off[l];  // W^T [out][in]: B(k=in, n=out) = Wt[n * in + k]
-    g.ldb = h->L.fan_in[l];
-    g.M = n;
-    g.N = drt::kMlpWidth;
-    g.K = h->L.fan_in[l];
-    g.k_split = g.K;
-    g.bias = h->p + h->L.b_off[l];
-    g.relu = 1;
-    g.out_bf16 = Hl(h, l);
-    HIPCHK(drt::launch_gemm(g, false, false, 1, st), "hidden gemm");
-  }
-  return DRT_OK;
+drt::FusedArgs fused_args(drt_mlp* h, long long n) {
+  drt::FusedArgs a{};
+  a.R = 1;
+  a.n = n;
+  a.Bf = h->Bf;
+  a.wt = h->wtbf;
+  a.p = h->p;
+  a.L = h->L;
+  a.yhat = h->yhat;
+  a.h_stride = (long long)h->max_batch * drt::kMlpWidth;
+  return a;
 }
 
 // Forward + MSE + backward on rows [0, n) of v/y; gradients into h->g, loss
 // (mean squared error over n) into loss_dev.
 int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss_dev, hipStream_t st) {
-  HIPCHK(drt::launch_features(v, nullptr, nullptr, 1, 0, n, h->Bf, h->X0, st), "features");
-  int rc = enqueue_hidden(h, n, st);
-  if (rc) return rc;
+  // features and hidden layers in one kernel, keeping X0 and every H_l for the backward pass
+  drt::FusedArgs fa = fused_args(h, n);
+  fa.v = v;
+  fa.H = h->H;
+  fa.X0T = h->X0T;
+  fa.HT = h->HT;
+  fa.ht_stride = (long long)h->max_batch * drt::kMlpWidth;
+  fa.ld_t = h->max_batch;
+  HIPCHK(drt::launch_mlp_fused(fa, st), "fused forward");
   const drt::MlpLayout& L = h->L;
   const int W = drt::kMlpWidth;
   HIPCHK(drt::launch_head(Hl(h, 4), n, h->p + L.head_w, h->p + L.head_b, y, 1.0f / (float)n, h->yhat, h->loss_part,
@@ -109,26 +111,31 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss
   HIPCHK(drt::launch_colsum(Hl(h, 4), n, W, h->gvec, h->col_part, h->g + L.head_w, st), "head weight grad");
   HIPCHK(drt::launch_sum_scalar(h->gvec, n, 1.0, h->g + L.head_b, st), "head bias grad");
   if (loss_dev) HIPCHK(drt::launch_sum_scalar(h->loss_part, n, 1.0 / (double)n, loss_dev, st), "loss");
-  // split of the batch dimension for the weight gradients
-  int k_split = ((n + h->max_slices - 1) / h->max_slices + 63) / 64 * 64;
-  if (k_split < 64) k_split = 64;
+  // split of the batch dimension for the weight gradients: slices of at
+  // least kRowsPerSlice rows, at most max_slices of them
+  constexpr int kRowsPerSlice = 1024;
+  int k_split = std::max(kRowsPerSlice, ((n + h->max_slices - 1) / h->max_slices + 63) / 64 * 64);
   const int slices = (n + k_split - 1) / k_split;
+  const long long ldt = h->max_batch;
   __bf16* dZ = h->dZ0;
   __bf16* dZn = h->dZ1;
   for (int l = drt::kMlpHidden - 1; l >= 0; --l) {
     const int fi = L.fan_in[l];
     HIPCHK(drt::launch_colsum(dZ, n, W, nullptr, h->col_part, h->g + L.b_off[l], st), "bias grad");
+    // dW_l = X_l^T dZ_l with both operands row-contiguous in the batch index:
+    // A(m = in, k = row) = X_l^T[in][row], B(k = row, n = out) = dZ_l^T[out][row]
+    HIPCHK(drt::launch_transpose_bf16(dZ, n, W, h->dZT, ldt, st), "dZ transpose");
     drt::GemmArgs g{};
-    g.A = l == 0 ? h->X0 : Hl(h, l - 1);  // A(m = in, k = row) = X[row * fi + in]
-    g.lda = fi;
-    g.B = dZ;                             // B(k = row, n = out) = dZ[row * 256 + out]
-    g.ldb = W;
+    g.A = l == 0 ? h->X0T : h->HT + (size_t)(l - 1) * ldt * W;
+    g.lda = (int)ldt;
+    g.B = h->dZT;
+    g.ldb = (int)ldt;
     g.M = fi;
     g.N = W;
     g.K = n;
     g.k_split = k_split;
     g.out_f32 = h->dw_part;
-    HIPCHK(drt::launch_gemm(g, true, true, slices, st), "weight grad gemm");
+    HIPCHK(drt::launch_gemm(g, false, false, slices, st), "weight grad gemm");
     HIPCHK(drt::launch_sum_slices(h->dw_part, slices, fi * W, h->g + L.w_off[l], st), "weight grad sum");
     if (l > 0) {
       drt::GemmArgs d{};
@@ -191,10 +198,12 @@ int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_
   alloc((void**)&h->step, 16);
   alloc((void**)&h->wbf, (size_t)h->L.n_bf * 2);
   alloc((void**)&h->wtbf, (size_t)h->L.n_bf * 2);
-  alloc((void**)&h->X0, nb * drt::kMlpIn * 2);
   alloc((void**)&h->H, nb * W * 2 * drt::kMlpHidden);
   alloc((void**)&h->dZ0, nb * W * 2);
   alloc((void**)&h->dZ1, nb * W * 2);
+  alloc((void**)&h->X0T, nb * drt::kMlpIn * 2);
+  alloc((void**)&h->HT, nb * W * 2 * (drt::kMlpHidden - 1));
+  alloc((void**)&h->dZT, nb * W * 2);
   alloc((void**)&h->yhat, nb * 4);
   alloc((void**)&h->gvec, nb * 4);
   alloc((void**)&h->loss_part, nb * 4);
@@ -273,15 +282,11 @@ int drt_mlp_forward(drt_mlp* mlp, const float* v_dev, int64_t n, float* yhat_dev
   if (n < 0) return failf(DRT_EINVAL, "n is negative");
   if (n > 0 && (!v_dev || !yhat_dev)) return failf(DRT_EINVAL, "v_dev / yhat_dev is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  for (int64_t r0 = 0; r0 < n; r0 += mlp->max_batch) {
-    const int rows = (int)std::min<int64_t>(mlp->max_batch, n - r0);
-    HIPCHK(drt::launch_features(v_dev + 4 * r0, nullptr, nullptr, 1, 0, rows, mlp->Bf, mlp->X0, st), "features");
-    int rc = enqueue_hidden(mlp, rows, st);
-    if (rc) return rc;
-    HIPCHK(drt::launch_head(Hl(mlp, 4), rows, mlp->p + mlp->L.head_w, mlp->p + mlp->L.head_b, nullptr, 0.0f,
-                            yhat_dev + r0, nullptr, nullptr, nullptr, st),
-           "head");
-  }
+  // one fused launch over all rows: the activations never leave the workgroup
+  drt::FusedArgs fa = fused_args(mlp, n);
+  fa.v = v_dev;
+  fa.yhat = yhat_dev;
+  HIPCHK(drt::launch_mlp_fused(fa, st), "fused forward");
   return DRT_OK;
 }
 
@@ -296,13 +301,12 @@ int drt_mlp_scan(drt_mlp* mlp, const float* tx_dev, int32_t n_tx, const float* r
   for (int t0 = 0; t0 < n_tx; t0 += per) {
     const int nt = std::min(per, n_tx - t0);
     const int rows = nt * n_rx;
-    HIPCHK(drt::launch_features(nullptr, tx_dev, rx_dev, n_rx, (long long)t0 * n_rx, rows, mlp->Bf, mlp->X0, st),
-           "features");
-    int rc = enqueue_hidden(mlp, rows, st);
-    if (rc) return rc;
-    HIPCHK(drt::launch_head(Hl(mlp, 4), rows, mlp->p + mlp->L.head_w, mlp->p + mlp->L.head_b, nullptr, 0.0f,
-                            mlp->yhat, nullptr, nullptr, nullptr, st),
-           "head");
+    drt::FusedArgs fa = fused_args(mlp, rows);
+    fa.tx = tx_dev;
+    fa.rx = rx_dev;
+    fa.R = n_rx;
+    fa.row0 = (long long)t0 * n_rx;
+    HIPCHK(drt::launch_mlp_fused(fa, st), "fused forward");
     HIPCHK(drt::launch_segment_mean(mlp->yhat, nt, n_rx, F_dev + t0, st), "segment mean");
   }
   return DRT_OK;

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
     S.a6h = S.a6 + 0.5f;
     S.a6m = 0.5f - S.a6;
     S.dead_lim = (MODE ? kHardBandMargin / alpha : 128.0f / S.a2) * 1.00001f;
+    S.cull = B.screen != 0;
     // number of candidates of this scene
     int n_cand = 1, term = 0;
     for (int k = 1; k <= B.max_order; ++k) {

@@ -34,8 +34,36 @@ struct GemmArgs {
   __bf16* out_bf16;      // [M][N] or NULL
 };
 
-hipError_t launch_features(const float* v, const float* tx, const float* rx, int R, long long row0, int n,
-                           const float* Bf, __bf16* X0, hipStream_t st);
+// Fused forward of rows [0, n): features from v [n][4] (v != NULL) or from
+// the pairs (tx[(row0 + row) / R], rx[(row0 + row) % R]); hidden layers from
+// the bf16 W^T copies wt and the FP32 biases in p; yhat [n] out; optional
+// X0 [n][128] and H [5][h_stride] (layer l at H + l h_stride, [n][256]) out,
+// and the transposed inputs of the weight gradients, X0T [128][ld_t] and
+// HT [4][ht_stride] (H_l^T [256][ld_t] for l = 0..3; ld_t % 8 == 0).
+struct FusedArgs {
+  const float* v;
+  const float* tx;
+  const float* rx;
+  int R;
+  long long row0;
+  long long n;
+  const float* Bf;
+  const __bf16* wt;
+  const float* p;
+  MlpLayout L;
+  float* yhat;
+  __bf16* X0;
+  __bf16* H;
+  long long h_stride;
+  __bf16* X0T;
+  __bf16* HT;
+  long long ht_stride;
+  long long ld_t;
+};
+
+hipError_t launch_mlp_fused(const FusedArgs& a, hipStream_t st);
+// out[c][r] = in[r][c], bf16 [n][cols] -> [cols][ld]; n % 64 == 0, cols % 64 == 0.
+hipError_t launch_transpose_bf16(const __bf16* in, int n, int cols, __bf16* out, long long ld, hipStream_t st);
 hipError_t launch_gemm(const GemmArgs& g, bool a_mc, bool b_nc, int n_slices, hipStream_t st);
 hipError_t launch_head(const __bf16* H, int n, const float* w, const float* b, const float* y, float inv_total,
                        float* yhat, float* loss_part, float* gout, __bf16* dZ, hipStream_t st);

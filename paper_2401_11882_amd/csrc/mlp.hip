@@ -1,6 +1,7 @@
-// Learned surrogate of the log smoothed power map: Fourier features of
-// (tx, rx) and a 6-layer ReLU MLP (128 -> 256 x 5 -> 1), trained and evaluated
-// with BF16 MFMA (v_mfma_f32_16x16x32_bf16) and FP32 accumulation.
+// Learned surrogate of the log smoothed power map: Fourier features
+// gamma(v) = [sin(2 pi B v), cos(2 pi B v)] of v = (tx, rx) and a 6-layer ReLU
+// MLP (128 -> 256 x 5 -> 1), trained and evaluated with BF16 MFMA
+// (v_mfma_f32_16x16x32_bf16) and FP32 accumulation.
 //
 // Layouts (row-major): features X0 [n][128] bf16; hidden activations
 // H_l [n][256] bf16; weights of hidden layer l as bf16 in two copies,
@@ -15,37 +16,6 @@ namespace drt {
 typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
-
-// ---------------------------------------------------------------------------
-// Fourier features: gamma(v) = [sin(2 pi B v), cos(2 pi B v)], v in R^4.
-// Rows come from v [n][4], or (pairs mode) from tx[row / R], rx[row % R].
-// ---------------------------------------------------------------------------
-__global__ void k_features(const float* __restrict__ v, const float* __restrict__ tx,
-                           const float* __restrict__ rx, int R, long long row0, int n,
-                           const float* __restrict__ Bf, bf16* __restrict__ X0) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long long)n * 64) return;
-  const int row = (int)(gid >> 6), f = (int)(gid & 63);
-  float x0, x1, x2, x3;
-  if (v) {
-    x0 = v[4 * (size_t)row];
-    x1 = v[4 * (size_t)row + 1];
-    x2 = v[4 * (size_t)row + 2];
-    x3 = v[4 * (size_t)row + 3];
-  } else {
-    const long long g = row0 + row;
-    const int t = (int)(g / R), r = (int)(g % R);
-    x0 = tx[2 * t];
-    x1 = tx[2 * t + 1];
-    x2 = rx[2 * r];
-    x3 = rx[2 * r + 1];
-  }
-  const float tt = Bf[4 * f] * x0 + Bf[4 * f + 1] * x1 + Bf[4 * f + 2] * x2 + Bf[4 * f + 3] * x3;
-  float s, c;
-  sincospif(2.0f * tt, &s, &c);  // sin / cos of 2 pi tt with argument reduction in units of pi
-  X0[(size_t)row * 128 + f] = (bf16)s;
-  X0[(size_t)row * 128 + 64 + f] = (bf16)c;
-}
 
 // ---------------------------------------------------------------------------
 // C[M x N] = A[M x K] . B[K x N], BF16 in, FP32 accumulate.
@@ -157,6 +127,166 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Fused forward: features, the five hidden layers and the head of a tile of
+// kFusedRows rows in one workgroup.  The tile's activations stay in LDS
+// (bf16, [row][k]) from layer to layer; each layer's weights W^T [256][in]
+// stream through LDS in chunks of 32 k (double-buffered, shared by the
+// workgroup's 8 wavefronts).  Wavefront w owns rows 16 w .. 16 w + 15 of the
+// tile and all 256 output columns: 16 MFMA 16x16x32 accumulators, k in
+// increasing steps of 32 -- the accumulation order of k_gemm, so every
+// activation is bitwise the one of the layer-by-layer path.  After a layer's
+// last chunk every wavefront has finished reading the activations, and the
+// new ones (bias, ReLU, bf16) overwrite them in place; optionally they also
+// go to global memory for the backward pass.  The head is k_head's per-row
+// dot product (4 columns per lane, then the wave sum).
+// ---------------------------------------------------------------------------
+constexpr int kFusedWaves = 8;
+constexpr int kFusedRows = 16 * kFusedWaves;
+constexpr int ALD = 256 + 8;    // activation row stride (bf16): 132 dwords, rows 4 banks apart
+constexpr int WKC = 32;         // k per staged weight chunk
+constexpr int WLD = WKC + 8;    // weight chunk row stride (bf16): 20 dwords
+
+// Row-major store of the tile's first `cols` activation columns, 16 bytes
+// per thread (rows past n are not stored).
+__device__ __forceinline__ void store_tile(const bf16* act, int cols, long long tile0, long long n, bf16* out) {
+  const int per_row = cols / 8;
+  for (int i = threadIdx.x; i < kFusedRows * per_row; i += kFusedWaves * 64) {
+    const int r = i / per_row, c8 = (i - r * per_row) * 8;
+    if (tile0 + r < n)
+      *reinterpret_cast<uint4*>(out + (tile0 + r) * cols + c8) = *reinterpret_cast<const uint4*>(&act[r * ALD + c8]);
+  }
+}
+
+// Transposed store out[col][tile0 + r] (row stride ld): 8 rows of one column
+// per thread, 16 bytes (rows past n are zero; ld and tile0 are multiples of 8).
+__device__ __forceinline__ void store_tile_t(const bf16* act, int cols, long long tile0, long long n, bf16* out,
+                                             long long ld) {
+  constexpr int kChunks = kFusedRows / 8;
+  for (int i = threadIdx.x; i < cols * kChunks; i += kFusedWaves * 64) {
+    const int col = i / kChunks, r8 = (i - col * kChunks) * 8;
+    if (tile0 + r8 >= n) continue;
+    bf16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = tile0 + r8 + q < n ? act[(r8 + q) * ALD + col] : (bf16)0.0f;
+    *reinterpret_cast<bf16x8*>(out + (size_t)col * ld + tile0 + r8) = v;
+  }
+}
+
+__global__ __launch_bounds__(kFusedWaves * 64) void k_mlp_fused(FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 act[kFusedRows * ALD];
+  __shared__ __attribute__((aligned(16))) bf16 wch[2][256 * WLD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const long long tile0 = (long long)blockIdx.x * kFusedRows;
+
+  // features of the tile's rows (rows past n get zeros and are never stored)
+  for (int i = tid; i < kFusedRows * 64; i += kFusedWaves * 64) {
+    const int r = i >> 6, f = i & 63;
+    const long long row = tile0 + r;
+    float s = 0.0f, c = 0.0f;
+    if (row < a.n) {
+      float x0, x1, x2, x3;
+      if (a.v) {
+        x0 = a.v[4 * row];
+        x1 = a.v[4 * row + 1];
+        x2 = a.v[4 * row + 2];
+        x3 = a.v[4 * row + 3];
+      } else {
+        const long long g = a.row0 + row;
+        const int t = (int)(g / a.R), q = (int)(g % a.R);
+        x0 = a.tx[2 * t];
+        x1 = a.tx[2 * t + 1];
+        x2 = a.rx[2 * q];
+        x3 = a.rx[2 * q + 1];
+      }
+      const float tt = a.Bf[4 * f] * x0 + a.Bf[4 * f + 1] * x1 + a.Bf[4 * f + 2] * x2 + a.Bf[4 * f + 3] * x3;
+      sincospif(2.0f * tt, &s, &c);
+    }
+    act[r * ALD + f] = (bf16)s;
+    act[r * ALD + 64 + f] = (bf16)c;
+  }
+  if (a.X0 || a.X0T) {
+    __syncthreads();
+    if (a.X0) store_tile(act, 128, tile0, a.n, a.X0);
+    if (a.X0T) store_tile_t(act, 128, tile0, a.n, a.X0T, a.ld_t);
+  }
+
+  const int ar = wave * 16 + (lane & 15);  // this lane's A row in the tile
+  const int kq = 8 * (lane >> 4);          // and its 8-wide k slot within a 32-k step
+  // staging of a weight chunk (256 columns x 32 k): thread -> (output column, 16-k half)
+  const int sc = tid >> 1, sh = (tid & 1) * 16;
+#pragma unroll 1
+  for (int l = 0; l < kMlpHidden; ++l) {
+    const int K = a.L.fan_in[l];
+    const bf16* Wt = a.wt + a.L.bf_off[l];  // [256][K]
+    const float* bias = a.p + a.L.b_off[l];
+    const int nch = K / WKC;
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(Wt + (size_t)sc * K + sh);
+      uint4* dst = reinterpret_cast<uint4*>(&wch[0][sc * WLD + sh]);
+      dst[0] = src[0];
+      dst[1] = src[1];
+    }
+    __syncthreads();  // features / previous layer's outputs and chunk 0 in place
+    floatx4 acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+    for (int kc = 0; kc < nch; ++kc) {
+      const int buf = kc & 1;
+      uint4 nx0, nx1;
+      const bool more = kc + 1 < nch;
+      if (more) {
+        const uint4* src = reinterpret_cast<const uint4*>(Wt + (size_t)sc * K + (kc + 1) * WKC + sh);
+        nx0 = src[0];
+        nx1 = src[1];
+      }
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[ar * ALD + kc * WKC + kq]);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(&wch[buf][(j * 16 + (lane & 15)) * WLD + kq]);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[j], 0, 0, 0);
+      }
+      if (more) {
+        uint4* dst = reinterpret_cast<uint4*>(&wch[buf ^ 1][sc * WLD + sh]);
+        dst[0] = nx0;
+        dst[1] = nx1;
+      }
+      __syncthreads();
+    }
+    // every wavefront is past its last read of this layer's inputs
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int col = j * 16 + (lane & 15);
+      const float b = bias[col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wave * 16 + 4 * (lane >> 4) + q;
+        act[r * ALD + col] = (bf16)fmaxf(acc[j][q] + b, 0.0f);
+      }
+    }
+    __syncthreads();
+    if (a.H) store_tile(act, 256, tile0, a.n, a.H + (size_t)l * a.h_stride);
+    if (a.HT && l + 1 < kMlpHidden) store_tile_t(act, 256, tile0, a.n, a.HT + (size_t)l * a.ht_stride, a.ld_t);
+  }
+  // head: rows of this wavefront, k_head's order
+  const float* hw = a.p + a.L.head_w;
+  float wv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
+  const float hb = a.p[a.L.head_b];
+#pragma unroll 1
+  for (int i = 0; i < 16; ++i) {
+    const int r = wave * 16 + i;
+    float part = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part = fmaf((float)act[r * ALD + lane * 4 + q], wv[q], part);
+    const float yh = wave_sum(part) + hb;
+    if (lane == 0 && tile0 + r < a.n) a.yhat[tile0 + r] = yh;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Head: yhat = H[m] . w + b (FP32).  Training: d = yhat - y, loss_part[m] = d^2,
 // g[m] = 2 d / n_total, dZ[m][i] = bf16(g w[i] (H[m][i] > 0)).
 // One wavefront per row; 4 rows per workgroup.
@@ -188,6 +318,32 @@ __global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ H, int n,
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) dZ[(size_t)m * 256 + lane * 4 + q] = (bf16)(h[q] > 0.0f ? gm * wv[q] : 0.0f);
+  }
+}
+
+// out[c][r] = in[r][c] for a bf16 [n][cols] matrix (out row stride ld):
+// 64 x 64 tiles through LDS, 16-byte loads and stores.  n % 64 == 0.
+__global__ __launch_bounds__(256) void k_transpose_bf16(const bf16* __restrict__ in, int n, int cols,
+                                                        bf16* __restrict__ out, long long ld) {
+  __shared__ bf16 t[64][64 + 8];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+#pragma unroll
+  for (int rep = 0; rep < 2; ++rep) {
+    const int i = threadIdx.x + rep * 256;
+    const int r = i >> 3, c8 = (i & 7) * 8;
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(in + (size_t)(r0 + r) * cols + c0 + c8);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t[r][c8 + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rep = 0; rep < 2; ++rep) {
+    const int i = threadIdx.x + rep * 256;
+    const int c = i >> 3, r8 = (i & 7) * 8;
+    bf16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = t[r8 + q][c];
+    *reinterpret_cast<bf16x8*>(out + (size_t)(c0 + c) * ld + r0 + r8) = v;
   }
 }
 
@@ -380,14 +536,6 @@ __global__ void k_log_eps(const float* __restrict__ P, long long n, float eps, f
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_features(const float* v, const float* tx, const float* rx, int R, long long row0, int n,
-                           const float* Bf, bf16* X0, hipStream_t st) {
-  const long long threads = (long long)n * 64;
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, v, tx, rx, R, row0,
-                     n, Bf, X0);
-  return hipGetLastError();
-}
-
 hipError_t launch_gemm(const GemmArgs& g, bool a_mc, bool b_nc, int n_slices, hipStream_t st) {
   const dim3 grid((g.M + GT - 1) / GT, g.N / GT, n_slices);
   if (!a_mc && !b_nc) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, g);
@@ -397,10 +545,24 @@ hipError_t launch_gemm(const GemmArgs& g, bool a_mc, bool b_nc, int n_slices, hi
   return hipGetLastError();
 }
 
+hipError_t launch_mlp_fused(const FusedArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  const unsigned tiles = (unsigned)((a.n + kFusedRows - 1) / kFusedRows);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(tiles), dim3(kFusedWaves * 64), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_head(const bf16* H, int n, const float* w, const float* b, const float* y, float inv_total,
                        float* yhat, float* loss_part, float* gout, bf16* dZ, hipStream_t st) {
   hipLaunchKernelGGL(k_head, dim3((n + 3) / 4), dim3(256), 0, st, H, n, w, b, y, inv_total, yhat, loss_part, gout,
                      dZ);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(const bf16* in, int n, int cols, bf16* out, long long ld, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n % 64 != 0 || cols % 64 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose_bf16, dim3(n / 64, cols / 64), dim3(256), 0, st, in, n, cols, out, ld);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct SceneView {
   float dmin2;
   float dead_lim;  // parameter range beyond which a factor is exactly 0 (see screen.h)
   float a6, a6h, a6m;  // hard sigmoid: alpha / 6, alpha / 6 + 1/2, 1/2 - alpha / 6
+  int cull;        // 1: skip (wall, leg) tests whose factor is provably 1 (culling); 0: test all
 };
 
 
@@ -292,7 +293,8 @@ __device__ __forceinline__ bool sat_separated(const WallBox& q, float ux, float 
 }
 
 // Calls fn(wall, masks, bit) for every wall that is not separated from some
-// leg box (walls in increasing order) until fn returns false; masks[l] bit
+// leg box (every wall when S.cull is 0; walls in increasing order) until fn
+// returns false; masks[l] bit
 // `bit` tells whether leg l needs the test (its own end walls are excluded
 // here).  Lane j of the wavefront checks wall b + j of each 64-wall batch.
 // Separating axes: u and v (the wall's projection, centre +- half extent,
@@ -335,7 +337,8 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
         lo = t ? P.lo[l] : lo;
         hi = t ? P.hi[l] : hi;
       }
-      const bool ov = valid & !empty & !sat_separated(q, ux, uy, umid, uh, vmid, vh) & (wj != lo) & (wj != hi);
+      const bool ov = valid & (!S.cull | (!empty & !sat_separated(q, ux, uy, umid, uh, vmid, vh))) & (wj != lo) &
+                      (wj != hi);
       const uint64_t M = ballot(ov);
       const uint64_t low = (1ull << r) - 1ull;
 #pragma unroll
@@ -355,7 +358,7 @@ __device__ __forceinline__ void visit_walls(const SceneView& S, const Path<K>& P
 #pragma unroll
       for (int l = 0; l <= K; ++l) {
         const LegBox& L = B[l];
-        const bool ov = valid & !L.empty & !sat_separated(q, L.ux, L.uy, L.umid, L.uh, L.vmid, L.vh) &
+        const bool ov = valid & (!S.cull | (!L.empty & !sat_separated(q, L.ux, L.uy, L.umid, L.uh, L.vmid, L.vh))) &
                         (wj != P.lo[l]) & (wj != P.hi[l]);
         m[l] = ballot(ov);
         uni |= m[l];

@@ -41,6 +41,8 @@ hipError_t launch_prep_walls(const float* walls, int n, float cull_c, WallRec* o
                              hipStream_t st);
 hipError_t launch_forward(const TraceArgs& A, int n_tiles, int nw, float* power, float* seed,
                           float* loss_part, int loss_kind, float log_eps, hipStream_t st);
+hipError_t launch_forward_fermat(const TraceArgs& A, int n_tiles, int nw, float* power, float* loss_part,
+                                 int loss_kind, float log_eps, int max_iter, float inv_eps, hipStream_t st);
 hipError_t launch_backward(const TraceArgs& A, int n_tiles, int nw, const float* gP, float* part,
                            float* grad_rx, int reuse, hipStream_t st);
 size_t backward_lds_bytes(int nw, int n_walls);

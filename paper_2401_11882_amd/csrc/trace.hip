@@ -39,29 +39,13 @@
 #include "path.h"
 #include "screen.h"
 #include "trace.h"
+#include "view.h"
 
 namespace drt {
 
 // ---------------------------------------------------------------------------
 // Forward kernel
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ SceneView view_of(const TraceArgs& A) {
-  SceneView S;
-  S.walls = A.walls;
-  S.boxes = A.boxes;
-  S.n_walls = A.n_walls;
-  S.alpha = A.alpha;
-  S.a2 = A.a2;
-  S.band_k = A.band_k;
-  S.cull_c = A.cull_c;
-  S.dmin2 = A.dmin2;
-  S.a6 = A.alpha * (1.0f / 6.0f);
-  S.a6h = S.a6 + 0.5f;
-  S.a6m = 0.5f - S.a6;
-  S.dead_lim = (A.mode ? kHardBandMargin / A.alpha : 128.0f / A.a2) * 1.00001f;
-  return S;
-}
 
 template <int NW, int MODE>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_forward(TraceArgs A, float* __restrict__ power,
@@ -77,8 +61,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   const int tile = blockIdx.x;
   const int m = rx_of_lane(tile, lane, A.grid_nx);
   const bool live = m < A.n_rx;
-  const float rxx = live ? A.rx[2 * m] : 0.5f;
-  const float rxy = live ? A.rx[2 * m + 1] : 0.5f;
+  float rxx, rxy;
+  receiver_of(A, m, live, rxx, rxy);
   const float txx = A.tx[0], txy = A.tx[1];
 
   const int slot = tile * NW + wave;
@@ -181,8 +165,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   const int tile = blockIdx.x;
   const int m = rx_of_lane(tile, lane, A.grid_nx);
   const bool live = m < A.n_rx;
-  const float rxx = live ? A.rx[2 * m] : 0.5f;
-  const float rxy = live ? A.rx[2 * m + 1] : 0.5f;
+  float rxx, rxy;
+  receiver_of(A, m, live, rxx, rxy);
   const float g = live ? gP[m] : 0.0f;
   const float txx = A.tx[0], txy = A.tx[1];
   LaneGrad G{0.0f, 0.0f, 0.0f, 0.0f};

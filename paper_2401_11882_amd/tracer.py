@@ -41,18 +41,29 @@ def stream_handle(stream=None) -> ctypes.c_void_p:
 
 
 class Scene:
-    """Device-resident scene description (walls [W,4], tx [2], rx [R,2])."""
+    """Device-resident scene description (walls [W,4], tx [2], rx [R,2]).
+
+    rx=None with grid_nx, grid_ny > 0 leaves the receivers to the library:
+    the cell centres of a grid_nx x grid_ny grid over [0,1]^2 (no receiver
+    array is passed)."""
 
     def __init__(self, walls, tx, rx, max_order: int, alpha: float, d_min: float = DEFAULT_DMIN,
-                 grid_nx: int = 0, smoothing: str = "sigmoid"):
+                 grid_nx: int = 0, smoothing: str = "sigmoid", grid_ny: int = 0):
         self.walls = _dev_f32(walls, "walls", (4,)) if walls.numel() else walls
         self.tx = _dev_f32(tx, "tx")
         if self.tx.numel() != 2:
             raise ValueError("tx must hold 2 floats")
-        self.rx = _dev_f32(rx, "rx", (2,))
         dev = self.tx.device
+        if rx is None:
+            if grid_nx <= 0 or grid_ny <= 0:
+                raise ValueError("rx=None needs grid_nx > 0 and grid_ny > 0")
+            self.rx = None
+            self._n_rx = int(grid_nx) * int(grid_ny)
+        else:
+            self.rx = _dev_f32(rx, "rx", (2,))
+            self._n_rx = int(self.rx.shape[0])
         for t, nm in ((self.walls, "walls"), (self.rx, "rx")):
-            if t.numel() and t.device != dev:
+            if t is not None and t.numel() and t.device != dev:
                 raise ValueError(f"{nm} is on {t.device}, tx on {dev}")
         self.max_order = int(max_order)
         self.alpha = float(alpha)
@@ -67,13 +78,14 @@ class Scene:
 
     @property
     def n_rx(self):
-        return int(self.rx.shape[0])
+        return self._n_rx
 
     def c_struct(self) -> DrtScene:
         return DrtScene(
             walls_dev=self.walls.data_ptr() if self.n_walls else None, n_walls=self.n_walls,
             tx_dev=self.tx.data_ptr(),
-            rx_dev=self.rx.data_ptr() if self.n_rx else None, n_rx=self.n_rx, rx_grid_nx=self.grid_nx,
+            rx_dev=self.rx.data_ptr() if (self.rx is not None and self.n_rx) else None, n_rx=self.n_rx,
+            rx_grid_nx=self.grid_nx,
             max_order=self.max_order, alpha=self.alpha, smoothing=self.smoothing, d_min=self.d_min)
 
 
@@ -148,6 +160,19 @@ def forward(scene: Scene, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS,
     check(lib().drt_forward(ctypes.byref(sc), _lib.LOSS[loss], float(log_eps), _ptr(P), _ptr(L),
                             _ptr(seed), _ptr(ws), nbytes, stream_handle(stream)))
     return P, L, seed
+
+
+def forward_fermat(scene: Scene, loss: str = "none", log_eps: float = DEFAULT_LOG_EPS, max_iter: int = 16,
+                   conv_eps: float = 1e-4, stream=None):
+    """P(r) [R] (and the loss scalar) with Fermat path tracing in place of the
+    image method (drt_forward_fermat; orders <= 2)."""
+    sc = scene.c_struct()
+    ws, nbytes = workspace(sc, scene.device)
+    P = torch.empty(scene.n_rx, dtype=torch.float32, device=scene.device)
+    L = torch.empty(1, dtype=torch.float32, device=scene.device) if loss != "none" else None
+    check(lib().drt_forward_fermat(ctypes.byref(sc), int(max_iter), float(conv_eps), _lib.LOSS[loss],
+                                   float(log_eps), _ptr(P), _ptr(L), _ptr(ws), nbytes, stream_handle(stream)))
+    return P, L
 
 
 def backward(scene: Scene, grad_power: torch.Tensor, want_rx: bool = False, reuse_forward: bool = False,

@@ -87,7 +87,6 @@ def test_workspace_size_host_only():
     ("smoothing", 2, _lib.DRT_ENOTSUP),
     ("walls_dev", None, _lib.DRT_EINVAL),
     ("tx_dev", None, _lib.DRT_EINVAL),
-    ("rx_dev", None, _lib.DRT_EINVAL),
 ])
 def test_scene_validation(field, value, code):
     L = _lib.lib()
@@ -176,7 +175,6 @@ def _scene3(**kw):
     ("smoothing", 2, _lib.DRT_ENOTSUP),
     ("panels_dev", None, _lib.DRT_EINVAL),
     ("tx_dev", None, _lib.DRT_EINVAL),
-    ("rx_dev", None, _lib.DRT_EINVAL),
 ])
 def test_scene3_validation(field, value, code):
     L = _lib.lib()
@@ -237,3 +235,13 @@ def test_noalloc_validation_before_any_device_call():
                                           None) == _lib.DRT_EINVAL
     msg = L.drt_last_error().decode()
     assert "allocation-free" in msg and "drt_forward_backward" in msg
+
+
+def test_receiver_grid_needs_a_row_length():
+    """rx_dev == NULL selects the library's receiver grid, which needs rx_grid_nx."""
+    L = _lib.lib()
+    n = ctypes.c_size_t()
+    sc = _scene(rx_dev=None, rx_grid_nx=0)
+    assert L.drt_workspace_size(ctypes.byref(sc), ctypes.byref(n)) == _lib.DRT_EINVAL
+    sc = _scene(rx_dev=None, rx_grid_nx=32)
+    assert L.drt_workspace_size(ctypes.byref(sc), ctypes.byref(n)) == 0

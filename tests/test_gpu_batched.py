@@ -220,6 +220,18 @@ def test_full_batch_512_sampled():
         torch.testing.assert_close(P[rs], P1, rtol=2e-6, atol=0)
         assert PU.rel_l2(gtx[s_i].numpy(), g1.numpy()) < 1e-5
         assert PU.rel_l2(gw[ws].numpy(), w1.numpy()) < 1e-5
+    # the two cheapest scenes in full against the oracle: every receiver's
+    # power, the scene's loss and its gradients (tx and every wall endpoint)
+    cost = [s.n_rx * WL.n_candidates(s.walls.shape[0], 2) for s in scenes]
+    for s_i in np.argsort(cost)[:2]:
+        s = scenes[s_i]
+        rs, ws = plan.scene_slice(s_i)
+        P_o, L_o, gw_o, gt_o, _ = T.forward_backward(s.walls, s.tx, s.rx, 2, s.alpha)
+        _, kap = PU.kappa(s.walls, s.tx, s.rx, 2, s.alpha, P0=P_o, runs=2)
+        st = PU.check_power(P[rs].numpy(), P_o, kap, f"scene {s_i} (full)")
+        assert float(L[s_i]) == pytest.approx(L_o, rel=1e-5, abs=1e-5)
+        PU.check_grads(gtx[s_i].numpy(), gw[ws].numpy(), gt_o, gw_o, f"scene {s_i} (full)")
+        print(f"batched scene {s_i}: {s.walls.shape[0]} walls, {s.n_rx} rx, {st}", flush=True)
     plan.close()
 
 
