@@ -47,6 +47,9 @@ drt::MlpLayout make_layout() {
 
 }  // namespace
 
+// Tiles of the fused forward per scan launch (the tile-sum buffer's size).
+constexpr int kMaxTiles = 1 << 20;
+
 struct drt_mlp {
   int device = 0;
   int max_batch = 0;
@@ -54,18 +57,20 @@ struct drt_mlp {
   drt::MlpLayout L{};
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *Bf = nullptr;
   int* step = nullptr;
-  __bf16 *wbf = nullptr, *wtbf = nullptr, *H = nullptr, *dZ0 = nullptr, *dZ1 = nullptr;
+  __bf16 *wbf = nullptr, *wtbf = nullptr, *H = nullptr, *dZ0 = nullptr;
   // transposed copies for the weight gradients: X0^T [128][max_batch],
-  // H_l^T [256][max_batch] (l = 0..3), dZ^T [256][max_batch]
+  // H_l^T [256][max_batch] (l = 0..3), dZ_l^T [256][max_batch] (l = 0..4)
   __bf16 *X0T = nullptr, *HT = nullptr, *dZT = nullptr;
   float *yhat = nullptr, *gvec = nullptr, *loss_part = nullptr, *dw_part = nullptr, *col_part = nullptr;
+  double* tile_sum = nullptr;  // [kMaxTiles] per-tile yhat sums of the scan
+  float* db_part = nullptr;    // [5][max_slices][256] bias-gradient partials
 };
 
 namespace {
 
 void free_mlp(drt_mlp* h) {
-  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->H, h->dZ0, h->dZ1,
-                  h->X0T, h->HT, h->dZT, h->yhat, h->gvec, h->loss_part, h->dw_part, h->col_part};
+  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->H, h->dZ0,
+                  h->X0T, h->HT, h->dZT, h->yhat, h->gvec, h->loss_part, h->dw_part, h->col_part, h->tile_sum, h->db_part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -111,48 +116,36 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss
   HIPCHK(drt::launch_colsum(Hl(h, 4), n, W, h->gvec, h->col_part, h->g + L.head_w, st), "head weight grad");
   HIPCHK(drt::launch_sum_scalar(h->gvec, n, 1.0, h->g + L.head_b, st), "head bias grad");
   if (loss_dev) HIPCHK(drt::launch_sum_scalar(h->loss_part, n, 1.0 / (double)n, loss_dev, st), "loss");
-  // split of the batch dimension for the weight gradients: slices of at
-  // least kRowsPerSlice rows, at most max_slices of them
-  constexpr int kRowsPerSlice = 1024;
-  int k_split = std::max(kRowsPerSlice, ((n + h->max_slices - 1) / h->max_slices + 63) / 64 * 64);
-  const int slices = (n + k_split - 1) / k_split;
+  // input gradients of hidden layers 4..1, every dZ_l stored transposed
   const long long ldt = h->max_batch;
-  __bf16* dZ = h->dZ0;
-  __bf16* dZn = h->dZ1;
-  for (int l = drt::kMlpHidden - 1; l >= 0; --l) {
-    const int fi = L.fan_in[l];
-    HIPCHK(drt::launch_colsum(dZ, n, W, nullptr, h->col_part, h->g + L.b_off[l], st), "bias grad");
-    // dW_l = X_l^T dZ_l with both operands row-contiguous in the batch index:
-    // A(m = in, k = row) = X_l^T[in][row], B(k = row, n = out) = dZ_l^T[out][row]
-    HIPCHK(drt::launch_transpose_bf16(dZ, n, W, h->dZT, ldt, st), "dZ transpose");
-    drt::GemmArgs g{};
-    g.A = l == 0 ? h->X0T : h->HT + (size_t)(l - 1) * ldt * W;
-    g.lda = (int)ldt;
-    g.B = h->dZT;
-    g.ldb = (int)ldt;
-    g.M = fi;
-    g.N = W;
-    g.K = n;
-    g.k_split = k_split;
-    g.out_f32 = h->dw_part;
-    HIPCHK(drt::launch_gemm(g, false, false, slices, st), "weight grad gemm");
-    HIPCHK(drt::launch_sum_slices(h->dw_part, slices, fi * W, h->g + L.w_off[l], st), "weight grad sum");
-    if (l > 0) {
-      drt::GemmArgs d{};
-      d.A = dZ;                            // [n][256]
-      d.lda = W;
-      d.B = h->wbf + L.bf_off[l];          // W [in][out]: B(k = out, n = in) = W[n * 256 + k]
-      d.ldb = W;
-      d.M = n;
-      d.N = fi;
-      d.K = W;
-      d.k_split = W;
-      d.mask = Hl(h, l - 1);               // ReLU derivative of the layer below
-      d.out_bf16 = dZn;
-      HIPCHK(drt::launch_gemm(d, false, false, 1, st), "input grad gemm");
-      std::swap(dZ, dZn);
-    }
-  }
+  drt::DxArgs dx{};
+  dx.dz4 = h->dZ0;
+  dx.H = h->H;
+  dx.h_stride = (long long)h->max_batch * W;
+  dx.w = h->wbf;
+  dx.L = L;
+  dx.dZT = h->dZT;
+  dx.dzt_stride = ldt * W;
+  dx.ld = ldt;
+  dx.n = n;
+  HIPCHK(drt::launch_mlp_dx(dx, st), "input gradients");
+  // weight and bias gradients of every hidden layer: slices of at least
+  // kSliceRows rows, at most max_slices of them
+  constexpr int kSliceRows = 512;
+  drt::DwArgs dw{};
+  dw.X0T = h->X0T;
+  dw.HT = h->HT;
+  dw.ht_stride = ldt * W;
+  dw.dZT = h->dZT;
+  dw.dzt_stride = ldt * W;
+  dw.ld = ldt;
+  dw.n = n;
+  dw.slice_rows = std::max(kSliceRows, ((n + h->max_slices - 1) / h->max_slices + 31) / 32 * 32);
+  dw.n_slices = (n + dw.slice_rows - 1) / dw.slice_rows;
+  dw.L = L;
+  dw.part = h->dw_part;
+  dw.part_b = h->db_part;
+  HIPCHK(drt::launch_mlp_dw(dw, h->g, st), "weight gradients");
   return DRT_OK;
 }
 
@@ -184,7 +177,7 @@ int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_
   if (!h) return failf(DRT_EINVAL, "out of host memory");
   h->L = make_layout();
   h->max_batch = max_batch;
-  h->max_slices = 64;
+  h->max_slices = 32;
   const size_t P = h->L.n_params, nb = (size_t)max_batch, W = drt::kMlpWidth;
   hipError_t e = hipGetDevice(&h->device);
   auto alloc = [&e](void** ptr, size_t bytes) {
@@ -200,15 +193,16 @@ int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_
   alloc((void**)&h->wtbf, (size_t)h->L.n_bf * 2);
   alloc((void**)&h->H, nb * W * 2 * drt::kMlpHidden);
   alloc((void**)&h->dZ0, nb * W * 2);
-  alloc((void**)&h->dZ1, nb * W * 2);
   alloc((void**)&h->X0T, nb * drt::kMlpIn * 2);
   alloc((void**)&h->HT, nb * W * 2 * (drt::kMlpHidden - 1));
-  alloc((void**)&h->dZT, nb * W * 2);
+  alloc((void**)&h->dZT, nb * W * 2 * drt::kMlpHidden);
   alloc((void**)&h->yhat, nb * 4);
   alloc((void**)&h->gvec, nb * 4);
   alloc((void**)&h->loss_part, nb * 4);
-  alloc((void**)&h->dw_part, (size_t)h->max_slices * W * W * 4);
+  alloc((void**)&h->dw_part, (size_t)drt::kMlpHidden * h->max_slices * W * W * 4);
   alloc((void**)&h->col_part, (size_t)drt::colsum_chunks(max_batch) * W * 4);
+  alloc((void**)&h->tile_sum, (size_t)kMaxTiles * sizeof(double));
+  alloc((void**)&h->db_part, (size_t)drt::kMlpHidden * h->max_slices * W * 4);
   if (e == hipSuccess) e = hipMemcpy(h->p, params_host, P * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->Bf, fourier_B_host, drt::kMlpFreq * 4 * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(h->m, 0, P * 4);
@@ -297,6 +291,26 @@ int drt_mlp_scan(drt_mlp* mlp, const float* tx_dev, int32_t n_tx, const float* r
     return failf(DRT_EINVAL, "n_tx=%d n_rx=%d (need 0 < n_rx <= max_batch=%d)", n_tx, n_rx, mlp->max_batch);
   if (n_tx > 0 && (!tx_dev || !rx_dev || !F_dev)) return failf(DRT_EINVAL, "NULL device array");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const int tile = drt::mlp_fused_rows();
+  if (n_rx % tile == 0) {
+    // whole tiles per transmitter: the fused forward sums each tile's yhat and
+    // the means follow from the tile sums, kMaxTiles tiles per launch
+    const int tiles_per_tx = n_rx / tile;
+    const int per = std::max(1, kMaxTiles / tiles_per_tx);
+    for (int t0 = 0; t0 < n_tx; t0 += per) {
+      const int nt = std::min(per, n_tx - t0);
+      drt::FusedArgs fa = fused_args(mlp, (long long)nt * n_rx);
+      fa.yhat = nullptr;
+      fa.tile_sum = mlp->tile_sum;
+      fa.tx = tx_dev;
+      fa.rx = rx_dev;
+      fa.R = n_rx;
+      fa.row0 = (long long)t0 * n_rx;
+      HIPCHK(drt::launch_mlp_fused(fa, st), "fused forward");
+      HIPCHK(drt::launch_tile_mean(mlp->tile_sum, nt, tiles_per_tx, n_rx, F_dev + t0, st), "tile means");
+    }
+    return DRT_OK;
+  }
   const int per = mlp->max_batch / n_rx;  // transmitters per chunk
   for (int t0 = 0; t0 < n_tx; t0 += per) {
     const int nt = std::min(per, n_tx - t0);

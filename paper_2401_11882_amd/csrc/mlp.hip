@@ -15,142 +15,35 @@ namespace drt {
 
 typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 
 // ---------------------------------------------------------------------------
-// C[M x N] = A[M x K] . B[K x N], BF16 in, FP32 accumulate.
-//   A(m, k) = A[m * lda + k]          (A_MC = false)
-//           = A[k * lda + m]          (A_MC = true)
-//   B(k, n) = B[n * ldb + k]          (B_NC = false)
-//           = B[k * ldb + n]          (B_NC = true)
-// Tile 64 x 64 x 64 per workgroup of 4 wavefronts (2 x 2, 32 x 32 each, as
-// 2 x 2 MFMA 16x16x32 tiles).  Both operand tiles sit in LDS with k
-// contiguous so every fragment is one 16-byte LDS read.  gridDim.z splits K
-// (k_split per slice); slice z writes out_f32 + z * M * N.
-// Epilogue: + bias[n], ReLU, * (mask[m][n] > 0), then FP32 and/or BF16 out.
-// Requires N % 64 == 0, K % 64 == 0, k_split % 64 == 0, lda / ldb % 8 == 0.
-// ---------------------------------------------------------------------------
-constexpr int GT = 64;          // tile edge
-constexpr int GLD = GT + 8;     // LDS row stride (bf16), 144 bytes
-
-template <bool A_MC, bool B_NC>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) bf16 As[GT * GLD];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[GT * GLD];
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
-  const int kb = blockIdx.z * g.k_split;
-  const int ke = min(g.K, kb + g.k_split);
-  const bf16x8 zero8 = {};
-
-  floatx4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
-
-  for (int k0 = kb; k0 < ke; k0 += GT) {
-    // stage A tile rows m0..m0+63, k0..k0+63 into As[m][k]
-#pragma unroll
-    for (int rep = 0; rep < 2; ++rep) {
-      const int c = t + rep * 256;
-      if (!A_MC) {
-        const int r = c >> 3, kc = (c & 7) * 8;
-        bf16x8 val = zero8;
-        if (m0 + r < g.M) val = *reinterpret_cast<const bf16x8*>(g.A + (size_t)(m0 + r) * g.lda + k0 + kc);
-        *reinterpret_cast<bf16x8*>(&As[r * GLD + kc]) = val;
-      } else {
-        const int kr = c >> 3, mc = (c & 7) * 8;
-        bf16x8 val = zero8;
-        if (m0 + mc < g.M) val = *reinterpret_cast<const bf16x8*>(g.A + (size_t)(k0 + kr) * g.lda + m0 + mc);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) As[(mc + j) * GLD + kr] = val[j];
-      }
-    }
-    // stage B tile n0..n0+63, k0..k0+63 into Bs[n][k]
-#pragma unroll
-    for (int rep = 0; rep < 2; ++rep) {
-      const int c = t + rep * 256;
-      if (!B_NC) {
-        const int r = c >> 3, kc = (c & 7) * 8;
-        const bf16x8 val = *reinterpret_cast<const bf16x8*>(g.B + (size_t)(n0 + r) * g.ldb + k0 + kc);
-        *reinterpret_cast<bf16x8*>(&Bs[r * GLD + kc]) = val;
-      } else {
-        const int kr = c >> 3, nc = (c & 7) * 8;
-        const bf16x8 val = *reinterpret_cast<const bf16x8*>(g.B + (size_t)(k0 + kr) * g.ldb + n0 + nc);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) Bs[(nc + j) * GLD + kr] = val[j];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GT; kk += 32) {
-      bf16x8 af[2], bfr[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = wm * 32 + i * 16 + (lane & 15);
-        af[i] = *reinterpret_cast<const bf16x8*>(&As[r * GLD + kk + 8 * (lane >> 4)]);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int r = wn * 32 + j * 16 + (lane & 15);
-        bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[r * GLD + kk + 8 * (lane >> 4)]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-
-  float* outf = g.out_f32 ? g.out_f32 + (size_t)blockIdx.z * g.M * g.N : nullptr;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn * 32 + j * 16 + (lane & 15);
-      const float bias = g.bias ? g.bias[col] : 0.0f;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-        if (row >= g.M) continue;
-        float x = acc[i][j][v] + bias;
-        if (g.relu) x = fmaxf(x, 0.0f);
-        if (g.mask && !((float)g.mask[(size_t)row * g.N + col] > 0.0f)) x = 0.0f;
-        if (outf) outf[(size_t)row * g.N + col] = x;
-        if (g.out_bf16) g.out_bf16[(size_t)row * g.N + col] = (bf16)x;
-      }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Fused forward: features, the five hidden layers and the head of a tile of
-// kFusedRows rows in one workgroup.  The tile's activations stay in LDS
-// (bf16, [row][k]) from layer to layer; each layer's weights W^T [256][in]
-// stream through LDS in chunks of 32 k (double-buffered, shared by the
-// workgroup's 8 wavefronts).  Wavefront w owns rows 16 w .. 16 w + 15 of the
-// tile and all 256 output columns: 16 MFMA 16x16x32 accumulators, k in
-// increasing steps of 32 -- the accumulation order of k_gemm, so every
-// activation is bitwise the one of the layer-by-layer path.  After a layer's
-// last chunk every wavefront has finished reading the activations, and the
-// new ones (bias, ReLU, bf16) overwrite them in place; optionally they also
-// go to global memory for the backward pass.  The head is k_head's per-row
-// dot product (4 columns per lane, then the wave sum).
+// ROWS rows (128, or 64 for small batches) in one workgroup of kFusedWaves
+// wavefronts.  The tile's
+// activations stay in LDS (bf16, [row][k]) from layer to layer and are read
+// by every wavefront; wavefront w owns output columns 64 w .. 64 w + 63 of
+// every row, so its weight fragments (W^T rows of those columns) are its own
+// and come straight from global memory (L2-resident: 640 KB for all five
+// layers), one k-step ahead, with no LDS traffic or barrier inside a layer.
+// Per 32-k step a wavefront issues (ROWS / 16) x 4 MFMA 16x16x32 (row
+// tiles x 4 column tiles), k in increasing steps of 32, FP32 accumulation.
+// After a layer every wavefront has finished reading its inputs (barrier),
+// the new activations (bias, ReLU, bf16) overwrite them in place, and
+// optionally go to global memory for the backward pass.  The head is k_head's
+// per-row dot product (4 columns per lane, then the wave sum).
 // ---------------------------------------------------------------------------
-constexpr int kFusedWaves = 8;
-constexpr int kFusedRows = 16 * kFusedWaves;
+constexpr int kFusedWaves = 4;
+constexpr int kFusedRows = 128;
 constexpr int ALD = 256 + 8;    // activation row stride (bf16): 132 dwords, rows 4 banks apart
-constexpr int WKC = 32;         // k per staged weight chunk
-constexpr int WLD = WKC + 8;    // weight chunk row stride (bf16): 20 dwords
 
 // Row-major store of the tile's first `cols` activation columns, 16 bytes
 // per thread (rows past n are not stored).
+template <int ROWS = kFusedRows>
 __device__ __forceinline__ void store_tile(const bf16* act, int cols, long long tile0, long long n, bf16* out) {
   const int per_row = cols / 8;
-  for (int i = threadIdx.x; i < kFusedRows * per_row; i += kFusedWaves * 64) {
+  for (int i = threadIdx.x; i < ROWS * per_row; i += kFusedWaves * 64) {
     const int r = i / per_row, c8 = (i - r * per_row) * 8;
     if (tile0 + r < n)
       *reinterpret_cast<uint4*>(out + (tile0 + r) * cols + c8) = *reinterpret_cast<const uint4*>(&act[r * ALD + c8]);
@@ -159,9 +52,10 @@ __device__ __forceinline__ void store_tile(const bf16* act, int cols, long long 
 
 // Transposed store out[col][tile0 + r] (row stride ld): 8 rows of one column
 // per thread, 16 bytes (rows past n are zero; ld and tile0 are multiples of 8).
+template <int ROWS = kFusedRows>
 __device__ __forceinline__ void store_tile_t(const bf16* act, int cols, long long tile0, long long n, bf16* out,
                                              long long ld) {
-  constexpr int kChunks = kFusedRows / 8;
+  constexpr int kChunks = ROWS / 8;
   for (int i = threadIdx.x; i < cols * kChunks; i += kFusedWaves * 64) {
     const int col = i / kChunks, r8 = (i - col * kChunks) * 8;
     if (tile0 + r8 >= n) continue;
@@ -172,15 +66,16 @@ __device__ __forceinline__ void store_tile_t(const bf16* act, int cols, long lon
   }
 }
 
-__global__ __launch_bounds__(kFusedWaves * 64) void k_mlp_fused(FusedArgs a) {
-  __shared__ __attribute__((aligned(16))) bf16 act[kFusedRows * ALD];
-  __shared__ __attribute__((aligned(16))) bf16 wch[2][256 * WLD];
+template <int ROWS>
+__global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 act[ROWS * ALD];
+  constexpr int kRT = ROWS / 16;  // row tiles
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const long long tile0 = (long long)blockIdx.x * kFusedRows;
+  const long long tile0 = (long long)blockIdx.x * ROWS;
 
   // features of the tile's rows (rows past n get zeros and are never stored)
-  for (int i = tid; i < kFusedRows * 64; i += kFusedWaves * 64) {
+  for (int i = tid; i < ROWS * 64; i += kFusedWaves * 64) {
     const int r = i >> 6, f = i & 63;
     const long long row = tile0 + r;
     float s = 0.0f, c = 0.0f;
@@ -205,69 +100,65 @@ __global__ __launch_bounds__(kFusedWaves * 64) void k_mlp_fused(FusedArgs a) {
     act[r * ALD + f] = (bf16)s;
     act[r * ALD + 64 + f] = (bf16)c;
   }
-  if (a.X0 || a.X0T) {
-    __syncthreads();
-    if (a.X0) store_tile(act, 128, tile0, a.n, a.X0);
-    if (a.X0T) store_tile_t(act, 128, tile0, a.n, a.X0T, a.ld_t);
-  }
+  __syncthreads();
+  if (a.X0) store_tile<ROWS>(act, 128, tile0, a.n, a.X0);
+  if (a.X0T) store_tile_t<ROWS>(act, 128, tile0, a.n, a.X0T, a.ld_t);
 
-  const int ar = wave * 16 + (lane & 15);  // this lane's A row in the tile
-  const int kq = 8 * (lane >> 4);          // and its 8-wide k slot within a 32-k step
-  // staging of a weight chunk (256 columns x 32 k): thread -> (output column, 16-k half)
-  const int sc = tid >> 1, sh = (tid & 1) * 16;
+  const int kq = 8 * (lane >> 4);  // this lane's 8-wide k slot within a 32-k step
+  const int c0 = wave * 64;        // this wavefront's first output column
 #pragma unroll 1
   for (int l = 0; l < kMlpHidden; ++l) {
     const int K = a.L.fan_in[l];
     const bf16* Wt = a.wt + a.L.bf_off[l];  // [256][K]
     const float* bias = a.p + a.L.b_off[l];
-    const int nch = K / WKC;
-    {
-      const uint4* src = reinterpret_cast<const uint4*>(Wt + (size_t)sc * K + sh);
-      uint4* dst = reinterpret_cast<uint4*>(&wch[0][sc * WLD + sh]);
-      dst[0] = src[0];
-      dst[1] = src[1];
-    }
-    __syncthreads();  // features / previous layer's outputs and chunk 0 in place
-    floatx4 acc[16];
+    const int nks = K / 32;
+    floatx4 acc[kRT][4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int i = 0; i < kRT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+    // weight fragments of k-step 0; then each step loads the next one's
+    bf16x8 bw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bw[j] = *reinterpret_cast<const bf16x8*>(Wt + (size_t)(c0 + 16 * j + (lane & 15)) * K + kq);
 #pragma unroll 1
-    for (int kc = 0; kc < nch; ++kc) {
-      const int buf = kc & 1;
-      uint4 nx0, nx1;
-      const bool more = kc + 1 < nch;
-      if (more) {
-        const uint4* src = reinterpret_cast<const uint4*>(Wt + (size_t)sc * K + (kc + 1) * WKC + sh);
-        nx0 = src[0];
-        nx1 = src[1];
-      }
-      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[ar * ALD + kc * WKC + kq]);
+    for (int ks = 0; ks < nks; ++ks) {
+      bf16x8 bn[4];
+      const int kn = ks + 1 < nks ? ks + 1 : ks;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(&wch[buf][(j * 16 + (lane & 15)) * WLD + kq]);
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j)
+        bn[j] = *reinterpret_cast<const bf16x8*>(Wt + (size_t)(c0 + 16 * j + (lane & 15)) * K + kn * 32 + kq);
+#pragma unroll
+      for (int i = 0; i < kRT; ++i) {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + ks * 32 + kq]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], af, acc[i][j], 0, 0, 0);
       }
-      if (more) {
-        uint4* dst = reinterpret_cast<uint4*>(&wch[buf ^ 1][sc * WLD + sh]);
-        dst[0] = nx0;
-        dst[1] = nx1;
-      }
-      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bw[j] = bn[j];
     }
-    // every wavefront is past its last read of this layer's inputs
+    __syncthreads();  // every wavefront is past its last read of this layer's inputs
+    // (weights as the first MFMA operand: a lane holds 4 consecutive output
+    // columns of one row, written to the activations as 8 bytes)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int col = j * 16 + (lane & 15);
-      const float b = bias[col];
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + 16 * j + 4 * (lane >> 4);
+      float b[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = wave * 16 + 4 * (lane >> 4) + q;
-        act[r * ALD + col] = (bf16)fmaxf(acc[j][q] + b, 0.0f);
+      for (int q = 0; q < 4; ++q) b[q] = bias[col + q];
+#pragma unroll
+      for (int i = 0; i < kRT; ++i) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (bf16)fmaxf(acc[i][j][q] + b[q], 0.0f);
+        *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
       }
     }
     __syncthreads();
-    if (a.H) store_tile(act, 256, tile0, a.n, a.H + (size_t)l * a.h_stride);
-    if (a.HT && l + 1 < kMlpHidden) store_tile_t(act, 256, tile0, a.n, a.HT + (size_t)l * a.ht_stride, a.ld_t);
+    if (a.H) store_tile<ROWS>(act, 256, tile0, a.n, a.H + (size_t)l * a.h_stride);
+    if (a.HT && l + 1 < kMlpHidden)
+      store_tile_t<ROWS>(act, 256, tile0, a.n, a.HT + (size_t)l * a.ht_stride, a.ld_t);
   }
   // head: rows of this wavefront, k_head's order
   const float* hw = a.p + a.L.head_w;
@@ -275,14 +166,254 @@ __global__ __launch_bounds__(kFusedWaves * 64) void k_mlp_fused(FusedArgs a) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
   const float hb = a.p[a.L.head_b];
+  constexpr int kRowsPerWave = ROWS / kFusedWaves;
+  double wsum = 0.0;  // lane 0: this wavefront's rows, in order
 #pragma unroll 1
-  for (int i = 0; i < 16; ++i) {
-    const int r = wave * 16 + i;
+  for (int i = 0; i < kRowsPerWave; ++i) {
+    const int r = wave * kRowsPerWave + i;
     float part = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) part = fmaf((float)act[r * ALD + lane * 4 + q], wv[q], part);
     const float yh = wave_sum(part) + hb;
-    if (lane == 0 && tile0 + r < a.n) a.yhat[tile0 + r] = yh;
+    if (lane == 0 && tile0 + r < a.n) {
+      if (a.yhat) a.yhat[tile0 + r] = yh;
+      wsum += (double)yh;
+    }
+  }
+  if (a.tile_sum) {
+    // the tile's sum of yhat, wavefronts in order (for per-transmitter means)
+    __shared__ double ws[kFusedWaves];
+    if (lane == 0) ws[wave] = wsum;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kFusedWaves; ++w) t += ws[w];
+      a.tile_sum[blockIdx.x] = t;
+    }
+  }
+}
+
+// F[t] = (sum over the tiles of transmitter t, in order) / R: the mean of
+// yhat over its R receivers from the fused forward's tile sums.
+__global__ void k_tile_mean(const double* __restrict__ tile_sum, int n_tx, int tiles_per_tx, int R,
+                            float* __restrict__ F) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tx) return;
+  double s = 0.0;
+  for (int j = 0; j < tiles_per_tx; ++j) s += tile_sum[(size_t)t * tiles_per_tx + j];
+  F[t] = (float)(s / R);
+}
+
+// ---------------------------------------------------------------------------
+// Input gradients of the hidden layers, 4 down to 1, fused over the layers
+// like the forward: a workgroup takes kDxRows rows of dZ_4 (the head's
+// gradient, row-major bf16) into LDS and forms
+//   dZ_{l-1} = (dZ_l W_l^T) * (H_{l-1} > 0)
+// in place, wavefront w owning columns 64 w .. 64 w + 63 with the weight
+// fragments (rows of W_l [in][out]) straight from global memory, k in steps of
+// 32, FP32 accumulation.  Each dZ_l (l = 4..0) is stored transposed, dZT + l dzt_stride
+// ([256][ld]), for the weight and bias gradients.
+// ---------------------------------------------------------------------------
+constexpr int kDxRows = 64;  // rows per workgroup of k_mlp_dx: more workgroups for small batches
+
+__global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dx(DxArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 act[kDxRows * ALD];
+  constexpr int kRT = kDxRows / 16;  // row tiles
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const long long tile0 = (long long)blockIdx.x * kDxRows;
+  for (int i = tid; i < kDxRows * 32; i += kFusedWaves * 64) {
+    const int r = i >> 5, c8 = (i & 31) * 8;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (tile0 + r < a.n) v = *reinterpret_cast<const uint4*>(a.dz4 + (tile0 + r) * 256 + c8);
+    *reinterpret_cast<uint4*>(&act[r * ALD + c8]) = v;
+  }
+  __syncthreads();
+  store_tile_t<kDxRows>(act, 256, tile0, a.n, a.dZT + (size_t)(kMlpHidden - 1) * a.dzt_stride, a.ld);
+  const int kq = 8 * (lane >> 4);
+  const int c0 = wave * 64;
+#pragma unroll 1
+  for (int l = kMlpHidden - 1; l >= 1; --l) {
+    const bf16* Wl = a.w + a.L.bf_off[l];  // W_l [in = 256][out = 256]
+    const bf16* mask = a.H + (size_t)(l - 1) * a.h_stride;
+    floatx4 acc[kRT][4];
+#pragma unroll
+    for (int i = 0; i < kRT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 bw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bw[j] = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(c0 + 16 * j + (lane & 15)) * 256 + kq);
+#pragma unroll 1
+    for (int ks = 0; ks < 8; ++ks) {
+      bf16x8 bn[4];
+      const int kn = ks + 1 < 8 ? ks + 1 : ks;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bn[j] = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(c0 + 16 * j + (lane & 15)) * 256 + kn * 32 + kq);
+#pragma unroll
+      for (int i = 0; i < kRT; ++i) {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + ks * 32 + kq]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], af, acc[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bw[j] = bn[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + 16 * j + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < kRT; ++i) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = (bf16)acc[i][j][q];
+        *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
+      }
+    }
+    __syncthreads();
+    // ReLU derivative of layer l - 1, 16 bytes at a time (rows past n become 0)
+    for (int c = tid; c < kDxRows * 32; c += kFusedWaves * 64) {
+      const int r = c >> 5, c8 = (c & 31) * 8;
+      bf16x8 v = *reinterpret_cast<const bf16x8*>(&act[r * ALD + c8]);
+      bf16x8 mk = {};
+      if (tile0 + r < a.n) mk = *reinterpret_cast<const bf16x8*>(mask + (tile0 + r) * 256 + c8);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (float)mk[q] > 0.0f ? v[q] : (bf16)0.0f;
+      *reinterpret_cast<bf16x8*>(&act[r * ALD + c8]) = v;
+    }
+    __syncthreads();
+    store_tile_t<kDxRows>(act, 256, tile0, a.n, a.dZT + (size_t)(l - 1) * a.dzt_stride, a.ld);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight-gradient partials of all five hidden layers in one launch:
+//   part[l][s][i][o] = sum over the rows r of slice s of X_l^T[i][r] dZ_l^T[o][r]
+// and the bias partials part_b[l][s][o] = sum over those rows of dZ_l^T[o][r]
+// (X_0 = the features, X_l = H_{l-1}), both operands contiguous in r.  A work
+// item is (layer, block of 128 rows i, slice); the X^T tile of a 32-row step
+// is staged in LDS (double-buffered) for the workgroup's 4 wavefronts, each
+// wavefront owning 64 columns o whose dZ^T fragments come straight from
+// global memory.  k in increasing steps of 32 within a slice.
+// ---------------------------------------------------------------------------
+constexpr int XLD = 32 + 8;     // staged X^T step row stride (bf16)
+
+__global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16 xs[2][128 * XLD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  // decode the work item: layer 0 has one block of 128 rows (fan-in 128), the others two
+  int item = blockIdx.x / a.n_slices;
+  const int s = blockIdx.x - item * a.n_slices;
+  const int l = item == 0 ? 0 : 1 + (item - 1) / 2;
+  const int rb = item == 0 ? 0 : (item - 1) % 2;
+  const bf16* XT = l == 0 ? a.X0T : a.HT + (size_t)(l - 1) * a.ht_stride;
+  const bf16* DT = a.dZT + (size_t)l * a.dzt_stride;
+  const long long r0 = (long long)s * a.slice_rows;
+  const long long r1 = r0 + a.slice_rows < a.n ? r0 + a.slice_rows : a.n;
+  const int nks = (int)((r1 - r0) / 32);
+  const int kq = 8 * (lane >> 4);
+  const int c0 = wave * 64;
+  // staging: thread -> (row i of the block, 16-row half of the step)
+  const int si = tid >> 1, sh = (tid & 1) * 16;
+  const bf16* xsrc = XT + (size_t)(128 * rb + si) * a.ld + r0 + sh;
+  floatx4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+  // the first block of each layer also sums its dZ^T fragments: bias partials
+  const bool bias = rb == 0;
+  float bsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (nks > 0) {
+    const uint4* src = reinterpret_cast<const uint4*>(xsrc);
+    uint4* dst = reinterpret_cast<uint4*>(&xs[0][si * XLD + sh]);
+    dst[0] = src[0];
+    dst[1] = src[1];
+  }
+  bf16x8 bw[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    bw[j] = *reinterpret_cast<const bf16x8*>(DT + (size_t)(c0 + 16 * j + (lane & 15)) * a.ld + r0 + kq);
+  __syncthreads();
+#pragma unroll 1
+  for (int ks = 0; ks < nks; ++ks) {
+    const int buf = ks & 1;
+    const bool more = ks + 1 < nks;
+    uint4 nx0, nx1;
+    bf16x8 bn[4];
+    if (more) {
+      const uint4* src = reinterpret_cast<const uint4*>(xsrc + (ks + 1) * 32);
+      nx0 = src[0];
+      nx1 = src[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bn[j] = *reinterpret_cast<const bf16x8*>(DT + (size_t)(c0 + 16 * j + (lane & 15)) * a.ld + r0 +
+                                                 (ks + 1) * 32 + kq);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bf16x8 af = *reinterpret_cast<const bf16x8*>(&xs[buf][(16 * i + (lane & 15)) * XLD + kq]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], af, acc[i][j], 0, 0, 0);
+    }
+    if (bias) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bsum[j] += (float)bw[j][q];
+    }
+    if (more) {
+      uint4* dst = reinterpret_cast<uint4*>(&xs[buf ^ 1][si * XLD + sh]);
+      dst[0] = nx0;
+      dst[1] = nx1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bw[j] = bn[j];
+    }
+    __syncthreads();
+  }
+  if (bias) {
+    // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the four 8-row slots of column o
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float b = bsum[j];
+      b += __shfl_xor(b, 16);
+      b += __shfl_xor(b, 32);
+      if (lane < 16) a.part_b[((size_t)l * a.n_slices + s) * 256 + c0 + 16 * j + lane] = b;
+    }
+  }
+  // (dZ^T as the first MFMA operand: a lane holds 4 consecutive columns o of one row i)
+  float* out = a.part + ((size_t)l * a.n_slices + s) * 256 * 256;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int o = c0 + 16 * j + 4 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      *reinterpret_cast<floatx4*>(out + (size_t)(128 * rb + 16 * i + (lane & 15)) * 256 + o) = acc[i][j];
+  }
+}
+
+// Weight and bias gradients from the partials, slices in order:
+// g[w_off_l + i 256 + o] = sum_s part[l][s][i][o], g[b_off_l + o] = sum_s part_b[l][s][o].
+__global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __restrict__ part_b, int n_slices,
+                             MlpLayout L, float* __restrict__ g) {
+  const int l = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // i 256 + o within layer l, then the 256 biases
+  const int nw = L.fan_in[l] * 256;
+  if (e < nw) {
+    const float* p = part + (size_t)l * n_slices * 256 * 256 + e;
+    float s = 0.0f;
+    for (int z = 0; z < n_slices; ++z) s += p[(size_t)z * 256 * 256];
+    g[L.w_off[l] + e] = s;
+  } else if (e < nw + 256) {
+    const float* p = part_b + (size_t)l * n_slices * 256 + (e - nw);
+    float s = 0.0f;
+    for (int z = 0; z < n_slices; ++z) s += p[(size_t)z * 256];
+    g[L.b_off[l] + e - nw] = s;
   }
 }
 
@@ -318,32 +449,6 @@ __global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ H, int n,
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) dZ[(size_t)m * 256 + lane * 4 + q] = (bf16)(h[q] > 0.0f ? gm * wv[q] : 0.0f);
-  }
-}
-
-// out[c][r] = in[r][c] for a bf16 [n][cols] matrix (out row stride ld):
-// 64 x 64 tiles through LDS, 16-byte loads and stores.  n % 64 == 0.
-__global__ __launch_bounds__(256) void k_transpose_bf16(const bf16* __restrict__ in, int n, int cols,
-                                                        bf16* __restrict__ out, long long ld) {
-  __shared__ bf16 t[64][64 + 8];
-  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-#pragma unroll
-  for (int rep = 0; rep < 2; ++rep) {
-    const int i = threadIdx.x + rep * 256;
-    const int r = i >> 3, c8 = (i & 7) * 8;
-    const bf16x8 v = *reinterpret_cast<const bf16x8*>(in + (size_t)(r0 + r) * cols + c0 + c8);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) t[r][c8 + q] = v[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int rep = 0; rep < 2; ++rep) {
-    const int i = threadIdx.x + rep * 256;
-    const int c = i >> 3, r8 = (i & 7) * 8;
-    bf16x8 v;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = t[r8 + q][c];
-    *reinterpret_cast<bf16x8*>(out + (size_t)(c0 + c) * ld + r0 + r8) = v;
   }
 }
 
@@ -429,25 +534,6 @@ __global__ __launch_bounds__(256) void k_colsum_fold(const float* __restrict__ p
     for (int k = 0; k < 8; ++k) t += sh[k][c];
     out[col] = t;
   }
-}
-
-// out[i] = sum_z part[z * n + i] in order.
-__global__ void k_sum_slices(const float* __restrict__ part, int n_slices, int n, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.0f;
-  int z = 0;
-  // eight loads in flight, then the adds in slice order (the order of a
-  // plain loop, so the sum is the same)
-  for (; z + 8 <= n_slices; z += 8) {
-    float v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = part[(size_t)(z + q) * n + i];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) s += v[q];
-  }
-  for (; z < n_slices; ++z) s += part[(size_t)z * n + i];
-  out[i] = s;
 }
 
 // scale * sum(x[0..n)) in FP64, fixed tree order; one workgroup of 1024.
@@ -536,19 +622,43 @@ __global__ void k_log_eps(const float* __restrict__ P, long long n, float eps, f
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_gemm(const GemmArgs& g, bool a_mc, bool b_nc, int n_slices, hipStream_t st) {
-  const dim3 grid((g.M + GT - 1) / GT, g.N / GT, n_slices);
-  if (!a_mc && !b_nc) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, g);
-  else if (a_mc && b_nc) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, g);
-  else if (a_mc) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, g);
-  else hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, g);
+hipError_t launch_mlp_fused(const FusedArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  // tiles of 64 rows while there are too few of 128 to fill the chip twice
+  // (training batches); per-tile sums always use tiles of kFusedRows
+  if (!a.tile_sum && a.n < 2LL * 256 * kFusedRows) {
+    hipLaunchKernelGGL(k_mlp_fused<kFusedRows / 2>, dim3((unsigned)((a.n + kFusedRows / 2 - 1) / (kFusedRows / 2))),
+                       dim3(kFusedWaves * 64), 0, st, a);
+  } else {
+    hipLaunchKernelGGL(k_mlp_fused<kFusedRows>, dim3((unsigned)((a.n + kFusedRows - 1) / kFusedRows)),
+                       dim3(kFusedWaves * 64), 0, st, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_fused(const FusedArgs& a, hipStream_t st) {
+int mlp_fused_rows() { return kFusedRows; }
+
+hipError_t launch_tile_mean(const double* tile_sum, int n_tx, int tiles_per_tx, int R, float* F, hipStream_t st) {
+  if (n_tx <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_mean, dim3((n_tx + 255) / 256), dim3(256), 0, st, tile_sum, n_tx, tiles_per_tx, R, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_dx(const DxArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  const unsigned tiles = (unsigned)((a.n + kFusedRows - 1) / kFusedRows);
-  hipLaunchKernelGGL(k_mlp_fused, dim3(tiles), dim3(kFusedWaves * 64), 0, st, a);
+  hipLaunchKernelGGL(k_mlp_dx, dim3((unsigned)((a.n + kDxRows - 1) / kDxRows)), dim3(kFusedWaves * 64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_dw(const DwArgs& a, float* g, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  if (a.n % 32 != 0 || a.slice_rows % 32 != 0 || a.ld % 8 != 0) return hipErrorInvalidValue;
+  // items: layer 0 (one block of 128 inputs) + layers 1..4 (two blocks each)
+  const int items = 1 + 2 * (kMlpHidden - 1);
+  hipLaunchKernelGGL(k_mlp_dw, dim3(items * a.n_slices), dim3(kFusedWaves * 64), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_dw_sum, dim3(257, kMlpHidden), dim3(256), 0, st, a.part, a.part_b, a.n_slices, a.L, g);
   return hipGetLastError();
 }
 
@@ -556,13 +666,6 @@ hipError_t launch_head(const bf16* H, int n, const float* w, const float* b, con
                        float* yhat, float* loss_part, float* gout, bf16* dZ, hipStream_t st) {
   hipLaunchKernelGGL(k_head, dim3((n + 3) / 4), dim3(256), 0, st, H, n, w, b, y, inv_total, yhat, loss_part, gout,
                      dZ);
-  return hipGetLastError();
-}
-
-hipError_t launch_transpose_bf16(const bf16* in, int n, int cols, bf16* out, long long ld, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  if (n % 64 != 0 || cols % 64 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_transpose_bf16, dim3(n / 64, cols / 64), dim3(256), 0, st, in, n, cols, out, ld);
   return hipGetLastError();
 }
 
@@ -576,11 +679,6 @@ hipError_t launch_colsum(const bf16* X, int M, int N, const float* wt, float* pa
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_colsum_fold, dim3((N + 31) / 32), dim3(256), 0, st, part, chunks, N, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_sum_slices(const float* part, int n_slices, int n, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, st, part, n_slices, n, out);
   return hipGetLastError();
 }
 
