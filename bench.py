@@ -31,7 +31,7 @@ UNPACKED_FP32_TFLOPS = 78.6     # the same without packed FP32: 256 CU x 64 lane
 
 # The sources the single-scene 2D tracer kernels (k_forward, k_backward) are
 # built from: counter figures are valid only while these are unchanged.
-TRACER_SOURCES = ("dev.h", "path.h", "screen.h", "trace.h", "trace.hip")
+TRACER_SOURCES = ("dev.h", "path.h", "screen.h", "trace.h", "trace.hip", "view.h")
 TRACER3D_SOURCES = ("dev.h", "path3d.h", "screen3.h", "trace3d.h", "trace3d.hip")
 BATCHED_SOURCES = ("dev.h", "path.h", "screen.h", "batched.h", "batched.hip")
 
