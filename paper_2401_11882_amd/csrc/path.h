@@ -725,16 +725,23 @@ __device__ __forceinline__ float candidate_power(const SceneView& S, const Cand&
   }
 }
 
-template <int MODE>
+// MAXK: the highest order the caller's candidates can have (the code of
+// higher orders is left out, which keeps register pressure at that order's).
+template <int MODE, int MAXK = 3>
 __device__ __forceinline__ float candidate_power_img(const SceneView& S, const Cand& cd, const float* Ix,
                                                      const float* Iy, float txx, float txy, float rxx,
                                                      float rxy, bool live, const float* boxes, int j,
                                                      float scut) {
+  static_assert(MAXK >= 1 && MAXK <= 3, "orders 1..3");
   switch (cd.k) {
     case 0: return path_power_img<0, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
     case 1: return path_power_img<1, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
-    case 2: return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
-    default: return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
+    case 2:
+      if constexpr (MAXK >= 2) return path_power_img<2, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
+      else return 0.0f;
+    default:
+      if constexpr (MAXK >= 3) return path_power_img<3, MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j, scut);
+      else return 0.0f;
   }
 }
 

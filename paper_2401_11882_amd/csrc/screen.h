@@ -149,6 +149,7 @@ __device__ __forceinline__ void store_leg_box(float a0x, float a0y, float a1x, f
 // and X_i on the part of its wall where it can lie at a receiver of the box
 // with a nonzero factor (the whole range -L..1+L wherever the screen cannot
 // tell, or when `test` is off).
+template <int MAXK = 3>
 __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim, bool test, const Cand& cd,
                                                  float txx, float txy, const RxBox& B, float (&Ix)[3],
                                                  float (&Iy)[3], float c, float* out) {
@@ -164,7 +165,7 @@ __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim
   float cx = txx, cy = txy;
   bool ok = true;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < MAXK; ++i) {
     if (i < cd.k) {
       w[i] = load_wall_lane(walls, sv[i]);
       const float nx = -w[i].ey, ny = w[i].ex;
@@ -190,7 +191,7 @@ __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim
   }
   // interactions K..1, backwards
 #pragma unroll
-  for (int i = 3; i >= 1; --i) {
+  for (int i = MAXK; i >= 1; --i) {
     if (i > cd.k) continue;
     const WallRec& wi = w[i - 1];
     float t0 = lo, t1 = hi;
@@ -230,7 +231,7 @@ __device__ __forceinline__ bool screen_candidate(const WallRec* walls, float lim
 // candidates from c_begin on, chunk q going to wavefront q mod nw.  With
 // `boxes` (this wavefront's LDS area of 6 (K + 1) x 64 floats), every
 // candidate's leg boxes are stored there.
-template <class Fn>
+template <int MAXK = 3, class Fn>
 __device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, int c_begin, int n_cand, float lim,
                                              bool test, int wave, int nw, int cchunk, float txx, float txy,
                                              const RxBox& B, float cull_c, float* boxes, Fn&& fn) {
@@ -247,7 +248,7 @@ __device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, 
     bool keep = false;
     if (c < n_cand) {
       cd = decode_candidate(c, n_walls);
-      keep = screen_candidate(walls, lim, test, cd, txx, txy, B, Ix, Iy, cull_c, boxes ? boxes + lane : nullptr);
+      keep = screen_candidate<MAXK>(walls, lim, test, cd, txx, txy, B, Ix, Iy, cull_c, boxes ? boxes + lane : nullptr);
     }
     uint64_t m = ballot(keep);
     while (m) {
@@ -259,9 +260,9 @@ __device__ __forceinline__ void for_screened(const WallRec* walls, int n_walls, 
       u.s1 = __builtin_amdgcn_readlane(cd.s1, j);
       u.s2 = __builtin_amdgcn_readlane(cd.s2, j);
       const int cu = __builtin_amdgcn_readlane(c, j);
-      float jx[3], jy[3];
+      float jx[3] = {0.0f, 0.0f, 0.0f}, jy[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < MAXK; ++i) {
         jx[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Ix[i]), j));
         jy[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Iy[i]), j));
       }

@@ -47,7 +47,7 @@ namespace drt {
 // Forward kernel
 // ---------------------------------------------------------------------------
 
-template <int NW, int MODE>
+template <int NW, int MODE, int MAXK>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_forward(TraceArgs A, float* __restrict__ power,
                                                         float* __restrict__ seed,
                                                         float* __restrict__ loss_part, int loss_kind,
@@ -79,8 +79,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   // this wavefront's own running sum since then.
   float cut_base = 0.0f, own_sync = 0.0f;
   auto visit = [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
-    const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
-                                              A.cut * (cut_base + (sum - comp) - own_sync));
+    const float v = candidate_power_img<MODE, MAXK>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
+                                                    A.cut * (cut_base + (sum - comp) - own_sync));
     kahan_add(sum, comp, v);
     if (cache_c && ballot(v != 0.0f) != 0) {
       if (nst < A.cache_cap) {
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
     }
   };
   if constexpr (!uses_cut<MODE>()) {
-    for_screened(S.walls, A.n_walls, 0, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
-                 S.cull_c, boxes, visit);
+    for_screened<MAXK>(S.walls, A.n_walls, 0, A.n_cand, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy,
+                       box, S.cull_c, boxes, visit);
   } else {
     // one copy of the candidate code serves every phase (the loop is not
     // unrolled); base is double-buffered, so one barrier per phase suffices
@@ -103,8 +103,8 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
     for (int ph = 0; ph < cp.n; ++ph) {
       const int b0 = ph == 0 ? 0 : (ph == 1 ? cp.end0 : cp.end1);
       const int b1 = ph == 0 ? cp.end0 : (ph == 1 ? cp.end1 : A.n_cand);
-      for_screened(S.walls, A.n_walls, b0, b1, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy, box,
-                   S.cull_c, boxes, visit);
+      for_screened<MAXK>(S.walls, A.n_walls, b0, b1, S.dead_lim, A.screen != 0, wave, NW, A.cchunk, txx, txy,
+                         box, S.cull_c, boxes, visit);
       if (ph + 1 < cp.n) {
         own_sync = sum - comp;
         base[ph & 1][wave][lane] = own_sync;
@@ -302,16 +302,24 @@ hipError_t launch_prep_walls(const float* walls, int n, float cull_c, WallRec* o
   return hipGetLastError();
 }
 
+template <int NW, int MAXK>
+static void fwd_launch(const TraceArgs& A, int n_tiles, size_t lds, float* power, float* seed, float* loss_part,
+                       int loss_kind, float log_eps, hipStream_t st) {
+  if (A.mode)
+    hipLaunchKernelGGL((k_forward<NW, 1, MAXK>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, power, seed,
+                       loss_part, loss_kind, log_eps);
+  else
+    hipLaunchKernelGGL((k_forward<NW, 0, MAXK>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, power, seed,
+                       loss_part, loss_kind, log_eps);
+}
+
 template <int NW>
 static hipError_t fwd_nw(const TraceArgs& A, int n_tiles, float* power, float* seed, float* loss_part,
                          int loss_kind, float log_eps, hipStream_t st) {
   const size_t lds = forward_lds_bytes(NW, A.max_order) - sizeof(float) * NW * 2 * kWave;  // minus static
-  if (A.mode)
-    hipLaunchKernelGGL((k_forward<NW, 1>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, power, seed, loss_part,
-                       loss_kind, log_eps);
-  else
-    hipLaunchKernelGGL((k_forward<NW, 0>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, power, seed, loss_part,
-                       loss_kind, log_eps);
+  // scenes up to order 2 run a kernel without the order-3 path code
+  if (A.max_order <= 2) fwd_launch<NW, 2>(A, n_tiles, lds, power, seed, loss_part, loss_kind, log_eps, st);
+  else fwd_launch<NW, 3>(A, n_tiles, lds, power, seed, loss_part, loss_kind, log_eps, st);
   return hipGetLastError();
 }
 
