@@ -57,11 +57,12 @@ struct drt_mlp {
   drt::MlpLayout L{};
   float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *Bf = nullptr;
   int* step = nullptr;
-  __bf16 *wbf = nullptr, *wtbf = nullptr, *H = nullptr, *dZ0 = nullptr;
+  __bf16 *wbf = nullptr, *wtbf = nullptr;
   // transposed copies for the weight gradients: X0^T [128][max_batch],
   // H_l^T [256][max_batch] (l = 0..3), dZ_l^T [256][max_batch] (l = 0..4)
   __bf16 *X0T = nullptr, *HT = nullptr, *dZT = nullptr;
-  float *yhat = nullptr, *gvec = nullptr, *loss_part = nullptr, *dw_part = nullptr, *col_part = nullptr;
+  float *yhat = nullptr, *dw_part = nullptr;
+  float *hw_part = nullptr, *hs_part = nullptr;  // per 64-row tile: head-weight gradient [256], (sum g, sum d^2)
   double* tile_sum = nullptr;  // [kMaxTiles] per-tile yhat sums of the scan
   float* db_part = nullptr;    // [5][max_slices][256] bias-gradient partials
 };
@@ -69,13 +70,11 @@ struct drt_mlp {
 namespace {
 
 void free_mlp(drt_mlp* h) {
-  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->H, h->dZ0,
-                  h->X0T, h->HT, h->dZT, h->yhat, h->gvec, h->loss_part, h->dw_part, h->col_part, h->tile_sum, h->db_part};
+  void* bufs[] = {h->p, h->g, h->m, h->v, h->Bf, h->step, h->wbf, h->wtbf, h->X0T, h->HT,
+                  h->dZT, h->yhat, h->dw_part, h->hw_part, h->hs_part, h->tile_sum, h->db_part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
-
-__bf16* Hl(drt_mlp* h, int l) { return h->H + (size_t)l * h->max_batch * drt::kMlpWidth; }
 
 #define HIPCHK(expr, what)                                                            \
   do {                                                                                \
@@ -92,45 +91,40 @@ drt::FusedArgs fused_args(drt_mlp* h, long long n) {
   a.p = h->p;
   a.L = h->L;
   a.yhat = h->yhat;
-  a.h_stride = (long long)h->max_batch * drt::kMlpWidth;
   return a;
 }
 
 // Forward + MSE + backward on rows [0, n) of v/y; gradients into h->g, loss
-// (mean squared error over n) into loss_dev.
-int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss_dev, hipStream_t st) {
-  // features and hidden layers in one kernel, keeping X0 and every H_l for the backward pass
-  drt::FusedArgs fa = fused_args(h, n);
-  fa.v = v;
-  fa.H = h->H;
-  fa.X0T = h->X0T;
-  fa.HT = h->HT;
-  fa.ht_stride = (long long)h->max_batch * drt::kMlpWidth;
-  fa.ld_t = h->max_batch;
-  HIPCHK(drt::launch_mlp_fused(fa, st), "fused forward");
+// (mean squared error over n) into loss_dev; with `count_step`, the Adam step
+// count is advanced for the update that follows.
+int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss_dev, bool count_step,
+                  hipStream_t st) {
   const drt::MlpLayout& L = h->L;
   const int W = drt::kMlpWidth;
-  HIPCHK(drt::launch_head(Hl(h, 4), n, h->p + L.head_w, h->p + L.head_b, y, 1.0f / (float)n, h->yhat, h->loss_part,
-                          h->gvec, h->dZ0, st),
-         "head");
-  HIPCHK(drt::launch_colsum(Hl(h, 4), n, W, h->gvec, h->col_part, h->g + L.head_w, st), "head weight grad");
-  HIPCHK(drt::launch_sum_scalar(h->gvec, n, 1.0, h->g + L.head_b, st), "head bias grad");
-  if (loss_dev) HIPCHK(drt::launch_sum_scalar(h->loss_part, n, 1.0 / (double)n, loss_dev, st), "loss");
-  // input gradients of hidden layers 4..1, every dZ_l stored transposed
   const long long ldt = h->max_batch;
-  drt::DxArgs dx{};
-  dx.dz4 = h->dZ0;
-  dx.H = h->H;
-  dx.h_stride = (long long)h->max_batch * W;
-  dx.w = h->wbf;
-  dx.L = L;
-  dx.dZT = h->dZT;
-  dx.dzt_stride = ldt * W;
-  dx.ld = ldt;
-  dx.n = n;
-  HIPCHK(drt::launch_mlp_dx(dx, st), "input gradients");
+  // forward, head and input gradients per 64-row tile in one kernel: the
+  // transposed operands of the weight gradients and the head's partial sums
+  drt::TrainArgs ta{};
+  ta.v = v;
+  ta.y = y;
+  ta.Bf = h->Bf;
+  ta.wt = h->wtbf;
+  ta.w = h->wbf;
+  ta.p = h->p;
+  ta.L = L;
+  ta.inv_total = 1.0f / (float)n;
+  ta.n = n;
+  ta.X0T = h->X0T;
+  ta.HT = h->HT;
+  ta.ht_stride = ldt * W;
+  ta.dZT = h->dZT;
+  ta.dzt_stride = ldt * W;
+  ta.hw_part = h->hw_part;
+  ta.hs_part = h->hs_part;
+  HIPCHK(drt::launch_mlp_train(ta, st), "training pass");
   // weight and bias gradients of every hidden layer: slices of at least
-  // kSliceRows rows, at most max_slices of them
+  // kSliceRows rows, at most max_slices of them; then every sum, the head's
+  // and the loss included
   constexpr int kSliceRows = 512;
   drt::DwArgs dw{};
   dw.X0T = h->X0T;
@@ -138,14 +132,15 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss
   dw.ht_stride = ldt * W;
   dw.dZT = h->dZT;
   dw.dzt_stride = ldt * W;
-  dw.ld = ldt;
   dw.n = n;
   dw.slice_rows = std::max(kSliceRows, ((n + h->max_slices - 1) / h->max_slices + 31) / 32 * 32);
   dw.n_slices = (n + dw.slice_rows - 1) / dw.slice_rows;
   dw.L = L;
   dw.part = h->dw_part;
   dw.part_b = h->db_part;
-  HIPCHK(drt::launch_mlp_dw(dw, h->g, st), "weight gradients");
+  drt::HeadFold hf{h->hw_part, h->hs_part, n / drt::mlp_train_rows(), 1.0 / (double)n, loss_dev,
+                  count_step ? h->step : nullptr};
+  HIPCHK(drt::launch_mlp_dw(dw, h->g, hf, st), "weight gradients");
   return DRT_OK;
 }
 
@@ -191,16 +186,13 @@ int drt_mlp_create(const float* fourier_B_host, const float* params_host, int32_
   alloc((void**)&h->step, 16);
   alloc((void**)&h->wbf, (size_t)h->L.n_bf * 2);
   alloc((void**)&h->wtbf, (size_t)h->L.n_bf * 2);
-  alloc((void**)&h->H, nb * W * 2 * drt::kMlpHidden);
-  alloc((void**)&h->dZ0, nb * W * 2);
   alloc((void**)&h->X0T, nb * drt::kMlpIn * 2);
   alloc((void**)&h->HT, nb * W * 2 * (drt::kMlpHidden - 1));
   alloc((void**)&h->dZT, nb * W * 2 * drt::kMlpHidden);
   alloc((void**)&h->yhat, nb * 4);
-  alloc((void**)&h->gvec, nb * 4);
-  alloc((void**)&h->loss_part, nb * 4);
   alloc((void**)&h->dw_part, (size_t)drt::kMlpHidden * h->max_slices * W * W * 4);
-  alloc((void**)&h->col_part, (size_t)drt::colsum_chunks(max_batch) * W * 4);
+  alloc((void**)&h->hw_part, nb / drt::mlp_train_rows() * W * 4);
+  alloc((void**)&h->hs_part, nb / drt::mlp_train_rows() * 2 * 4);
   alloc((void**)&h->tile_sum, (size_t)kMaxTiles * sizeof(double));
   alloc((void**)&h->db_part, (size_t)drt::kMlpHidden * h->max_slices * W * 4);
   if (e == hipSuccess) e = hipMemcpy(h->p, params_host, P * 4, hipMemcpyHostToDevice);
@@ -251,7 +243,7 @@ int drt_mlp_grads(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t 
   if (rc) return rc;
   if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, st))) return rc;
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, false, st))) return rc;
   if (grads_dev) HIPCHK(hipMemcpyAsync(grads_dev, mlp->g, (size_t)mlp->L.n_params * 4, hipMemcpyDeviceToDevice, st),
                         "grad copy");
   return DRT_OK;
@@ -264,7 +256,7 @@ int drt_mlp_train_step(drt_mlp* mlp, const float* v_dev, const float* y_dev, int
   if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
   if (!(lr > 0.0f) || !std::isfinite(lr)) return failf(DRT_EINVAL, "lr must be finite and > 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, st))) return rc;
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, true, st))) return rc;
   HIPCHK(drt::launch_adam_mlp(mlp->p, mlp->g, mlp->m, mlp->v, mlp->step, mlp->L.n_params, lr, 0.9f, 0.999f, 1e-8f,
                               mlp->L, mlp->wbf, mlp->wtbf, st),
          "adam");

@@ -22,10 +22,7 @@ struct MlpLayout {
 
 // Fused forward of rows [0, n): features from v [n][4] (v != NULL) or from
 // the pairs (tx[(row0 + row) / R], rx[(row0 + row) % R]); hidden layers from
-// the bf16 W^T copies wt and the FP32 biases in p; yhat [n] out; optional
-// X0 [n][128] and H [5][h_stride] (layer l at H + l h_stride, [n][256]) out,
-// and the transposed inputs of the weight gradients, X0T [128][ld_t] and
-// HT [4][ht_stride] (H_l^T [256][ld_t] for l = 0..3; ld_t % 8 == 0).
+// the bf16 W^T copies wt and the FP32 biases in p; yhat [n] out.
 struct FusedArgs {
   const float* v;
   const float* tx;
@@ -38,13 +35,6 @@ struct FusedArgs {
   const float* p;
   MlpLayout L;
   float* yhat;
-  __bf16* X0;
-  __bf16* H;
-  long long h_stride;
-  __bf16* X0T;
-  __bf16* HT;
-  long long ht_stride;
-  long long ld_t;
   double* tile_sum;  // [n / fused rows] or NULL: per-tile sums of yhat (yhat may then be NULL)
 };
 
@@ -54,37 +44,65 @@ int mlp_fused_rows();
 // F[t] = sum of tile_sum[t tiles_per_tx .. + tiles_per_tx) / R.
 hipError_t launch_tile_mean(const double* tile_sum, int n_tx, int tiles_per_tx, int R, float* F, hipStream_t st);
 
-// Input gradients of hidden layers 4..1 from dz4 [n][256] (the head's
-// gradient), masks H [5][h_stride] ([n][256] per layer), weights w (bf16
-// W [in][out] copies); every dZ_l stored transposed at dZT + l dzt_stride
-// ([256][ld]).  n % 8 == 0.
-struct DxArgs {
-  const __bf16* dz4;
-  const __bf16* H;
-  long long h_stride;
+// Training pass of rows [0, n) (n % 64 == 0): features of v [n][4], the
+// forward through the bf16 W^T copies wt, the head with targets y (squared
+// error, output gradient g = 2 (yhat - y) inv_total), and the input
+// gradients through the bf16 W copies w.  Out, transposed in blocks of 32
+// rows (element (col, row) of an operand with C columns at
+// (row / 32) 32 C + 32 col + row % 32): X0T (C = 128), HT [4][ht_stride]
+// (H_l, l = 0..3, C = 256), dZT [5][dzt_stride] (dZ_l, C = 256); per tile t
+// of mlp_train_rows() rows: hw_part[t][i] = sum_m g_m H_4[m][i]
+// and hs_part[t] = (sum_m g_m, sum_m (yhat_m - y_m)^2); yhat [n] if not NULL.
+struct TrainArgs {
+  const float* v;
+  const float* y;
+  const float* Bf;
+  const __bf16* wt;
   const __bf16* w;
+  const float* p;
   MlpLayout L;
+  float inv_total;
+  long long n;
+  __bf16* X0T;
+  __bf16* HT;
+  long long ht_stride;
   __bf16* dZT;
   long long dzt_stride;
-  long long ld;
-  long long n;
+  float* hw_part;
+  float* hs_part;
+  float* yhat;
 };
 
-hipError_t launch_mlp_dx(const DxArgs& a, hipStream_t st);
+hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st);
+// Rows per tile of the training pass.
+int mlp_train_rows();
+
+// The head's part of the gradient sums: g[head_w + i] = sum_t hw_part[t][i],
+// g[head_b] = sum_t hs_part[t][0], loss[0] = inv_n sum_t hs_part[t][1]
+// (fixed order; hw_part NULL: nothing; loss NULL: no loss); step[0] += 1
+// if step is not NULL (the Adam step count of a training step).
+struct HeadFold {
+  const float* hw_part;
+  const float* hs_part;
+  int tiles;
+  double inv_n;
+  float* loss;
+  int* step;
+};
 
 // Weight and bias gradients of the hidden layers from the transposed
-// operands X0T [128][ld], HT [4][ht_stride] and dZT [5][dzt_stride]:
+// operands X0T, HT [4][ht_stride] and dZT [5][dzt_stride] (blocks of 32 rows
+// as written by the training pass):
 // partials over slices of slice_rows rows (weights into part, biases -- the
 // row sums of dZ_l^T -- into part_b), then the in-order slice sums into g
-// (W_l at w_off_l, b_l at b_off_l).  n and slice_rows are
-// multiples of 32, n_slices = ceil(n / slice_rows).
+// (W_l at w_off_l, b_l at b_off_l), and the head's sums (HeadFold).  n and
+// slice_rows are multiples of 32, n_slices = ceil(n / slice_rows).
 struct DwArgs {
   const __bf16* X0T;
   const __bf16* HT;
   long long ht_stride;
   const __bf16* dZT;
   long long dzt_stride;
-  long long ld;
   long long n;
   int slice_rows;
   int n_slices;
@@ -93,16 +111,10 @@ struct DwArgs {
   float* part_b;  // [5][n_slices][256]
 };
 
-hipError_t launch_mlp_dw(const DwArgs& a, float* g, hipStream_t st);
-hipError_t launch_head(const __bf16* H, int n, const float* w, const float* b, const float* y, float inv_total,
-                       float* yhat, float* loss_part, float* gout, __bf16* dZ, hipStream_t st);
-// out[col] = sum_m X[m][col] * (wt ? wt[m] : 1) through per-chunk partials
-// (part: colsum_chunks(M) x N floats), fixed order.
-int colsum_chunks(int M);
-hipError_t launch_colsum(const __bf16* X, int M, int N, const float* wt, float* part, float* out, hipStream_t st);
-hipError_t launch_sum_scalar(const float* x, int n, double scale, float* out, hipStream_t st);
+hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, hipStream_t st);
 hipError_t launch_segment_mean(const float* yhat, int T, int R, float* F, hipStream_t st);
-hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, int* step, int n, float lr, float b1,
+// Adam at step t = step[0] (already counted up for this step).
+hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, const int* step, int n, float lr, float b1,
                            float b2, float eps, const MlpLayout& L, __bf16* wbf, __bf16* wtbf, hipStream_t st);
 hipError_t launch_mlp_copies(const float* p, int n, const MlpLayout& L, __bf16* wbf, __bf16* wtbf,
                              hipStream_t st);

@@ -3,11 +3,12 @@
 // MLP (128 -> 256 x 5 -> 1), trained and evaluated with BF16 MFMA
 // (v_mfma_f32_16x16x32_bf16) and FP32 accumulation.
 //
-// Layouts (row-major): features X0 [n][128] bf16; hidden activations
-// H_l [n][256] bf16; weights of hidden layer l as bf16 in two copies,
-// W [in][out] and W^T [out][in]; master weights, biases, Adam moments FP32 in
-// one flat vector: per hidden layer W_l [in][out] then b_l [out], then the
-// head w5 [256], b5 [1].
+// Layouts: activations of a row tile in LDS, row-major bf16; the inputs of
+// the weight gradients (features, hidden activations, their gradients)
+// transposed in blocks of 32 rows; weights of hidden layer l as bf16 in two
+// copies, W and W^T, in MFMA fragment order (frag_off); master weights,
+// biases, Adam moments FP32 in one flat vector: per hidden layer
+// W_l [in][out] then b_l [out], then the head w5 [256], b5 [1].
 #include "dev.h"
 #include "mlp.h"
 
@@ -30,39 +31,104 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 // Per 32-k step a wavefront issues (ROWS / 16) x 4 MFMA 16x16x32 (row
 // tiles x 4 column tiles), k in increasing steps of 32, FP32 accumulation.
 // After a layer every wavefront has finished reading its inputs (barrier),
-// the new activations (bias, ReLU, bf16) overwrite them in place, and
-// optionally go to global memory for the backward pass.  The head is k_head's
-// per-row dot product (4 columns per lane, then the wave sum).
+// and the new activations (bias, ReLU, bf16) overwrite them in place.  The
+// head is a per-row dot product in FP32 (4 columns per lane, then the wave
+// sum), the same as in the training pass.
 // ---------------------------------------------------------------------------
 constexpr int kFusedWaves = 4;
 constexpr int kFusedRows = 128;
 constexpr int ALD = 256 + 8;    // activation row stride (bf16): 132 dwords, rows 4 banks apart
+constexpr int kTrainRows = 32;  // rows per workgroup of the training pass (tile of the head's partial sums)
 
-// Row-major store of the tile's first `cols` activation columns, 16 bytes
-// per thread (rows past n are not stored).
-template <int ROWS = kFusedRows>
-__device__ __forceinline__ void store_tile(const bf16* act, int cols, long long tile0, long long n, bf16* out) {
-  const int per_row = cols / 8;
-  for (int i = threadIdx.x; i < ROWS * per_row; i += kFusedWaves * 64) {
-    const int r = i / per_row, c8 = (i - r * per_row) * 8;
-    if (tile0 + r < n)
-      *reinterpret_cast<uint4*>(out + (tile0 + r) * cols + c8) = *reinterpret_cast<const uint4*>(&act[r * ALD + c8]);
+// The bf16 weight copies are stored in MFMA fragment order.  A copy is read
+// as a matrix M [256][K] whose rows are the product's output columns c
+// (W^T for the forward, W for the backward).  The operand of k-step ks,
+// column tile j of the wavefront that owns columns 64 s .. 64 s + 63 is 64
+// lanes x 8 consecutive k (lane = 16 (k / 8 % 4) + c % 16); those 1024
+// bytes are contiguous, so one load instruction reads whole cache lines.
+__device__ __forceinline__ size_t frag_off(int c, int k, int K) {
+  return ((((size_t)(c >> 6) * (K >> 5) + (k >> 5)) * 4 + ((c >> 4) & 3)) * 64 + ((((k >> 3) & 3) << 4) | (c & 15))) * 8 +
+         (k & 7);
+}
+
+// This lane's operand of (wavefront s, k-step ks, column tile j).
+__device__ __forceinline__ const bf16* frag_ptr(const bf16* M, int K, int s, int ks, int j, int lane) {
+  return M + ((((size_t)s * (K >> 5) + ks) * 4 + j) * 64 + lane) * 8;
+}
+
+// The transposed operands of the weight gradients are stored in blocks of
+// kTB rows: element (col, row) of an operand with `cols` columns is at
+// (row / kTB) cols kTB + col kTB + row % kTB, so a block is one contiguous
+// piece (every 32-row k-step of the weight-gradient product reads one block).
+constexpr int kTB = 32;
+
+// Transposed store of the tile's first `cols` columns (cols % 4 == 0; ROWS
+// and tile0 multiples of kTB; every row of the tile is below n).  A work item
+// is 4 columns x 8 rows: eight 8-byte LDS reads (one row's 4 columns each)
+// are transposed in registers into four 16-byte stores (one column's 8 rows
+// each); adjacent lanes write adjacent 16-byte pieces.
+template <int ROWS>
+__device__ __forceinline__ void store_tile_t(const bf16* act, int cols, long long tile0, bf16* out) {
+  static_assert(ROWS % kTB == 0, "whole blocks");
+  constexpr int kChunks = ROWS / 8;
+  for (int it = threadIdx.x; it < (cols / 4) * kChunks; it += kFusedWaves * 64) {
+    const int g = it / kChunks, r8 = (it - g * kChunks) * 8;
+    uint32_t d[8][2];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) {
+      const uint2 x = *reinterpret_cast<const uint2*>(&act[(r8 + rr) * ALD + 4 * g]);
+      d[rr][0] = x.x;  // columns 4g, 4g + 1
+      d[rr][1] = x.y;  // columns 4g + 2, 4g + 3
+    }
+    const long long row = tile0 + r8;
+    bf16* blk = out + (size_t)(row / kTB) * cols * kTB + row % kTB;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      uint4 o;
+      uint32_t* ow = reinterpret_cast<uint32_t*>(&o);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t a0 = d[2 * k][c >> 1], a1 = d[2 * k + 1][c >> 1];
+        ow[k] = (c & 1) ? ((a0 >> 16) | (a1 & 0xffff0000u)) : ((a0 & 0xffffu) | (a1 << 16));
+      }
+      *reinterpret_cast<uint4*>(blk + (size_t)(4 * g + c) * kTB) = o;
+    }
   }
 }
 
-// Transposed store out[col][tile0 + r] (row stride ld): 8 rows of one column
-// per thread, 16 bytes (rows past n are zero; ld and tile0 are multiples of 8).
-template <int ROWS = kFusedRows>
-__device__ __forceinline__ void store_tile_t(const bf16* act, int cols, long long tile0, long long n, bf16* out,
-                                             long long ld) {
-  constexpr int kChunks = ROWS / 8;
-  for (int i = threadIdx.x; i < cols * kChunks; i += kFusedWaves * 64) {
-    const int col = i / kChunks, r8 = (i - col * kChunks) * 8;
-    if (tile0 + r8 >= n) continue;
-    bf16x8 v;
+// Fourier features of rows tile0 .. tile0 + ROWS - 1 into act[r][0..127]
+// (sin, then cos; rows past n get zeros).  The rows' inputs and B are first
+// staged in LDS with one coalesced load per element, so the feature loop
+// itself waits on no global load.  x(r, e): input e (0..3) of row r.
+template <int ROWS, class X>
+__device__ __forceinline__ void tile_features(bf16* act, float (*xin)[4], float (*bfs)[4], const float* Bf,
+                                              long long tile0, long long n, X&& x) {
+  const int tid = threadIdx.x;
+  constexpr int kPer = (ROWS * 4 + kFusedWaves * 64 - 1) / (kFusedWaves * 64);
+  float xv[kPer];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = tile0 + r8 + q < n ? act[(r8 + q) * ALD + col] : (bf16)0.0f;
-    *reinterpret_cast<bf16x8*>(out + (size_t)col * ld + tile0 + r8) = v;
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + u * kFusedWaves * 64;
+    const long long row = tile0 + (e >> 2);
+    xv[u] = (e < ROWS * 4 && row < n) ? x(row, e & 3) : 0.0f;
+  }
+  const float bv = Bf[tid];  // kMlpFreq x 4 = 256 values, one per thread
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + u * kFusedWaves * 64;
+    if (e < ROWS * 4) xin[e >> 2][e & 3] = xv[u];
+  }
+  bfs[tid >> 2][tid & 3] = bv;
+  __syncthreads();
+  for (int i = tid; i < ROWS * 64; i += kFusedWaves * 64) {
+    const int r = i >> 6, f = i & 63;
+    float sn = 0.0f, cs = 0.0f;
+    if (tile0 + r < n) {
+      const float tt = bfs[f][0] * xin[r][0] + bfs[f][1] * xin[r][1] + bfs[f][2] * xin[r][2] + bfs[f][3] * xin[r][3];
+      sincospif(2.0f * tt, &sn, &cs);
+    }
+    act[r * ALD + f] = (bf16)sn;
+    act[r * ALD + 64 + f] = (bf16)cs;
   }
 }
 
@@ -74,35 +140,22 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
   const int lane = tid & 63, wave = tid >> 6;
   const long long tile0 = (long long)blockIdx.x * ROWS;
 
-  // features of the tile's rows (rows past n get zeros and are never stored)
-  for (int i = tid; i < ROWS * 64; i += kFusedWaves * 64) {
-    const int r = i >> 6, f = i & 63;
-    const long long row = tile0 + r;
-    float s = 0.0f, c = 0.0f;
-    if (row < a.n) {
-      float x0, x1, x2, x3;
-      if (a.v) {
-        x0 = a.v[4 * row];
-        x1 = a.v[4 * row + 1];
-        x2 = a.v[4 * row + 2];
-        x3 = a.v[4 * row + 3];
-      } else {
-        const long long g = a.row0 + row;
-        const int t = (int)(g / a.R), q = (int)(g % a.R);
-        x0 = a.tx[2 * t];
-        x1 = a.tx[2 * t + 1];
-        x2 = a.rx[2 * q];
-        x3 = a.rx[2 * q + 1];
-      }
-      const float tt = a.Bf[4 * f] * x0 + a.Bf[4 * f + 1] * x1 + a.Bf[4 * f + 2] * x2 + a.Bf[4 * f + 3] * x3;
-      sincospif(2.0f * tt, &s, &c);
-    }
-    act[r * ALD + f] = (bf16)s;
-    act[r * ALD + 64 + f] = (bf16)c;
+  // head parameters now, so their loads are long done when the head runs
+  const float* hw = a.p + a.L.head_w;
+  float wv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
+  const float hb = a.p[a.L.head_b];
+  __shared__ float xin[ROWS][4], bfs[kMlpFreq][4];
+  if (a.v) {
+    tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) { return a.v[4 * row + e]; });
+  } else {
+    tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) {
+      const long long g = a.row0 + row;
+      return e < 2 ? a.tx[2 * (g / a.R) + e] : a.rx[2 * (g % a.R) + e - 2];
+    });
   }
   __syncthreads();
-  if (a.X0) store_tile<ROWS>(act, 128, tile0, a.n, a.X0);
-  if (a.X0T) store_tile_t<ROWS>(act, 128, tile0, a.n, a.X0T, a.ld_t);
 
   const int kq = 8 * (lane >> 4);  // this lane's 8-wide k slot within a 32-k step
   const int c0 = wave * 64;        // this wavefront's first output column
@@ -121,14 +174,14 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
     bf16x8 bw[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      bw[j] = *reinterpret_cast<const bf16x8*>(Wt + (size_t)(c0 + 16 * j + (lane & 15)) * K + kq);
+      bw[j] = *reinterpret_cast<const bf16x8*>(frag_ptr(Wt, K, wave, 0, j, lane));
 #pragma unroll 1
     for (int ks = 0; ks < nks; ++ks) {
       bf16x8 bn[4];
       const int kn = ks + 1 < nks ? ks + 1 : ks;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bn[j] = *reinterpret_cast<const bf16x8*>(Wt + (size_t)(c0 + 16 * j + (lane & 15)) * K + kn * 32 + kq);
+        bn[j] = *reinterpret_cast<const bf16x8*>(frag_ptr(Wt, K, wave, kn, j, lane));
 #pragma unroll
       for (int i = 0; i < kRT; ++i) {
         const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + ks * 32 + kq]);
@@ -156,16 +209,8 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
       }
     }
     __syncthreads();
-    if (a.H) store_tile<ROWS>(act, 256, tile0, a.n, a.H + (size_t)l * a.h_stride);
-    if (a.HT && l + 1 < kMlpHidden)
-      store_tile_t<ROWS>(act, 256, tile0, a.n, a.HT + (size_t)l * a.ht_stride, a.ld_t);
   }
-  // head: rows of this wavefront, k_head's order
-  const float* hw = a.p + a.L.head_w;
-  float wv[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
-  const float hb = a.p[a.L.head_b];
+  // head: rows of this wavefront, one wave sum per row
   constexpr int kRowsPerWave = ROWS / kFusedWaves;
   double wsum = 0.0;  // lane 0: this wavefront's rows, in order
 #pragma unroll 1
@@ -194,6 +239,214 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Training pass of one tile of ROWS rows in one workgroup: the fused
+// forward (features, five hidden layers), the head with the squared error
+// and its output gradient, and the input-gradient chain
+//   dZ_{l-1} = (dZ_l W_l^T) * (H_{l-1} > 0),  l = 4 .. 1,
+// all on the tile's activations in LDS.  The ReLU masks of layers 0..3 stay
+// in LDS (4 bits per byte); no row-major activation leaves the workgroup.  Out: the
+// transposed operands of the weight gradients (X0T, HT_0..3, dZT_0..4), and
+// per tile the partial sums of the head's gradients (sum_m g_m H_4[m][i] and
+// sum_m g_m) and of the squared errors.
+//
+// Nine products of the tile (5 forward with W_l^T, 4 backward with W_l) run
+// through one loop.  Wavefront w owns output columns 64 w .. 64 w + 63; its
+// operand of a whole product (8 k-steps x 4 column tiles of bf16x8, 128
+// VGPRs) sits in registers and is reloaded for the next product as soon as
+// the multiplications are issued, so the loads are in flight during the
+// epilogue and the stores.  Tiles are small (32 rows) so that two
+// workgroups share a CU and one's products overlap the other's epilogue.
+// ---------------------------------------------------------------------------
+struct WSlice {
+  bf16x8 f[8][4];  // [k-step][column tile]
+};
+
+// Rows c0 .. c0 + 63 of M [256][K] (K = 128 or 256, fragment order), this
+// lane's operands of every k-step.
+__device__ __forceinline__ void load_wslice(WSlice& s, const bf16* M, int K, int c0, int lane) {
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (ks * 32 < K) s.f[ks][j] = *reinterpret_cast<const bf16x8*>(frag_ptr(M, K, c0 >> 6, ks, j, lane));
+}
+
+// Product p of the training pass: the matrix ([256][K], rows = output
+// columns) and K.  p = 0..4: W_p^T; p = 5..8: W_{9-p} (backward).
+__device__ __forceinline__ const bf16* train_matrix(const TrainArgs& a, int p, int& K) {
+  if (p < kMlpHidden) {
+    K = a.L.fan_in[p];
+    return a.wt + a.L.bf_off[p];
+  }
+  K = kMlpWidth;
+  return a.w + a.L.bf_off[2 * kMlpHidden - 1 - p];
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_train(TrainArgs a) {
+  constexpr int kRT = ROWS / 16;  // row tiles
+  __shared__ __attribute__((aligned(16))) bf16 act[ROWS * ALD];
+  __shared__ uint8_t mnib[kMlpHidden - 1][ROWS][kMlpWidth / 4];  // H_l > 0, l = 0..3: bit c % 4 of byte c / 4
+  __shared__ float hwp[kFusedWaves][kMlpWidth];              // per-wavefront head-weight gradient partials
+  __shared__ float hsp[kFusedWaves][2];                      // per-wavefront sums of g and of d^2
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const long long tile0 = (long long)blockIdx.x * ROWS;
+
+  // head parameters and this wavefront's targets now, so their loads are
+  // long done when the head runs (lane i < 16: row 16 wave + i)
+  constexpr int kRowsPerWave = ROWS / kFusedWaves;
+  const float* hw = a.p + a.L.head_w;
+  float wv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
+  const float hb = a.p[a.L.head_b];
+  const long long yrow = tile0 + wave * kRowsPerWave + (lane & (kRowsPerWave - 1));
+  const float yv = yrow < a.n ? a.y[yrow] : 0.0f;
+  // the hidden layers' biases, staged in LDS for the epilogues
+  __shared__ __attribute__((aligned(16))) float bsh[kMlpHidden][kMlpWidth];
+#pragma unroll
+  for (int l = 0; l < kMlpHidden; ++l) bsh[l][tid] = a.p[a.L.b_off[l] + tid];
+  __shared__ float xin[ROWS][4], bfs[kMlpFreq][4];
+  tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) { return a.v[4 * row + e]; });
+  __syncthreads();
+  store_tile_t<ROWS>(act, kMlpIn, tile0, a.X0T);
+
+  const int kq = 8 * (lane >> 4);
+  const int c0 = wave * 64;
+  WSlice ws;
+  {
+    int K;
+    const bf16* M = train_matrix(a, 0, K);
+    load_wslice(ws, M, K, c0, lane);
+  }
+#pragma unroll 1
+  for (int p = 0; p < 2 * kMlpHidden - 1; ++p) {
+    int K;
+    (void)train_matrix(a, p, K);
+    floatx4 acc[kRT][4];
+#pragma unroll
+    for (int i = 0; i < kRT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      if (ks * 32 < K) {
+#pragma unroll
+        for (int i = 0; i < kRT; ++i) {
+          const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + ks * 32 + kq]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ws.f[ks][j], af, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    // the next product's operand, in flight during the epilogue and the stores
+    if (p + 1 < 2 * kMlpHidden - 1) {
+      int Kn;
+      const bf16* Mn = train_matrix(a, p + 1, Kn);
+      load_wslice(ws, Mn, Kn, c0, lane);
+    }
+    __syncthreads();  // every wavefront is past its last read of this product's input
+    if (p < kMlpHidden) {
+      // forward: bias, ReLU, bf16; a lane holds 4 consecutive columns of one row
+      // (and writes their ReLU mask as one byte)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + 16 * j + 4 * (lane >> 4);
+        const float4 b = *reinterpret_cast<const float4*>(&bsh[p][col]);
+        const float bq[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < kRT; ++i) {
+          bf16x4 v;
+          uint32_t m = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            v[q] = (bf16)fmaxf(acc[i][j][q] + bq[q], 0.0f);
+            m |= ((float)v[q] > 0.0f ? 1u : 0u) << q;
+          }
+          if (p < kMlpHidden - 1) mnib[p][16 * i + (lane & 15)][col / 4] = (uint8_t)m;
+          *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
+        }
+      }
+    } else {
+      // backward: dZ_{l-1} = bf16(dZ_l W_l^T) masked by H_{l-1} > 0, l = 9 - p
+      const int lm = 2 * kMlpHidden - 2 - p;  // l - 1
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + 16 * j + 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < kRT; ++i) {
+          const uint32_t m = mnib[lm][16 * i + (lane & 15)][col / 4];
+          bf16x4 v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = ((m >> q) & 1u) ? (bf16)acc[i][j][q] : (bf16)0.0f;
+          *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (p < kMlpHidden - 1) {
+      store_tile_t<ROWS>(act, kMlpWidth, tile0, a.HT + (size_t)p * a.ht_stride);
+    } else if (p == kMlpHidden - 1) {
+      // head on this wavefront's rows: yhat = H_4 . w + b, d = yhat - y,
+      // g = 2 d / n_total, dZ_4 = bf16(g w (H_4 > 0)) in place (each row is
+      // read and written by the same lanes)
+      float gw[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      float gsum = 0.0f, lsum = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kRowsPerWave; ++i) {
+        const int r = wave * kRowsPerWave + i;
+        const bool in = tile0 + r < a.n;
+        float h[4], part = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          h[q] = (float)act[r * ALD + lane * 4 + q];
+          part = fmaf(h[q], wv[q], part);
+        }
+        const float yh = wave_sum(part) + hb;
+        const float d = in ? yh - __int_as_float(__builtin_amdgcn_readlane(__float_as_int(yv), i)) : 0.0f;
+        const float gm = 2.0f * d * a.inv_total;
+        if (in && a.yhat && lane == 0) a.yhat[tile0 + r] = yh;
+        gsum += gm;
+        lsum = fmaf(d, d, lsum);
+        bf16x4 dz;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          gw[q] = fmaf(gm, h[q], gw[q]);
+          dz[q] = (bf16)(h[q] > 0.0f ? gm * wv[q] : 0.0f);
+        }
+        *reinterpret_cast<bf16x4*>(&act[r * ALD + lane * 4]) = dz;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hwp[wave][lane * 4 + q] = gw[q];
+      if (lane == 0) {
+        hsp[wave][0] = gsum;
+        hsp[wave][1] = lsum;
+      }
+      __syncthreads();
+      // the tile's partials, wavefronts in order
+      {
+        float t = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kFusedWaves; ++w) t += hwp[w][tid];
+        a.hw_part[(size_t)blockIdx.x * kMlpWidth + tid] = t;
+        if (tid < 2) {
+          float u = 0.0f;
+#pragma unroll
+          for (int w = 0; w < kFusedWaves; ++w) u += hsp[w][tid];
+          a.hs_part[2 * (size_t)blockIdx.x + tid] = u;
+        }
+      }
+      store_tile_t<ROWS>(act, kMlpWidth, tile0, a.dZT + (size_t)(kMlpHidden - 1) * a.dzt_stride);
+    } else {
+      const int lm = 2 * kMlpHidden - 2 - p;
+      store_tile_t<ROWS>(act, kMlpWidth, tile0, a.dZT + (size_t)lm * a.dzt_stride);
+    }
+  }
+}
+
 // F[t] = (sum over the tiles of transmitter t, in order) / R: the mean of
 // yhat over its R receivers from the fused forward's tile sums.
 __global__ void k_tile_mean(const double* __restrict__ tile_sum, int n_tx, int tiles_per_tx, int R,
@@ -203,91 +456,6 @@ __global__ void k_tile_mean(const double* __restrict__ tile_sum, int n_tx, int t
   double s = 0.0;
   for (int j = 0; j < tiles_per_tx; ++j) s += tile_sum[(size_t)t * tiles_per_tx + j];
   F[t] = (float)(s / R);
-}
-
-// ---------------------------------------------------------------------------
-// Input gradients of the hidden layers, 4 down to 1, fused over the layers
-// like the forward: a workgroup takes kDxRows rows of dZ_4 (the head's
-// gradient, row-major bf16) into LDS and forms
-//   dZ_{l-1} = (dZ_l W_l^T) * (H_{l-1} > 0)
-// in place, wavefront w owning columns 64 w .. 64 w + 63 with the weight
-// fragments (rows of W_l [in][out]) straight from global memory, k in steps of
-// 32, FP32 accumulation.  Each dZ_l (l = 4..0) is stored transposed, dZT + l dzt_stride
-// ([256][ld]), for the weight and bias gradients.
-// ---------------------------------------------------------------------------
-constexpr int kDxRows = 64;  // rows per workgroup of k_mlp_dx: more workgroups for small batches
-
-__global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dx(DxArgs a) {
-  __shared__ __attribute__((aligned(16))) bf16 act[kDxRows * ALD];
-  constexpr int kRT = kDxRows / 16;  // row tiles
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const long long tile0 = (long long)blockIdx.x * kDxRows;
-  for (int i = tid; i < kDxRows * 32; i += kFusedWaves * 64) {
-    const int r = i >> 5, c8 = (i & 31) * 8;
-    uint4 v = {0u, 0u, 0u, 0u};
-    if (tile0 + r < a.n) v = *reinterpret_cast<const uint4*>(a.dz4 + (tile0 + r) * 256 + c8);
-    *reinterpret_cast<uint4*>(&act[r * ALD + c8]) = v;
-  }
-  __syncthreads();
-  store_tile_t<kDxRows>(act, 256, tile0, a.n, a.dZT + (size_t)(kMlpHidden - 1) * a.dzt_stride, a.ld);
-  const int kq = 8 * (lane >> 4);
-  const int c0 = wave * 64;
-#pragma unroll 1
-  for (int l = kMlpHidden - 1; l >= 1; --l) {
-    const bf16* Wl = a.w + a.L.bf_off[l];  // W_l [in = 256][out = 256]
-    const bf16* mask = a.H + (size_t)(l - 1) * a.h_stride;
-    floatx4 acc[kRT][4];
-#pragma unroll
-    for (int i = 0; i < kRT; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8 bw[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      bw[j] = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(c0 + 16 * j + (lane & 15)) * 256 + kq);
-#pragma unroll 1
-    for (int ks = 0; ks < 8; ++ks) {
-      bf16x8 bn[4];
-      const int kn = ks + 1 < 8 ? ks + 1 : ks;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bn[j] = *reinterpret_cast<const bf16x8*>(Wl + (size_t)(c0 + 16 * j + (lane & 15)) * 256 + kn * 32 + kq);
-#pragma unroll
-      for (int i = 0; i < kRT; ++i) {
-        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + ks * 32 + kq]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], af, acc[i][j], 0, 0, 0);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bw[j] = bn[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = c0 + 16 * j + 4 * (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < kRT; ++i) {
-        bf16x4 v;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (bf16)acc[i][j][q];
-        *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
-      }
-    }
-    __syncthreads();
-    // ReLU derivative of layer l - 1, 16 bytes at a time (rows past n become 0)
-    for (int c = tid; c < kDxRows * 32; c += kFusedWaves * 64) {
-      const int r = c >> 5, c8 = (c & 31) * 8;
-      bf16x8 v = *reinterpret_cast<const bf16x8*>(&act[r * ALD + c8]);
-      bf16x8 mk = {};
-      if (tile0 + r < a.n) mk = *reinterpret_cast<const bf16x8*>(mask + (tile0 + r) * 256 + c8);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = (float)mk[q] > 0.0f ? v[q] : (bf16)0.0f;
-      *reinterpret_cast<bf16x8*>(&act[r * ALD + c8]) = v;
-    }
-    __syncthreads();
-    store_tile_t<kDxRows>(act, 256, tile0, a.n, a.dZT + (size_t)(l - 1) * a.dzt_stride, a.ld);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -318,9 +486,14 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   const int nks = (int)((r1 - r0) / 32);
   const int kq = 8 * (lane >> 4);
   const int c0 = wave * 64;
+  // k-step ks (rows r0 + 32 ks ..) is block b0 + ks of both operands
+  const long long b0 = r0 / kTB;
+  const int xcols = l == 0 ? kMlpIn : kMlpWidth;
   // staging: thread -> (row i of the block, 16-row half of the step)
   const int si = tid >> 1, sh = (tid & 1) * 16;
-  const bf16* xsrc = XT + (size_t)(128 * rb + si) * a.ld + r0 + sh;
+  const bf16* xsrc = XT + (size_t)b0 * xcols * kTB + (size_t)(128 * rb + si) * kTB + sh;
+  const size_t xstep = (size_t)xcols * kTB, dstep = (size_t)kMlpWidth * kTB;
+  const bf16* dsrc = DT + (size_t)b0 * dstep + kq;
   floatx4 acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -338,7 +511,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   bf16x8 bw[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
-    bw[j] = *reinterpret_cast<const bf16x8*>(DT + (size_t)(c0 + 16 * j + (lane & 15)) * a.ld + r0 + kq);
+    bw[j] = *reinterpret_cast<const bf16x8*>(dsrc + (size_t)(c0 + 16 * j + (lane & 15)) * kTB);
   __syncthreads();
 #pragma unroll 1
   for (int ks = 0; ks < nks; ++ks) {
@@ -347,13 +520,12 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
     uint4 nx0, nx1;
     bf16x8 bn[4];
     if (more) {
-      const uint4* src = reinterpret_cast<const uint4*>(xsrc + (ks + 1) * 32);
+      const uint4* src = reinterpret_cast<const uint4*>(xsrc + (ks + 1) * xstep);
       nx0 = src[0];
       nx1 = src[1];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bn[j] = *reinterpret_cast<const bf16x8*>(DT + (size_t)(c0 + 16 * j + (lane & 15)) * a.ld + r0 +
-                                                 (ks + 1) * 32 + kq);
+        bn[j] = *reinterpret_cast<const bf16x8*>(dsrc + (ks + 1) * dstep + (size_t)(c0 + 16 * j + (lane & 15)) * kTB);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -400,8 +572,58 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
 // Weight and bias gradients from the partials, slices in order:
 // g[w_off_l + i 256 + o] = sum_s part[l][s][i][o], g[b_off_l + o] = sum_s part_b[l][s][o].
 __global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __restrict__ part_b, int n_slices,
-                             MlpLayout L, float* __restrict__ g) {
+                             MlpLayout L, float* __restrict__ g, HeadFold hf) {
   const int l = blockIdx.y;
+  if (l == kMlpHidden) {
+    // the head (blocks 0..8 of the last row; fixed order throughout):
+    // block b < 8: g[head_w + i], i = 32 b .. 32 b + 31, thread (i, z)
+    // adding tiles z, z + 8, ... with eight loads in flight, then the eight
+    // z in order; block 8: g[head_b] and the loss from the per-tile sums in
+    // FP64 (strided per thread, then a tree), and the Adam step count.
+    __shared__ double dsh[256];
+    if (!hf.hw_part || blockIdx.x > 8) return;
+    const int tid = threadIdx.x;
+    if (blockIdx.x < 8) {
+      const int i = 32 * blockIdx.x + (tid & 31), z = tid >> 5;
+      float s = 0.0f;
+      int t = z;
+      for (; t + 56 < hf.tiles; t += 64) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = hf.hw_part[(size_t)(t + 8 * k) * kMlpWidth + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+      }
+      for (; t < hf.tiles; t += 8) s += hf.hw_part[(size_t)t * kMlpWidth + i];
+      float* sh = reinterpret_cast<float*>(dsh);
+      sh[tid] = s;
+      __syncthreads();
+      if (z == 0) {
+        float u = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u += sh[32 * k + (tid & 31)];
+        g[L.head_w + i] = u;
+      }
+      return;
+    }
+    for (int c = 0; c < 2; ++c) {
+      double u = 0.0;
+      for (int t = tid; t < hf.tiles; t += 256) u += (double)hf.hs_part[2 * (size_t)t + c];
+      dsh[tid] = u;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) dsh[tid] += dsh[tid + w];
+        __syncthreads();
+      }
+      if (tid == 0) {
+        if (c == 0) g[L.head_b] = (float)dsh[0];
+        else if (hf.loss) hf.loss[0] = (float)(dsh[0] * hf.inv_n);
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && hf.step) hf.step[0] += 1;
+    return;
+  }
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // i 256 + o within layer l, then the 256 biases
   const int nw = L.fan_in[l] * 256;
   if (e < nw) {
@@ -415,140 +637,6 @@ __global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __rest
     for (int z = 0; z < n_slices; ++z) s += p[(size_t)z * 256];
     g[L.b_off[l] + e - nw] = s;
   }
-}
-
-// ---------------------------------------------------------------------------
-// Head: yhat = H[m] . w + b (FP32).  Training: d = yhat - y, loss_part[m] = d^2,
-// g[m] = 2 d / n_total, dZ[m][i] = bf16(g w[i] (H[m][i] > 0)).
-// One wavefront per row; 4 rows per workgroup.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_head(const bf16* __restrict__ H, int n, const float* __restrict__ w,
-                                              const float* __restrict__ b, const float* __restrict__ y,
-                                              float inv_total, float* __restrict__ yhat,
-                                              float* __restrict__ loss_part, float* __restrict__ gout,
-                                              bf16* __restrict__ dZ) {
-  const int lane = threadIdx.x & 63;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= n) return;  // whole wavefront leaves together
-  float h[4], wv[4];
-  float part = 0.0f;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    h[q] = (float)H[(size_t)m * 256 + lane * 4 + q];
-    wv[q] = w[lane * 4 + q];
-    part = fmaf(h[q], wv[q], part);
-  }
-  const float yh = wave_sum(part) + b[0];
-  if (yhat && lane == 0) yhat[m] = yh;
-  if (y) {
-    const float d = yh - y[m];
-    const float gm = 2.0f * d * inv_total;
-    if (lane == 0) {
-      loss_part[m] = d * d;
-      gout[m] = gm;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dZ[(size_t)m * 256 + lane * 4 + q] = (bf16)(h[q] > 0.0f ? gm * wv[q] : 0.0f);
-  }
-}
-
-// part[chunk][col] = sum over the chunk's kColChunk rows m of
-// X[m][col] * (wt ? wt[m] : 1); one workgroup per (chunk, 256 columns).
-// Thread (row lane r, column group g) reads 8 columns at once (16 bytes) of
-// rows r, r + 8, ... in order; the 8 row lanes are then added in order
-// through LDS (fixed order overall, with k_colsum_fold).  N % 8 == 0.
-constexpr int kColChunk = 128;
-
-__global__ __launch_bounds__(256) void k_colsum_part(const bf16* __restrict__ X, int M, int N,
-                                                     const float* __restrict__ wt, float* __restrict__ part) {
-  __shared__ float sh[8][256];
-  const int cg = threadIdx.x & 31, rl = threadIdx.x >> 5;
-  const int col0 = blockIdx.y * 256 + cg * 8;
-  const int m0 = blockIdx.x * kColChunk, m1 = min(M, m0 + kColChunk);
-  float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  if (col0 < N) {
-    int m = m0 + rl;
-    // four rows' loads in flight, then their products in row order (the
-    // order of the plain loop below)
-    for (; m + 24 < m1; m += 32) {
-      uint4 raw[4];
-      float w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        raw[q] = *reinterpret_cast<const uint4*>(X + (size_t)(m + 8 * q) * N + col0);
-        w[q] = wt ? wt[m + 8 * q] : 1.0f;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bf16* x = reinterpret_cast<const bf16*>(&raw[q]);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) s[k] = fmaf((float)x[k], w[q], s[k]);
-      }
-    }
-    for (; m < m1; m += 8) {
-      const uint4 raw = *reinterpret_cast<const uint4*>(X + (size_t)m * N + col0);
-      const bf16* x = reinterpret_cast<const bf16*>(&raw);
-      const float w = wt ? wt[m] : 1.0f;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) s[k] = fmaf((float)x[k], w, s[k]);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) sh[rl][cg * 8 + k] = s[k];
-  __syncthreads();
-  const int col = blockIdx.y * 256 + threadIdx.x;
-  if (col < N) {
-    float t = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) t += sh[r][threadIdx.x];
-    part[(size_t)blockIdx.x * N + col] = t;
-  }
-}
-
-// out[col] = sum over chunks of part[chunk][col]: 32 columns per workgroup,
-// 8 threads per column each adding every 8th chunk in order, then the 8
-// partials in order.
-__global__ __launch_bounds__(256) void k_colsum_fold(const float* __restrict__ part, int chunks, int N,
-                                                     float* __restrict__ out) {
-  __shared__ float sh[8][32];
-  const int c = threadIdx.x & 31, q = threadIdx.x >> 5;
-  const int col = blockIdx.x * 32 + c;
-  float s = 0.0f;
-  if (col < N) {
-    int z = q;
-    // eight loads in flight, then the adds in chunk order
-    for (; z + 56 < chunks; z += 64) {
-      float v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = part[(size_t)(z + 8 * j) * N + col];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) s += v[j];
-    }
-    for (; z < chunks; z += 8) s += part[(size_t)z * N + col];
-  }
-  sh[q][c] = s;
-  __syncthreads();
-  if (q == 0 && col < N) {
-    float t = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) t += sh[k][c];
-    out[col] = t;
-  }
-}
-
-// scale * sum(x[0..n)) in FP64, fixed tree order; one workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_sum_scalar(const float* __restrict__ x, int n, double scale,
-                                                     float* __restrict__ out) {
-  __shared__ double sh[1024];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) s += (double)x[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = (float)(scale * sh[0]);
 }
 
 // Segment means: F[t] = mean of yhat[t * R .. t * R + R).  One workgroup per t.
@@ -566,14 +654,12 @@ __global__ void k_segment_mean(const float* __restrict__ yhat, int R, float* __r
   if (threadIdx.x == 0) F[blockIdx.x] = (float)(sh[0] / R);
 }
 
-// Adam on the flat FP32 parameters (torch semantics) with t = step[0] + 1,
-// then BF16 copies W [in][out] and W^T [out][in] of the hidden layers.
-__global__ void k_adam_mlp(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
-                           float* __restrict__ v, const int* __restrict__ step, int n, float lr, float b1,
-                           float b2, float eps, MlpLayout L, bf16* __restrict__ wbf, bf16* __restrict__ wtbf) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One element of Adam (torch semantics) at step t, and its BF16 copies.
+__device__ __forceinline__ void adam_elem(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
+                                          float* __restrict__ v, int t, int i, int n, float lr, float b1, float b2,
+                                          float eps, const MlpLayout& L, bf16* __restrict__ wbf,
+                                          bf16* __restrict__ wtbf) {
   if (i >= n) return;
-  const int t = step[0] + 1;
   const float gi = gr[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -588,13 +674,20 @@ __global__ void k_adam_mlp(float* __restrict__ p, const float* __restrict__ gr, 
     const int off = L.w_off[l], fi = L.fan_in[l];
     if (i >= off && i < off + fi * 256) {
       const int r = (i - off) / 256, c = (i - off) % 256;
-      wbf[L.bf_off[l] + r * 256 + c] = (bf16)pi;
-      wtbf[L.bf_off[l] + c * fi + r] = (bf16)pi;
+      wbf[L.bf_off[l] + frag_off(r, c, 256)] = (bf16)pi;  // W: rows = inputs, k = outputs
+      wtbf[L.bf_off[l] + frag_off(c, r, fi)] = (bf16)pi;  // W^T: rows = outputs, k = inputs
     }
   }
 }
 
-__global__ void k_step_inc(int* step) { step[0] += 1; }
+// Adam on the flat FP32 parameters (torch semantics) at step t = step[0]
+// (counted up by the gradient sums of the same training step), then BF16
+// copies of W and W^T (fragment order) of the hidden layers.
+__global__ void k_adam_mlp(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
+                           float* __restrict__ v, const int* __restrict__ step, int n, float lr, float b1,
+                           float b2, float eps, MlpLayout L, bf16* __restrict__ wbf, bf16* __restrict__ wtbf) {
+  adam_elem(p, gr, m, v, step[0], blockIdx.x * blockDim.x + threadIdx.x, n, lr, b1, b2, eps, L, wbf, wtbf);
+}
 
 // Same bf16 copies without an update (after loading parameters).
 __global__ void k_mlp_copies(const float* __restrict__ p, int n, MlpLayout L, bf16* __restrict__ wbf,
@@ -606,8 +699,8 @@ __global__ void k_mlp_copies(const float* __restrict__ p, int n, MlpLayout L, bf
     const int off = L.w_off[l], fi = L.fan_in[l];
     if (i >= off && i < off + fi * 256) {
       const int r = (i - off) / 256, c = (i - off) % 256;
-      wbf[L.bf_off[l] + r * 256 + c] = (bf16)p[i];
-      wtbf[L.bf_off[l] + c * fi + r] = (bf16)p[i];
+      wbf[L.bf_off[l] + frag_off(r, c, 256)] = (bf16)p[i];
+      wtbf[L.bf_off[l] + frag_off(c, r, fi)] = (bf16)p[i];
     }
   }
 }
@@ -644,46 +737,25 @@ hipError_t launch_tile_mean(const double* tile_sum, int n_tx, int tiles_per_tx, 
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_dx(const DxArgs& a, hipStream_t st) {
+hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_dx, dim3((unsigned)((a.n + kDxRows - 1) / kDxRows)), dim3(kFusedWaves * 64), 0, st, a);
+  if (a.n % kTrainRows != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_mlp_train<kTrainRows>, dim3((unsigned)(a.n / kTrainRows)), dim3(kFusedWaves * 64), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_dw(const DwArgs& a, float* g, hipStream_t st) {
+int mlp_train_rows() { return kTrainRows; }
+
+hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
-  if (a.n % 32 != 0 || a.slice_rows % 32 != 0 || a.ld % 8 != 0) return hipErrorInvalidValue;
+  if (a.n % kTB != 0 || a.slice_rows % kTB != 0) return hipErrorInvalidValue;
   // items: layer 0 (one block of 128 inputs) + layers 1..4 (two blocks each)
   const int items = 1 + 2 * (kMlpHidden - 1);
   hipLaunchKernelGGL(k_mlp_dw, dim3(items * a.n_slices), dim3(kFusedWaves * 64), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_dw_sum, dim3(257, kMlpHidden), dim3(256), 0, st, a.part, a.part_b, a.n_slices, a.L, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_head(const bf16* H, int n, const float* w, const float* b, const float* y, float inv_total,
-                       float* yhat, float* loss_part, float* gout, bf16* dZ, hipStream_t st) {
-  hipLaunchKernelGGL(k_head, dim3((n + 3) / 4), dim3(256), 0, st, H, n, w, b, y, inv_total, yhat, loss_part, gout,
-                     dZ);
-  return hipGetLastError();
-}
-
-int colsum_chunks(int M) { return (M + kColChunk - 1) / kColChunk; }
-
-hipError_t launch_colsum(const bf16* X, int M, int N, const float* wt, float* part, float* out, hipStream_t st) {
-  const int chunks = colsum_chunks(M);
-  if (chunks <= 0 || N <= 0) return hipSuccess;
-  if (N % 8 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_colsum_part, dim3(chunks, (N + 255) / 256), dim3(256), 0, st, X, M, N, wt, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_colsum_fold, dim3((N + 31) / 32), dim3(256), 0, st, part, chunks, N, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_sum_scalar(const float* x, int n, double scale, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(1024), 0, st, x, n, scale, out);
+  hipLaunchKernelGGL(k_mlp_dw_sum, dim3(257, kMlpHidden + 1), dim3(256), 0, st, a.part, a.part_b, a.n_slices, a.L, g,
+                     hf);
   return hipGetLastError();
 }
 
@@ -692,13 +764,10 @@ hipError_t launch_segment_mean(const float* yhat, int T, int R, float* F, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, int* step, int n, float lr, float b1,
+hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, const int* step, int n, float lr, float b1,
                            float b2, float eps, const MlpLayout& L, bf16* wbf, bf16* wtbf, hipStream_t st) {
   hipLaunchKernelGGL(k_adam_mlp, dim3((n + 255) / 256), dim3(256), 0, st, p, gr, m, v, step, n, lr, b1, b2, eps, L,
                      wbf, wtbf);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step);
   return hipGetLastError();
 }
 
