@@ -51,6 +51,11 @@ __device__ __forceinline__ size_t frag_off(int c, int k, int K) {
          (k & 7);
 }
 
+// Workgroup barrier that orders LDS only, so that global loads stay in
+// flight across it (used where no wavefront reads global memory that
+// another wavefront of the workgroup writes in the same launch).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // This lane's operand of (wavefront s, k-step ks, column tile j).
 __device__ __forceinline__ const bf16* frag_ptr(const bf16* M, int K, int s, int ks, int j, int lane) {
   return M + ((((size_t)s * (K >> 5) + ks) * 4 + j) * 64 + lane) * 8;
@@ -502,51 +507,71 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   // the first block of each layer also sums its dZ^T fragments: bias partials
   const bool bias = rb == 0;
   float bsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // pipeline, two k-steps deep: at step ks the X^T piece and the dZ^T
+  // fragments of step ks + 2 are requested, the X^T piece of step ks + 1
+  // (requested one step earlier) goes to the other LDS buffer, and the
+  // barriers order LDS only, so the requests stay in flight across them
+  auto xload = [&](int ks, uint4& x0, uint4& x1) {
+    const uint4* src = reinterpret_cast<const uint4*>(xsrc + (size_t)ks * xstep);
+    x0 = src[0];
+    x1 = src[1];
+  };
+  auto dload = [&](int ks, bf16x8 (&d)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      d[j] = *reinterpret_cast<const bf16x8*>(dsrc + (size_t)ks * dstep + (size_t)(c0 + 16 * j + (lane & 15)) * kTB);
+  };
+  // three register sets for each operand, rotated by name (the loop body
+  // is written out three times), so no copy waits for a load in flight
+  uint4 X0a = {}, X0b = {}, X1a = {}, X1b = {}, X2a = {}, X2b = {};
+  bf16x8 D0[4] = {}, D1[4] = {}, D2[4] = {};
   if (nks > 0) {
-    const uint4* src = reinterpret_cast<const uint4*>(xsrc);
-    uint4* dst = reinterpret_cast<uint4*>(&xs[0][si * XLD + sh]);
-    dst[0] = src[0];
-    dst[1] = src[1];
+    xload(0, X0a, X0b);
+    dload(0, D0);
   }
-  bf16x8 bw[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    bw[j] = *reinterpret_cast<const bf16x8*>(dsrc + (size_t)(c0 + 16 * j + (lane & 15)) * kTB);
-  __syncthreads();
-#pragma unroll 1
-  for (int ks = 0; ks < nks; ++ks) {
+  if (nks > 1) {
+    xload(1, X1a, X1b);
+    dload(1, D1);
+  }
+  if (nks > 0) {
+    uint4* dst = reinterpret_cast<uint4*>(&xs[0][si * XLD + sh]);
+    dst[0] = X0a;
+    dst[1] = X0b;
+  }
+  lds_barrier();
+  // step ks: request step ks + 2 into (dl, xl), multiply with dc and LDS
+  // buffer ks % 2, store the X^T piece of step ks + 1 (xw) to the other buffer
+  auto step = [&](int ks, const bf16x8 (&dc)[4], bf16x8 (&dl)[4], uint4& xl0, uint4& xl1, const uint4& xw0,
+                  const uint4& xw1) __attribute__((always_inline)) {
     const int buf = ks & 1;
-    const bool more = ks + 1 < nks;
-    uint4 nx0, nx1;
-    bf16x8 bn[4];
-    if (more) {
-      const uint4* src = reinterpret_cast<const uint4*>(xsrc + (ks + 1) * xstep);
-      nx0 = src[0];
-      nx1 = src[1];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bn[j] = *reinterpret_cast<const bf16x8*>(dsrc + (ks + 1) * dstep + (size_t)(c0 + 16 * j + (lane & 15)) * kTB);
-    }
+    // (always issued, clamped to the last step, so the wait counts are static)
+    const int kn = ks + 2 < nks ? ks + 2 : nks - 1;
+    xload(kn, xl0, xl1);
+    dload(kn, dl);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const bf16x8 af = *reinterpret_cast<const bf16x8*>(&xs[buf][(16 * i + (lane & 15)) * XLD + kq]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], af, acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dc[j], af, acc[i][j], 0, 0, 0);
     }
     if (bias) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) bsum[j] += (float)bw[j][q];
+        for (int q = 0; q < 8; ++q) bsum[j] += (float)dc[j][q];
     }
-    if (more) {
+    if (ks + 1 < nks) {
       uint4* dst = reinterpret_cast<uint4*>(&xs[buf ^ 1][si * XLD + sh]);
-      dst[0] = nx0;
-      dst[1] = nx1;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bw[j] = bn[j];
+      dst[0] = xw0;
+      dst[1] = xw1;
     }
-    __syncthreads();
+    lds_barrier();
+  };
+#pragma unroll 1
+  for (int ks = 0; ks < nks; ks += 3) {
+    step(ks, D0, D2, X2a, X2b, X1a, X1b);
+    if (ks + 1 < nks) step(ks + 1, D1, D0, X0a, X0b, X2a, X2b);
+    if (ks + 2 < nks) step(ks + 2, D2, D1, X1a, X1b, X0a, X0b);
   }
   if (bias) {
     // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the four 8-row slots of column o
