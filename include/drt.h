@@ -419,6 +419,14 @@ int drt_mlp_grads(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t 
 int drt_mlp_train_step(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t n, float lr,
                        float* loss_dev, void* stream);
 
+/* drt_mlp_train_step on the rows rows_dev[0..n) of v_dev / y_dev (int32
+   device indices into arrays of any length; the caller keeps them in range):
+   a shuffled mini-batch without gathering it first.  Same arithmetic as
+   drt_mlp_train_step on the gathered rows.  n as there; rows_dev NULL is
+   DRT_EINVAL. */
+int drt_mlp_train_step_rows(drt_mlp* mlp, const float* v_dev, const float* y_dev, const int32_t* rows_dev,
+                            int64_t n, float lr, float* loss_dev, void* stream);
+
 /* yhat_dev [n] for inputs v_dev [n][4] (any n >= 0; processed in chunks). */
 int drt_mlp_forward(drt_mlp* mlp, const float* v_dev, int64_t n, float* yhat_dev, void* stream);
 

@@ -108,6 +108,8 @@ _SIGS = {
     "drt_mlp_set_params": ([c_void_p, c_void_p], c_int32),
     "drt_mlp_grads": ([c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p], c_int32),
     "drt_mlp_train_step": ([c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p, c_void_p], c_int32),
+    "drt_mlp_train_step_rows": ([c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p,
+                                 c_void_p], c_int32),
     "drt_mlp_forward": ([c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p], c_int32),
     "drt_mlp_scan": ([c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p], c_int32),
     "drt_log_targets": ([c_void_p, ctypes.c_int64, c_float, c_void_p, c_void_p], c_int32),

@@ -97,8 +97,8 @@ drt::FusedArgs fused_args(drt_mlp* h, long long n) {
 // Forward + MSE + backward on rows [0, n) of v/y; gradients into h->g, loss
 // (mean squared error over n) into loss_dev; with `count_step`, the Adam step
 // count is advanced for the update that follows.
-int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss_dev, bool count_step,
-                  hipStream_t st) {
+int enqueue_grads(drt_mlp* h, const float* v, const float* y, const int32_t* rows, int n, float* loss_dev,
+                  bool count_step, hipStream_t st) {
   const drt::MlpLayout& L = h->L;
   const int W = drt::kMlpWidth;
   const long long ldt = h->max_batch;
@@ -107,6 +107,7 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, int n, float* loss
   drt::TrainArgs ta{};
   ta.v = v;
   ta.y = y;
+  ta.rows = rows;
   ta.Bf = h->Bf;
   ta.wt = h->wtbf;
   ta.w = h->wbf;
@@ -243,7 +244,7 @@ int drt_mlp_grads(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t 
   if (rc) return rc;
   if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, false, st))) return rc;
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, nullptr, (int)n, loss_dev, false, st))) return rc;
   if (grads_dev) HIPCHK(hipMemcpyAsync(grads_dev, mlp->g, (size_t)mlp->L.n_params * 4, hipMemcpyDeviceToDevice, st),
                         "grad copy");
   return DRT_OK;
@@ -256,7 +257,21 @@ int drt_mlp_train_step(drt_mlp* mlp, const float* v_dev, const float* y_dev, int
   if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
   if (!(lr > 0.0f) || !std::isfinite(lr)) return failf(DRT_EINVAL, "lr must be finite and > 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, (int)n, loss_dev, true, st))) return rc;
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, nullptr, (int)n, loss_dev, true, st))) return rc;
+  HIPCHK(drt::launch_adam_mlp(mlp->p, mlp->g, mlp->m, mlp->v, mlp->step, mlp->L.n_params, lr, 0.9f, 0.999f, 1e-8f,
+                              mlp->L, mlp->wbf, mlp->wtbf, st),
+         "adam");
+  return DRT_OK;
+}
+
+int drt_mlp_train_step_rows(drt_mlp* mlp, const float* v_dev, const float* y_dev, const int32_t* rows_dev,
+                            int64_t n, float lr, float* loss_dev, void* stream) {
+  int rc = check_rows(mlp, n);
+  if (rc) return rc;
+  if (!v_dev || !y_dev || !rows_dev) return failf(DRT_EINVAL, "v_dev / y_dev / rows_dev is NULL");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return failf(DRT_EINVAL, "lr must be finite and > 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, rows_dev, (int)n, loss_dev, true, st))) return rc;
   HIPCHK(drt::launch_adam_mlp(mlp->p, mlp->g, mlp->m, mlp->v, mlp->step, mlp->L.n_params, lr, 0.9f, 0.999f, 1e-8f,
                               mlp->L, mlp->wbf, mlp->wtbf, st),
          "adam");

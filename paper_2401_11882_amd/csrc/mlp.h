@@ -56,6 +56,7 @@ hipError_t launch_tile_mean(const double* tile_sum, int n_tx, int tiles_per_tx, 
 struct TrainArgs {
   const float* v;
   const float* y;
+  const int32_t* rows;  // NULL: row m is sample m; else sample rows[m]
   const float* Bf;
   const __bf16* wt;
   const __bf16* w;

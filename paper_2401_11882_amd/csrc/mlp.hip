@@ -308,13 +308,15 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_train(TrainArgs a) 
   for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
   const float hb = a.p[a.L.head_b];
   const long long yrow = tile0 + wave * kRowsPerWave + (lane & (kRowsPerWave - 1));
-  const float yv = yrow < a.n ? a.y[yrow] : 0.0f;
+  const float yv = yrow < a.n ? a.y[a.rows ? (long long)a.rows[yrow] : yrow] : 0.0f;
   // the hidden layers' biases, staged in LDS for the epilogues
   __shared__ __attribute__((aligned(16))) float bsh[kMlpHidden][kMlpWidth];
 #pragma unroll
   for (int l = 0; l < kMlpHidden; ++l) bsh[l][tid] = a.p[a.L.b_off[l] + tid];
   __shared__ float xin[ROWS][4], bfs[kMlpFreq][4];
-  tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) { return a.v[4 * row + e]; });
+  tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) {
+    return a.v[4 * (a.rows ? (long long)a.rows[row] : row) + e];
+  });
   __syncthreads();
   store_tile_t<ROWS>(act, kMlpIn, tile0, a.X0T);
 

@@ -82,9 +82,16 @@ class Surrogate:
         check(lib().drt_mlp_grads(self._h, _p(v), _p(y), v.shape[0], _p(g), _p(loss), tr.stream_handle()))
         return g, loss
 
-    def train_step(self, v: torch.Tensor, y: torch.Tensor, lr: float) -> torch.Tensor:
-        check(lib().drt_mlp_train_step(self._h, _p(v), _p(y), v.shape[0], float(lr), _p(self._loss),
-                                       tr.stream_handle()))
+    def train_step(self, v: torch.Tensor, y: torch.Tensor, lr: float, rows: torch.Tensor | None = None) -> torch.Tensor:
+        """One Adam step on the rows of (v, y), or on the rows `rows` (int32,
+        on the device) of them when given; returns the device loss."""
+        if rows is None:
+            check(lib().drt_mlp_train_step(self._h, _p(v), _p(y), v.shape[0], float(lr), _p(self._loss),
+                                           tr.stream_handle()))
+        else:
+            assert rows.dtype == torch.int32 and rows.is_contiguous()
+            check(lib().drt_mlp_train_step_rows(self._h, _p(v), _p(y), _p(rows), rows.shape[0], float(lr),
+                                                _p(self._loss), tr.stream_handle()))
         return self._loss
 
     def forward(self, v: torch.Tensor) -> torch.Tensor:
@@ -151,14 +158,12 @@ def train(surr: Surrogate, v: torch.Tensor, y: torch.Tensor, epochs: int, batch:
     steps_total = epochs * (n // batch)
     k = 0
     for ep in range(epochs):
-        perm = torch.randperm(v.shape[0], device=v.device, generator=gen)[:n]
+        perm = torch.randperm(v.shape[0], device=v.device, generator=gen)[:n].to(torch.int32)
         acc = torch.zeros(1, device=v.device)
         for s in range(0, n, batch):
-            idx = perm[s:s + batch]
-            vb = v.index_select(0, idx).contiguous()
-            yb = yn.index_select(0, idx).contiguous()
             lr_k = lr if lr_final is None else lr * (lr_final / lr) ** (k / max(1, steps_total - 1))
-            acc += surr.train_step(vb, yb, lr_k)
+            # the kernels read the shuffled rows through the index slice: no gather
+            acc += surr.train_step(v, yn, lr_k, rows=perm[s:s + batch])
             k += 1
         hist.append(float(acc) / (n // batch))
         if log_every and (ep + 1) % log_every == 0:

@@ -128,6 +128,9 @@ def test_call_validation_before_launch():
     assert L.drt_alpha_schedule(BOGUS, 100, 0.0, 100.0, BOGUS, 4, None) == _lib.DRT_EINVAL
     assert L.drt_alpha_schedule(BOGUS, 100, 1.0, 100.0, BOGUS, 0, None) == _lib.DRT_EINVAL
     assert L.drt_alpha_schedule(None, 100, 1.0, 100.0, BOGUS, 4, None) == _lib.DRT_EINVAL
+    # surrogate steps: a NULL handle, or a NULL row list, is rejected on the host
+    assert L.drt_mlp_train_step(None, BOGUS, BOGUS, 64, 1e-3, None, None) == _lib.DRT_EINVAL
+    assert L.drt_mlp_train_step_rows(None, BOGUS, BOGUS, BOGUS, 64, 1e-3, None, None) == _lib.DRT_EINVAL
     # the min loss needs a receiver; an unknown smoothing is not supported
     empty = _scene(n_rx=0, rx_dev=None, rx_grid_nx=0)
     assert L.drt_forward(ctypes.byref(empty), 3, 1e-6, None, BOGUS, None, BOGUS, 1 << 30, None) == _lib.DRT_EINVAL

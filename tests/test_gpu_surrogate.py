@@ -90,6 +90,25 @@ def test_train_step_is_adam_on_the_gradients():
     net.close()
 
 
+def test_train_step_on_row_indices_equals_gathered_rows():
+    """drt_mlp_train_step_rows on an index list = drt_mlp_train_step on the gathered rows, bitwise."""
+    S, a = _net()
+    _, b = _net()
+    v, y = _inputs(3000, seed=4)
+    vd, yd = torch.tensor(v).cuda(), torch.tensor(y).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    rows = torch.randperm(3000, device="cuda", generator=g)[:1024].to(torch.int32).contiguous()
+    for step in range(2):
+        la = a.train_step(vd, yd, 1e-3, rows=rows).clone()
+        lb = b.train_step(vd.index_select(0, rows.long()).contiguous(),
+                          yd.index_select(0, rows.long()).contiguous(), 1e-3).clone()
+        assert torch.equal(la, lb), (step, float(la), float(lb))
+    np.testing.assert_array_equal(a.params(), b.params())
+    a.close()
+    b.close()
+
+
 def test_scan_is_mean_of_forward():
     S, net = _net(max_batch=8192)
     tx = torch.tensor(WL.rx_grid(4)).cuda()          # 16 transmitters
