@@ -10,8 +10,8 @@ bracket each kernel.  path-evals per step =
 receivers x candidates = 65,536 x 4,625.
 
 Prints one JSON line (see the fields below).  Inputs are resident in device
-memory before timing starts.  --gpus N > 1 is refused: this build runs on one
-GPU.
+memory before timing starts.  --gpus N > 1 is refused: the benchmark runs on
+one GPU.
 """
 from __future__ import annotations
 
@@ -502,8 +502,8 @@ def main() -> int:
                     help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a design "
-              "note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
+              "described, not implemented.", file=sys.stderr)
         return 2
     rank = int(os.environ.get("RANK", "0"))
     if args.extra is not None:
