@@ -470,10 +470,12 @@ __global__ void k_tile_mean(const double* __restrict__ tile_sum, int n_tx, int t
 //   part[l][s][i][o] = sum over the rows r of slice s of X_l^T[i][r] dZ_l^T[o][r]
 // and the bias partials part_b[l][s][o] = sum over those rows of dZ_l^T[o][r]
 // (X_0 = the features, X_l = H_{l-1}), both operands contiguous in r.  A work
-// item is (layer, block of 128 rows i, slice); the X^T tile of a 32-row step
-// is staged in LDS (double-buffered) for the workgroup's 4 wavefronts, each
-// wavefront owning 64 columns o whose dZ^T fragments come straight from
-// global memory.  k in increasing steps of 32 within a slice.
+// item is (layer, block of 128 rows i, half of the 256 columns o, slice): the
+// halves double the workgroups, so two or more share a CU and cover each
+// other's loads and barriers.  The X^T tile of a 32-row step is staged in LDS
+// (double-buffered) for the workgroup's 4 wavefronts, each wavefront owning
+// 32 columns o whose dZ^T fragments come straight from global memory.  k in
+// increasing steps of 32 within a slice.
 // ---------------------------------------------------------------------------
 constexpr int XLD = 32 + 8;     // staged X^T step row stride (bf16)
 
@@ -481,9 +483,12 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   __shared__ __attribute__((aligned(16))) bf16 xs[2][128 * XLD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  // decode the work item: layer 0 has one block of 128 rows (fan-in 128), the others two
+  // decode the work item: half oh of the outputs o; layer 0 has one block
+  // of 128 rows i (fan-in 128), the others two
   int item = blockIdx.x / a.n_slices;
   const int s = blockIdx.x - item * a.n_slices;
+  const int oh = item & 1;
+  item >>= 1;
   const int l = item == 0 ? 0 : 1 + (item - 1) / 2;
   const int rb = item == 0 ? 0 : (item - 1) % 2;
   const bf16* XT = l == 0 ? a.X0T : a.HT + (size_t)(l - 1) * a.ht_stride;
@@ -492,7 +497,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   const long long r1 = r0 + a.slice_rows < a.n ? r0 + a.slice_rows : a.n;
   const int nks = (int)((r1 - r0) / 32);
   const int kq = 8 * (lane >> 4);
-  const int c0 = wave * 64;
+  const int c0 = 128 * oh + 32 * wave;  // this wavefront's 32 columns o
   // k-step ks (rows r0 + 32 ks ..) is block b0 + ks of both operands
   const long long b0 = r0 / kTB;
   const int xcols = l == 0 ? kMlpIn : kMlpWidth;
@@ -501,14 +506,14 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   const bf16* xsrc = XT + (size_t)b0 * xcols * kTB + (size_t)(128 * rb + si) * kTB + sh;
   const size_t xstep = (size_t)xcols * kTB, dstep = (size_t)kMlpWidth * kTB;
   const bf16* dsrc = DT + (size_t)b0 * dstep + kq;
-  floatx4 acc[8][4];
+  floatx4 acc[8][2];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
   // the first block of each layer also sums its dZ^T fragments: bias partials
   const bool bias = rb == 0;
-  float bsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float bsum[2] = {0.0f, 0.0f};
   // pipeline, two k-steps deep: at step ks the X^T piece and the dZ^T
   // fragments of step ks + 2 are requested, the X^T piece of step ks + 1
   // (requested one step earlier) goes to the other LDS buffer, and the
@@ -518,15 +523,15 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
     x0 = src[0];
     x1 = src[1];
   };
-  auto dload = [&](int ks, bf16x8 (&d)[4]) {
+  auto dload = [&](int ks, bf16x8 (&d)[2]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
       d[j] = *reinterpret_cast<const bf16x8*>(dsrc + (size_t)ks * dstep + (size_t)(c0 + 16 * j + (lane & 15)) * kTB);
   };
   // three register sets for each operand, rotated by name (the loop body
   // is written out three times), so no copy waits for a load in flight
   uint4 X0a = {}, X0b = {}, X1a = {}, X1b = {}, X2a = {}, X2b = {};
-  bf16x8 D0[4] = {}, D1[4] = {}, D2[4] = {};
+  bf16x8 D0[2] = {}, D1[2] = {}, D2[2] = {};
   if (nks > 0) {
     xload(0, X0a, X0b);
     dload(0, D0);
@@ -543,7 +548,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   lds_barrier();
   // step ks: request step ks + 2 into (dl, xl), multiply with dc and LDS
   // buffer ks % 2, store the X^T piece of step ks + 1 (xw) to the other buffer
-  auto step = [&](int ks, const bf16x8 (&dc)[4], bf16x8 (&dl)[4], uint4& xl0, uint4& xl1, const uint4& xw0,
+  auto step = [&](int ks, const bf16x8 (&dc)[2], bf16x8 (&dl)[2], uint4& xl0, uint4& xl1, const uint4& xw0,
                   const uint4& xw1) __attribute__((always_inline)) {
     const int buf = ks & 1;
     // (always issued, clamped to the last step, so the wait counts are static)
@@ -554,11 +559,11 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
     for (int i = 0; i < 8; ++i) {
       const bf16x8 af = *reinterpret_cast<const bf16x8*>(&xs[buf][(16 * i + (lane & 15)) * XLD + kq]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dc[j], af, acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dc[j], af, acc[i][j], 0, 0, 0);
     }
     if (bias) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int q = 0; q < 8; ++q) bsum[j] += (float)dc[j][q];
     }
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   if (bias) {
     // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the four 8-row slots of column o
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 2; ++j) {
       float b = bsum[j];
       b += __shfl_xor(b, 16);
       b += __shfl_xor(b, 32);
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   // (dZ^T as the first MFMA operand: a lane holds 4 consecutive columns o of one row i)
   float* out = a.part + ((size_t)l * a.n_slices + s) * 256 * 256;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 2; ++j) {
     const int o = c0 + 16 * j + 4 * (lane >> 4);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -777,7 +782,7 @@ hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, hipStrea
   if (a.n <= 0) return hipSuccess;
   if (a.n % kTB != 0 || a.slice_rows % kTB != 0) return hipErrorInvalidValue;
   // items: layer 0 (one block of 128 inputs) + layers 1..4 (two blocks each)
-  const int items = 1 + 2 * (kMlpHidden - 1);
+  const int items = 2 * (1 + 2 * (kMlpHidden - 1));  // (layer, row block) x two halves of the outputs
   hipLaunchKernelGGL(k_mlp_dw, dim3(items * a.n_slices), dim3(kFusedWaves * 64), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
