@@ -148,6 +148,7 @@ drt::Trace3Args make_args3(const drt3_scene* s, const Plan3& p, void* ws) {
   A.n_rx = s->n_rx;
   A.grid_nx = s->rx_grid_nx;
   A.n_cand = (int)count_candidates(s->n_panels, s->max_order);
+  A.max_order = s->max_order;
   A.alpha = s->alpha;
   A.a2 = s->alpha * drt::kLog2e;
   A.band_k = 1.0f + 2.0f * (hard ? drt::kHardBandMargin : drt::kBandMargin) / s->alpha;

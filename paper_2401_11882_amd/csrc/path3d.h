@@ -662,30 +662,42 @@ __device__ __forceinline__ void path_adjoint3_known(const Scene3View& S, const C
 // Contribution of candidate cd at this lane; with mask_out, its culling masks
 // are kept there (see visit_panels).  A lane drops the candidate (returns 0)
 // once its contribution is provably <= scut (the contribution cut).
-template <int MODE>
+// (MAXK: the highest order the caller's candidates can have; the code of
+// higher orders is left out.)
+template <int MODE, int MAXK = 3>
 __device__ __forceinline__ float candidate_power3(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                   float tz, float rx, float ry, float rz, bool live,
                                                   uint64_t* mask_out = nullptr, float scut = 0.0f) {
+  static_assert(MAXK >= 1 && MAXK <= 3, "orders 1..3");
   switch (cd.k) {
     case 0: return path_power3<0, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
     case 1: return path_power3<1, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
-    case 2: return path_power3<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
-    default: return path_power3<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
+    case 2:
+      if constexpr (MAXK >= 2) return path_power3<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
+      else return 0.0f;
+    default:
+      if constexpr (MAXK >= 3) return path_power3<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, mask_out, scut);
+      else return 0.0f;
   }
 }
 
 // Adjoint of candidate cd given Wl = g(r) c; with mask_in, the culling masks
 // its forward recorded.
-template <int MODE>
+template <int MODE, int MAXK = 3>
 __device__ __forceinline__ void candidate_adjoint3(const Scene3View& S, const Cand& cd, float tx, float ty,
                                                    float tz, float rx, float ry, float rz, bool live, float Wl,
                                                    float* acc, int lane, LaneGrad3& G,
                                                    const uint64_t* mask_in = nullptr) {
+  static_assert(MAXK >= 1 && MAXK <= 3, "orders 1..3");
   switch (cd.k) {
     case 0: path_adjoint3_known<0, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
     case 1: path_adjoint3_known<1, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
-    case 2: path_adjoint3_known<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
-    default: path_adjoint3_known<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in); break;
+    case 2:
+      if constexpr (MAXK >= 2) path_adjoint3_known<2, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in);
+      break;
+    default:
+      if constexpr (MAXK >= 3) path_adjoint3_known<3, MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, mask_in);
+      break;
   }
 }
 

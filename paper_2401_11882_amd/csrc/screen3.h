@@ -121,6 +121,7 @@ __device__ __forceinline__ bool step3_ranges(const PanelRec& w, float Ix, float 
 // Screen of candidate cd (order <= 3) for the receivers in box B.  False only
 // if every receiver in the box has a zero interaction factor.  Panel records
 // are read again where needed rather than held, to keep registers free.
+template <int MAXK = 3>
 __device__ __forceinline__ bool screen_candidate3(const PanelRec* panels, float lim, const Cand& cd, float tx,
                                                   float ty, float tz, const RxBox3& B) {
   if (cd.k == 0) return true;
@@ -129,7 +130,7 @@ __device__ __forceinline__ bool screen_candidate3(const PanelRec* panels, float 
   float cx = tx, cy = ty, cz = tz;
   bool ok = true;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < MAXK; ++i) {
     if (i < cd.k) {
       const PanelRec w = load_panel_lane(panels, sv[i]);
       ok = ok && (w.s > 0.0f);
@@ -149,7 +150,7 @@ __device__ __forceinline__ bool screen_candidate3(const PanelRec* panels, float 
   float b0 = 0.0f, b1 = 0.0f, g0 = 0.0f, g1 = 0.0f;
   float ax = 0.0f, ay = 0.0f, az = 0.0f, e1x = 0.0f, e1y = 0.0f, e1z = 0.0f, e2x = 0.0f, e2y = 0.0f, e2z = 0.0f;
 #pragma unroll
-  for (int i = 3; i >= 1; --i) {
+  for (int i = MAXK; i >= 1; --i) {
     if (i > cd.k) continue;
     const PanelRec wi = load_panel_lane(panels, sv[i - 1]);
     float lo[3], hi[3];
@@ -194,7 +195,7 @@ __device__ __forceinline__ bool screen_candidate3(const PanelRec* panels, float 
 // Calls fn(c, cd) (wave-uniform) for every candidate of this wavefront's
 // share of [c_begin, n_cand) (c = c_begin + wave + nw p, p = 0, 1, ...) that
 // survives the screen, in increasing order.
-template <class Fn>
+template <int MAXK = 3, class Fn>
 __device__ __forceinline__ void for_screened3(const PanelRec* panels, int n_panels, int c_begin, int n_cand,
                                               float lim, bool test, int wave, int nw, float tx, float ty, float tz,
                                               const RxBox3& B, Fn&& fn) {
@@ -206,7 +207,7 @@ __device__ __forceinline__ void for_screened3(const PanelRec* panels, int n_pane
     bool keep = false;
     if (c < n_cand) {
       cd = decode_candidate(c, n_panels);
-      keep = !test || screen_candidate3(panels, lim, cd, tx, ty, tz, B);
+      keep = !test || screen_candidate3<MAXK>(panels, lim, cd, tx, ty, tz, B);
     }
     uint64_t m = ballot(keep);
     while (m) {

@@ -22,6 +22,7 @@ struct Trace3Args {
   int n_rx;
   int grid_nx;             // 0 = consecutive receivers per wavefront
   int n_cand;
+  int max_order;           // highest interaction order of the candidates
   float alpha;
   float a2;                // alpha * log2(e)
   float band_k;            // 1 + 2 * 18 / alpha

@@ -91,7 +91,7 @@ __global__ void k_prep_panels(const float* __restrict__ pan, int n, float cull_c
   boxes[j] = q;
 }
 
-template <int NW, int MODE>
+template <int NW, int MODE, int MAXK>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_forward3(Trace3Args A, float* __restrict__ power,
                                                          float* __restrict__ seed, float* __restrict__ loss_part,
                                                          int loss_kind, float log_eps) {
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   // sum of the later candidates bound P(r) from below.
   float cut_base = 0.0f, own1 = 0.0f;
   auto visit = [&](int c, const Cand& cd) {
-    const float v = candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr,
+    const float v = candidate_power3<MODE, MAXK>(S, cd, tx, ty, tz, rx, ry, rz, live, cache_c ? mrec[wave] : nullptr,
                                            A.cut * (cut_base + (sum - comp) - own1));
     kahan_add(sum, comp, v);
     if (cache_c && ballot(v != 0.0f) != 0) {
@@ -135,12 +135,12 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   // phase 0: candidates [0, n1) (orders 0-1), phase 1: [n1, C); one copy of
   // the candidate code serves both (the loop is not unrolled)
   if constexpr (!uses_cut<MODE>()) {
-    for_screened3(A.panels, A.n_panels, 0, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box, visit);
+    for_screened3<MAXK>(A.panels, A.n_panels, 0, A.n_cand, lim, A.screen != 0, wave, NW, tx, ty, tz, box, visit);
   } else {
     const int n1 = min(A.n_cand, 1 + A.n_panels);
 #pragma nounroll
     for (int ph = 0; ph < 2; ++ph) {
-      for_screened3(A.panels, A.n_panels, ph ? n1 : 0, ph ? A.n_cand : n1, lim, A.screen != 0, wave, NW, tx, ty,
+      for_screened3<MAXK>(A.panels, A.n_panels, ph ? n1 : 0, ph ? A.n_cand : n1, lim, A.screen != 0, wave, NW, tx, ty,
                     tz, box, visit);
       if (ph == 0) {
         own1 = sum - comp;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(6, 8
   }
 }
 
-template <int NW, int MODE>
+template <int NW, int MODE, int MAXK>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_backward3(Trace3Args A, const float* __restrict__ gP,
                                                           float* __restrict__ part, float* __restrict__ grad_rx,
                                                           int reuse) {
@@ -211,14 +211,14 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         const Cand cd = decode_candidate(cache_idx[p], A.n_panels);
         const uint64_t masks =
             lane < A.mask_stride ? A.cache_mask[((size_t)slot * A.cache_cap + p) * A.mask_stride + lane] : 0;
-        candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, &masks);
+        candidate_adjoint3<MODE, MAXK>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G, &masks);
       }
     } else if constexpr (!uses_cut<MODE>()) {
       for (int c = wave; c < A.n_cand; c += NW) {
         const Cand cd = decode_candidate(c, A.n_panels);
-        const float Wl = g * candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live);
+        const float Wl = g * candidate_power3<MODE, MAXK>(S, cd, tx, ty, tz, rx, ry, rz, live);
         if (ballot(Wl != 0.0f) == 0) continue;
-        candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
+        candidate_adjoint3<MODE, MAXK>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
       }
     } else {
       // re-evaluation over the forward's share of candidates (orders 0-1,
@@ -229,11 +229,11 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(4, 8
         const int c0 = part == 0 ? 0 : n1, c1 = part == 0 ? n1 : A.n_cand;
         for (int c = c0 + wave; c < c1; c += NW) {
           const Cand cd = decode_candidate(c, A.n_panels);
-          const float v = candidate_power3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, nullptr, A.cut * (rs - rc));
+          const float v = candidate_power3<MODE, MAXK>(S, cd, tx, ty, tz, rx, ry, rz, live, nullptr, A.cut * (rs - rc));
           kahan_add(rs, rc, v);
           const float Wl = g * v;
           if (ballot(Wl != 0.0f) == 0) continue;
-          candidate_adjoint3<MODE>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
+          candidate_adjoint3<MODE, MAXK>(S, cd, tx, ty, tz, rx, ry, rz, live, Wl, acc, lane, G);
         }
       }
     }
@@ -336,8 +336,14 @@ hipError_t launch_prep_panels(const float* panels, int n, float cull_c, PanelRec
 template <int NW, int MODE>
 static hipError_t fwd3_nw(const Trace3Args& A, int n_tiles, float* power, float* seed, float* loss_part,
                           int loss_kind, float log_eps, hipStream_t st) {
-  hipLaunchKernelGGL((k_forward3<NW, MODE>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part, loss_kind,
-                     log_eps);
+  // scenes up to order 2 run a kernel without the order-3 path code (fewer
+  // register spills, so less scratch traffic)
+  if (A.max_order <= 2)
+    hipLaunchKernelGGL((k_forward3<NW, MODE, 2>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
+                       loss_kind, log_eps);
+  else
+    hipLaunchKernelGGL((k_forward3<NW, MODE, 3>), dim3(n_tiles), dim3(NW * kWave), 0, st, A, power, seed, loss_part,
+                       loss_kind, log_eps);
   return hipGetLastError();
 }
 
@@ -363,8 +369,13 @@ size_t backward3_lds_bytes(int nw, int n_panels) {
 template <int NW, int MODE>
 static hipError_t bwd3_nw(const Trace3Args& A, int n_tiles, const float* gP, float* part, float* grad_rx, int reuse,
                           hipStream_t st) {
-  hipLaunchKernelGGL((k_backward3<NW, MODE>), dim3(n_tiles), dim3(NW * kWave), backward3_lds_bytes(NW, A.n_panels), st, A,
-                     gP, part, grad_rx, reuse);
+  const size_t lds = backward3_lds_bytes(NW, A.n_panels);
+  if (A.max_order <= 2)
+    hipLaunchKernelGGL((k_backward3<NW, MODE, 2>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, gP, part, grad_rx,
+                       reuse);
+  else
+    hipLaunchKernelGGL((k_backward3<NW, MODE, 3>), dim3(n_tiles), dim3(NW * kWave), lds, st, A, gP, part, grad_rx,
+                       reuse);
   return hipGetLastError();
 }
 
