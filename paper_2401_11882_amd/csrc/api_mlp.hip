@@ -94,11 +94,17 @@ drt::FusedArgs fused_args(drt_mlp* h, long long n) {
   return a;
 }
 
+// Adam arguments of a training step at learning rate lr (torch defaults
+// for the rest).
+drt::AdamArgs adam_args(drt_mlp* h, float lr) {
+  return drt::AdamArgs{h->p, h->m, h->v, h->step, lr, 0.9f, 0.999f, 1e-8f, h->wbf, h->wtbf};
+}
+
 // Forward + MSE + backward on rows [0, n) of v/y; gradients into h->g, loss
-// (mean squared error over n) into loss_dev; with `count_step`, the Adam step
-// count is advanced for the update that follows.
+// (mean squared error over n) into loss_dev; with adam.p set, the Adam step
+// count is advanced and every parameter updated as its gradient is formed.
 int enqueue_grads(drt_mlp* h, const float* v, const float* y, const int32_t* rows, int n, float* loss_dev,
-                  bool count_step, hipStream_t st) {
+                  const drt::AdamArgs& adam, hipStream_t st) {
   const drt::MlpLayout& L = h->L;
   const int W = drt::kMlpWidth;
   const long long ldt = h->max_batch;
@@ -122,10 +128,11 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, const int32_t* row
   ta.dzt_stride = ldt * W;
   ta.hw_part = h->hw_part;
   ta.hs_part = h->hs_part;
+  ta.step = adam.p ? h->step : nullptr;
   HIPCHK(drt::launch_mlp_train(ta, st), "training pass");
   // weight and bias gradients of every hidden layer: slices of at least
   // kSliceRows rows, at most max_slices of them; then every sum, the head's
-  // and the loss included
+  // and the loss included, each followed by its parameter's update
   constexpr int kSliceRows = 512;
   drt::DwArgs dw{};
   dw.X0T = h->X0T;
@@ -139,9 +146,8 @@ int enqueue_grads(drt_mlp* h, const float* v, const float* y, const int32_t* row
   dw.L = L;
   dw.part = h->dw_part;
   dw.part_b = h->db_part;
-  drt::HeadFold hf{h->hw_part, h->hs_part, n / drt::mlp_train_rows(), 1.0 / (double)n, loss_dev,
-                  count_step ? h->step : nullptr};
-  HIPCHK(drt::launch_mlp_dw(dw, h->g, hf, st), "weight gradients");
+  drt::HeadFold hf{h->hw_part, h->hs_part, n / drt::mlp_train_rows(), 1.0 / (double)n, loss_dev};
+  HIPCHK(drt::launch_mlp_dw(dw, h->g, hf, adam, st), "weight gradients");
   return DRT_OK;
 }
 
@@ -244,7 +250,7 @@ int drt_mlp_grads(drt_mlp* mlp, const float* v_dev, const float* y_dev, int64_t 
   if (rc) return rc;
   if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, nullptr, (int)n, loss_dev, false, st))) return rc;
+  if ((rc = enqueue_grads(mlp, v_dev, y_dev, nullptr, (int)n, loss_dev, drt::AdamArgs{}, st))) return rc;
   if (grads_dev) HIPCHK(hipMemcpyAsync(grads_dev, mlp->g, (size_t)mlp->L.n_params * 4, hipMemcpyDeviceToDevice, st),
                         "grad copy");
   return DRT_OK;
@@ -257,11 +263,7 @@ int drt_mlp_train_step(drt_mlp* mlp, const float* v_dev, const float* y_dev, int
   if (!v_dev || !y_dev) return failf(DRT_EINVAL, "v_dev / y_dev is NULL");
   if (!(lr > 0.0f) || !std::isfinite(lr)) return failf(DRT_EINVAL, "lr must be finite and > 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, nullptr, (int)n, loss_dev, true, st))) return rc;
-  HIPCHK(drt::launch_adam_mlp(mlp->p, mlp->g, mlp->m, mlp->v, mlp->step, mlp->L.n_params, lr, 0.9f, 0.999f, 1e-8f,
-                              mlp->L, mlp->wbf, mlp->wtbf, st),
-         "adam");
-  return DRT_OK;
+  return enqueue_grads(mlp, v_dev, y_dev, nullptr, (int)n, loss_dev, adam_args(mlp, lr), st);
 }
 
 int drt_mlp_train_step_rows(drt_mlp* mlp, const float* v_dev, const float* y_dev, const int32_t* rows_dev,
@@ -271,11 +273,7 @@ int drt_mlp_train_step_rows(drt_mlp* mlp, const float* v_dev, const float* y_dev
   if (!v_dev || !y_dev || !rows_dev) return failf(DRT_EINVAL, "v_dev / y_dev / rows_dev is NULL");
   if (!(lr > 0.0f) || !std::isfinite(lr)) return failf(DRT_EINVAL, "lr must be finite and > 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = enqueue_grads(mlp, v_dev, y_dev, rows_dev, (int)n, loss_dev, true, st))) return rc;
-  HIPCHK(drt::launch_adam_mlp(mlp->p, mlp->g, mlp->m, mlp->v, mlp->step, mlp->L.n_params, lr, 0.9f, 0.999f, 1e-8f,
-                              mlp->L, mlp->wbf, mlp->wtbf, st),
-         "adam");
-  return DRT_OK;
+  return enqueue_grads(mlp, v_dev, y_dev, rows_dev, (int)n, loss_dev, adam_args(mlp, lr), st);
 }
 
 int drt_mlp_forward(drt_mlp* mlp, const float* v_dev, int64_t n, float* yhat_dev, void* stream) {

@@ -72,6 +72,7 @@ struct TrainArgs {
   float* hw_part;
   float* hs_part;
   float* yhat;
+  int* step;  // not NULL: step[0] += 1, the Adam step count of the update that follows
 };
 
 hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st);
@@ -80,15 +81,26 @@ int mlp_train_rows();
 
 // The head's part of the gradient sums: g[head_w + i] = sum_t hw_part[t][i],
 // g[head_b] = sum_t hs_part[t][0], loss[0] = inv_n sum_t hs_part[t][1]
-// (fixed order; hw_part NULL: nothing; loss NULL: no loss); step[0] += 1
-// if step is not NULL (the Adam step count of a training step).
+// (fixed order; hw_part NULL: nothing; loss NULL: no loss).
 struct HeadFold {
   const float* hw_part;
   const float* hs_part;
   int tiles;
   double inv_n;
   float* loss;
-  int* step;
+};
+
+// Adam (torch semantics) applied to each gradient element as its sum is
+// formed, at step t = step[0] (counted up by the training pass), with the
+// BF16 copies of W and W^T (fragment order) rewritten.  p NULL: no update.
+struct AdamArgs {
+  float* p;
+  float* m;
+  float* v;
+  const int* step;
+  float lr, b1, b2, eps;
+  __bf16* wbf;
+  __bf16* wtbf;
 };
 
 // Weight and bias gradients of the hidden layers from the transposed
@@ -96,7 +108,8 @@ struct HeadFold {
 // as written by the training pass):
 // partials over slices of slice_rows rows (weights into part, biases -- the
 // row sums of dZ_l^T -- into part_b), then the in-order slice sums into g
-// (W_l at w_off_l, b_l at b_off_l), and the head's sums (HeadFold).  n and
+// (W_l at w_off_l, b_l at b_off_l), the head's sums (HeadFold), and with
+// adam.p set the parameter update of every element (AdamArgs).  n and
 // slice_rows are multiples of 32, n_slices = ceil(n / slice_rows).
 struct DwArgs {
   const __bf16* X0T;
@@ -112,11 +125,8 @@ struct DwArgs {
   float* part_b;  // [5][n_slices][256]
 };
 
-hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, hipStream_t st);
+hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, const AdamArgs& adam, hipStream_t st);
 hipError_t launch_segment_mean(const float* yhat, int T, int R, float* F, hipStream_t st);
-// Adam at step t = step[0] (already counted up for this step).
-hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, const int* step, int n, float lr, float b1,
-                           float b2, float eps, const MlpLayout& L, __bf16* wbf, __bf16* wtbf, hipStream_t st);
 hipError_t launch_mlp_copies(const float* p, int n, const MlpLayout& L, __bf16* wbf, __bf16* wtbf,
                              hipStream_t st);
 hipError_t launch_log_eps(const float* P, long long n, float eps, float* y, hipStream_t st);

@@ -298,6 +298,8 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_train(TrainArgs a) 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const long long tile0 = (long long)blockIdx.x * ROWS;
+  // the step count of the update this pass feeds (read by a later launch only)
+  if (a.step && blockIdx.x == 0 && tid == 0) a.step[0] += 1;
 
   // head parameters and this wavefront's targets now, so their loads are
   // long done when the head runs (lane i < 16: row 16 wave + i)
@@ -601,17 +603,33 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_dw(DwArgs a) {
   }
 }
 
+// One element of Adam (torch semantics) at step t with gradient gi: updates
+// p[i], m[i], v[i] and returns the new p[i].
+__device__ __forceinline__ float adam_elem(const AdamArgs& ad, int t, int i, float gi) {
+  const float mi = ad.b1 * ad.m[i] + (1.0f - ad.b1) * gi;
+  const float vi = ad.b2 * ad.v[i] + (1.0f - ad.b2) * gi * gi;
+  ad.m[i] = mi;
+  ad.v[i] = vi;
+  const float bc1 = 1.0f - powf(ad.b1, (float)t);
+  const float bc2 = 1.0f - powf(ad.b2, (float)t);
+  const float pi = ad.p[i] - (ad.lr / bc1) * (mi / (sqrtf(vi) / sqrtf(bc2) + ad.eps));
+  ad.p[i] = pi;
+  return pi;
+}
+
 // Weight and bias gradients from the partials, slices in order:
-// g[w_off_l + i 256 + o] = sum_s part[l][s][i][o], g[b_off_l + o] = sum_s part_b[l][s][o].
+// g[w_off_l + i 256 + o] = sum_s part[l][s][i][o], g[b_off_l + o] = sum_s part_b[l][s][o];
+// with ad.p set, each element's Adam update follows its sum at once (and
+// for hidden-layer weights the two BF16 copies).
 __global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __restrict__ part_b, int n_slices,
-                             MlpLayout L, float* __restrict__ g, HeadFold hf) {
+                             MlpLayout L, float* __restrict__ g, HeadFold hf, AdamArgs ad) {
   const int l = blockIdx.y;
   if (l == kMlpHidden) {
     // the head (blocks 0..8 of the last row; fixed order throughout):
     // block b < 8: g[head_w + i], i = 32 b .. 32 b + 31, thread (i, z)
     // adding tiles z, z + 8, ... with eight loads in flight, then the eight
     // z in order; block 8: g[head_b] and the loss from the per-tile sums in
-    // FP64 (strided per thread, then a tree), and the Adam step count.
+    // FP64 (strided per thread, then a tree).
     __shared__ double dsh[256];
     if (!hf.hw_part || blockIdx.x > 8) return;
     const int tid = threadIdx.x;
@@ -635,6 +653,7 @@ __global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __rest
 #pragma unroll
         for (int k = 0; k < 8; ++k) u += sh[32 * k + (tid & 31)];
         g[L.head_w + i] = u;
+        if (ad.p) (void)adam_elem(ad, ad.step[0], L.head_w + i, u);
       }
       return;
     }
@@ -648,12 +667,16 @@ __global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __rest
         __syncthreads();
       }
       if (tid == 0) {
-        if (c == 0) g[L.head_b] = (float)dsh[0];
-        else if (hf.loss) hf.loss[0] = (float)(dsh[0] * hf.inv_n);
+        if (c == 0) {
+          const float gb = (float)dsh[0];
+          g[L.head_b] = gb;
+          if (ad.p) (void)adam_elem(ad, ad.step[0], L.head_b, gb);
+        } else if (hf.loss) {
+          hf.loss[0] = (float)(dsh[0] * hf.inv_n);
+        }
       }
       __syncthreads();
     }
-    if (tid == 0 && hf.step) hf.step[0] += 1;
     return;
   }
   const int e = blockIdx.x * blockDim.x + threadIdx.x;  // i 256 + o within layer l, then the 256 biases
@@ -663,11 +686,18 @@ __global__ void k_mlp_dw_sum(const float* __restrict__ part, const float* __rest
     float s = 0.0f;
     for (int z = 0; z < n_slices; ++z) s += p[(size_t)z * 256 * 256];
     g[L.w_off[l] + e] = s;
+    if (ad.p) {
+      const float pi = adam_elem(ad, ad.step[0], L.w_off[l] + e, s);
+      const int r = e >> 8, c = e & 255;  // W[r][c]: input r, output c
+      ad.wbf[L.bf_off[l] + frag_off(r, c, 256)] = (bf16)pi;         // W: rows = inputs, k = outputs
+      ad.wtbf[L.bf_off[l] + frag_off(c, r, L.fan_in[l])] = (bf16)pi;  // W^T: rows = outputs, k = inputs
+    }
   } else if (e < nw + 256) {
     const float* p = part_b + (size_t)l * n_slices * 256 + (e - nw);
     float s = 0.0f;
     for (int z = 0; z < n_slices; ++z) s += p[(size_t)z * 256];
     g[L.b_off[l] + e - nw] = s;
+    if (ad.p) (void)adam_elem(ad, ad.step[0], L.b_off[l] + e - nw, s);
   }
 }
 
@@ -684,41 +714,6 @@ __global__ void k_segment_mean(const float* __restrict__ yhat, int R, float* __r
     __syncthreads();
   }
   if (threadIdx.x == 0) F[blockIdx.x] = (float)(sh[0] / R);
-}
-
-// One element of Adam (torch semantics) at step t, and its BF16 copies.
-__device__ __forceinline__ void adam_elem(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
-                                          float* __restrict__ v, int t, int i, int n, float lr, float b1, float b2,
-                                          float eps, const MlpLayout& L, bf16* __restrict__ wbf,
-                                          bf16* __restrict__ wtbf) {
-  if (i >= n) return;
-  const float gi = gr[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float bc1 = 1.0f - powf(b1, (float)t);
-  const float bc2 = 1.0f - powf(b2, (float)t);
-  const float pi = p[i] - (lr / bc1) * (mi / (sqrtf(vi) / sqrtf(bc2) + eps));
-  p[i] = pi;
-#pragma unroll
-  for (int l = 0; l < kMlpHidden; ++l) {
-    const int off = L.w_off[l], fi = L.fan_in[l];
-    if (i >= off && i < off + fi * 256) {
-      const int r = (i - off) / 256, c = (i - off) % 256;
-      wbf[L.bf_off[l] + frag_off(r, c, 256)] = (bf16)pi;  // W: rows = inputs, k = outputs
-      wtbf[L.bf_off[l] + frag_off(c, r, fi)] = (bf16)pi;  // W^T: rows = outputs, k = inputs
-    }
-  }
-}
-
-// Adam on the flat FP32 parameters (torch semantics) at step t = step[0]
-// (counted up by the gradient sums of the same training step), then BF16
-// copies of W and W^T (fragment order) of the hidden layers.
-__global__ void k_adam_mlp(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
-                           float* __restrict__ v, const int* __restrict__ step, int n, float lr, float b1,
-                           float b2, float eps, MlpLayout L, bf16* __restrict__ wbf, bf16* __restrict__ wtbf) {
-  adam_elem(p, gr, m, v, step[0], blockIdx.x * blockDim.x + threadIdx.x, n, lr, b1, b2, eps, L, wbf, wtbf);
 }
 
 // Same bf16 copies without an update (after loading parameters).
@@ -778,7 +773,7 @@ hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st) {
 
 int mlp_train_rows() { return kTrainRows; }
 
-hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, hipStream_t st) {
+hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, const AdamArgs& adam, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   if (a.n % kTB != 0 || a.slice_rows % kTB != 0) return hipErrorInvalidValue;
   // items: layer 0 (one block of 128 inputs) + layers 1..4 (two blocks each)
@@ -787,19 +782,12 @@ hipError_t launch_mlp_dw(const DwArgs& a, float* g, const HeadFold& hf, hipStrea
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mlp_dw_sum, dim3(257, kMlpHidden + 1), dim3(256), 0, st, a.part, a.part_b, a.n_slices, a.L, g,
-                     hf);
+                     hf, adam);
   return hipGetLastError();
 }
 
 hipError_t launch_segment_mean(const float* yhat, int T, int R, float* F, hipStream_t st) {
   hipLaunchKernelGGL(k_segment_mean, dim3(T), dim3(256), 0, st, yhat, R, F);
-  return hipGetLastError();
-}
-
-hipError_t launch_adam_mlp(float* p, const float* gr, float* m, float* v, const int* step, int n, float lr, float b1,
-                           float b2, float eps, const MlpLayout& L, bf16* wbf, bf16* wtbf, hipStream_t st) {
-  hipLaunchKernelGGL(k_adam_mlp, dim3((n + 255) / 256), dim3(256), 0, st, p, gr, m, v, step, n, lr, b1, b2, eps, L,
-                     wbf, wtbf);
   return hipGetLastError();
 }
 
