@@ -34,6 +34,7 @@ UNPACKED_FP32_TFLOPS = 78.6     # the same without packed FP32: 256 CU x 64 lane
 TRACER_SOURCES = ("dev.h", "path.h", "screen.h", "trace.h", "trace.hip", "view.h")
 TRACER3D_SOURCES = ("dev.h", "path3d.h", "screen3.h", "trace3d.h", "trace3d.hip")
 BATCHED_SOURCES = ("dev.h", "path.h", "screen.h", "batched.h", "batched.hip")
+FERMAT_SOURCES = ("dev.h", "path.h", "trace.h", "view.h", "fermat.h", "fermat.hip")
 
 
 def source_hash(names=TRACER_SOURCES) -> str:
@@ -332,6 +333,9 @@ def extra_fermat(dev, steps: int = 5):
     Pi, _, _ = tr.forward(sc)
     r = (Pf.double() - Pi.double()).abs() / Pi.double()
     out["power_rel_diff_to_image_method"] = {"median": float(r.median()), "frac_below_1e-5": float((r < 1e-5).double().mean())}
+    out["roofline"] = alu_roofline("fermat_scene64", "k_forward_fermat", out["fermat"]["ms"], sources=FERMAT_SOURCES,
+                                   time_basis="HIP events around the whole Fermat forward call (k_forward_fermat "
+                                              "and its small setup and loss kernels), averaged over the calls")
     return out
 
 
