@@ -75,18 +75,21 @@ def test_gradients_match_reference():
 
 
 def test_train_step_is_adam_on_the_gradients():
+    """Three consecutive steps, each against torch's Adam given the library's
+    gradients at the current parameters (the bias corrections use the device
+    step count, which the training pass advances)."""
     S, net = _net()
     v, y = _inputs(1024, seed=2)
     vd, yd = torch.tensor(v).cuda(), torch.tensor(y).cuda()
-    p0 = net.params().astype(np.float64)
-    g, _ = net.grads(vd, yd)
-    net.train_step(vd, yd, 1e-3)
-    p1 = net.params().astype(np.float64)
-    pt = torch.tensor(p0, requires_grad=True)
+    pt = torch.tensor(net.params().astype(np.float64), requires_grad=True)
     opt = torch.optim.Adam([pt], lr=1e-3)
-    pt.grad = torch.tensor(g.cpu().numpy().astype(np.float64))
-    opt.step()
-    np.testing.assert_allclose(p1, pt.detach().numpy(), rtol=1e-5, atol=1e-7)
+    for step in range(3):
+        g, _ = net.grads(vd, yd)
+        net.train_step(vd, yd, 1e-3)
+        pt.grad = torch.tensor(g.cpu().numpy().astype(np.float64))
+        opt.step()
+        np.testing.assert_allclose(net.params().astype(np.float64), pt.detach().numpy(), rtol=1e-5, atol=1e-7,
+                                   err_msg=f"after step {step + 1}")
     net.close()
 
 
