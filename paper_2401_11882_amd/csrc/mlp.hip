@@ -130,7 +130,11 @@ __device__ __forceinline__ void tile_features(bf16* act, float (*xin)[4], float 
     float sn = 0.0f, cs = 0.0f;
     if (tile0 + r < n) {
       const float tt = bfs[f][0] * xin[r][0] + bfs[f][1] * xin[r][1] + bfs[f][2] * xin[r][2] + bfs[f][3] * xin[r][3];
-      sincospif(2.0f * tt, &sn, &cs);
+      // sin / cos of 2 pi tt by the hardware's revolution-scaled sine and
+      // cosine on the fractional part (exact), as BF16 features
+      const float fr = __builtin_amdgcn_fractf(tt);
+      sn = __builtin_amdgcn_sinf(fr);
+      cs = __builtin_amdgcn_cosf(fr);
     }
     act[r * ALD + f] = (bf16)sn;
     act[r * ALD + 64 + f] = (bf16)cs;
