@@ -174,11 +174,16 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
     const bf16* Wt = a.wt + a.L.bf_off[l];  // [256][K]
     const float* bias = a.p + a.L.b_off[l];
     const int nks = K / 32;
+    // the accumulators start at the bias of their 4 columns (weights as the
+    // first MFMA operand: a lane holds 4 consecutive output columns of one row)
     floatx4 acc[kRT][4];
 #pragma unroll
-    for (int i = 0; i < kRT; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + 16 * j + 4 * (lane >> 4);
+      const floatx4 b = (floatx4){bias[col], bias[col + 1], bias[col + 2], bias[col + 3]};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = (floatx4){0.0f, 0.0f, 0.0f, 0.0f};
+      for (int i = 0; i < kRT; ++i) acc[i][j] = b;
+    }
     // weight fragments of k-step 0; then each step loads the next one's
     bf16x8 bw[4];
 #pragma unroll
@@ -201,19 +206,15 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
       for (int j = 0; j < 4; ++j) bw[j] = bn[j];
     }
     __syncthreads();  // every wavefront is past its last read of this layer's inputs
-    // (weights as the first MFMA operand: a lane holds 4 consecutive output
-    // columns of one row, written to the activations as 8 bytes)
+    // ReLU, BF16, 4 columns of one row per lane written as 8 bytes
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int col = c0 + 16 * j + 4 * (lane >> 4);
-      float b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = bias[col + q];
 #pragma unroll
       for (int i = 0; i < kRT; ++i) {
         bf16x4 v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (bf16)fmaxf(acc[i][j][q] + b[q], 0.0f);
+        for (int q = 0; q < 4; ++q) v[q] = (bf16)fmaxf(acc[i][j][q], 0.0f);
         *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
       }
     }
