@@ -184,26 +184,33 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
 #pragma unroll
       for (int i = 0; i < kRT; ++i) acc[i][j] = b;
     }
-    // weight fragments of k-step 0; then each step loads the next one's
-    bf16x8 bw[4];
+    // weight fragments in two register sets, named apart (the loop body is
+    // written out twice): the next k-step's fragments load into one while the
+    // multiplications use the other.  nks (4 or 8) is even; the last request
+    // is clamped to the last step, so the wait counts stay static.
+    // (a scheduling barrier after each request keeps the compiler from
+    // sinking it to just before its use)
+    auto wload = [&](bf16x8 (&w)[4], int k) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      bw[j] = *reinterpret_cast<const bf16x8*>(frag_ptr(Wt, K, wave, 0, j, lane));
-#pragma unroll 1
-    for (int ks = 0; ks < nks; ++ks) {
-      bf16x8 bn[4];
-      const int kn = ks + 1 < nks ? ks + 1 : ks;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bn[j] = *reinterpret_cast<const bf16x8*>(frag_ptr(Wt, K, wave, kn, j, lane));
+      for (int j = 0; j < 4; ++j) w[j] = *reinterpret_cast<const bf16x8*>(frag_ptr(Wt, K, wave, k, j, lane));
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto wmul = [&](const bf16x8 (&w)[4], int k) {
 #pragma unroll
       for (int i = 0; i < kRT; ++i) {
-        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + ks * 32 + kq]);
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + k * 32 + kq]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[j], af, acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], af, acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bw[j] = bn[j];
+    };
+    bf16x8 wa[4], wb[4];
+    wload(wa, 0);
+#pragma unroll 1
+    for (int ks = 0; ks < nks; ks += 2) {
+      wload(wb, ks + 1);
+      wmul(wa, ks);
+      wload(wa, ks + 2 < nks ? ks + 2 : ks + 1);
+      wmul(wb, ks + 1);
     }
     __syncthreads();  // every wavefront is past its last read of this layer's inputs
     // ReLU, BF16, 4 columns of one row per lane written as 8 bytes
