@@ -280,13 +280,16 @@ struct WSlice {
 };
 
 // Rows c0 .. c0 + 63 of M [256][K] (K = 128 or 256, fragment order), this
-// lane's operands of every k-step.
-__device__ __forceinline__ void load_wslice(WSlice& s, const bf16* M, int K, int c0, int lane) {
+// lane's operands of every k-step.  K is a compile-time constant, so the
+// requests are issued back to back with no branch between them (a branch
+// per k-step made the compiler wait for each group before the next).
+template <int K>
+__device__ __forceinline__ void load_wslice(WSlice& s, const bf16* M, int c0, int lane) {
+  static_assert(K == kMlpIn || K == kMlpWidth, "fan-in");
 #pragma unroll
-  for (int ks = 0; ks < 8; ++ks)
+  for (int ks = 0; ks < K / 32; ++ks)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (ks * 32 < K) s.f[ks][j] = *reinterpret_cast<const bf16x8*>(frag_ptr(M, K, c0 >> 6, ks, j, lane));
+    for (int j = 0; j < 4; ++j) s.f[ks][j] = *reinterpret_cast<const bf16x8*>(frag_ptr(M, K, c0 >> 6, ks, j, lane));
 }
 
 // Product p of the training pass: the matrix ([256][K], rows = output
@@ -338,9 +341,9 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_train(TrainArgs a) 
   const int c0 = wave * 64;
   WSlice ws;
   {
-    int K;
+    int K;  // product 0 (W_0^T) has the features' fan-in, every other product 256
     const bf16* M = train_matrix(a, 0, K);
-    load_wslice(ws, M, K, c0, lane);
+    load_wslice<kMlpIn>(ws, M, c0, lane);
   }
 #pragma unroll 1
   for (int p = 0; p < 2 * kMlpHidden - 1; ++p) {
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_train(TrainArgs a) 
     if (p + 1 < 2 * kMlpHidden - 1) {
       int Kn;
       const bf16* Mn = train_matrix(a, p + 1, Kn);
-      load_wslice(ws, Mn, Kn, c0, lane);
+      load_wslice<kMlpWidth>(ws, Mn, c0, lane);
     }
     __syncthreads();  // every wavefront is past its last read of this product's input
     if (p < kMlpHidden) {
