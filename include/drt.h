@@ -200,8 +200,8 @@ int drt_forward(const drt_scene* scene, int32_t loss_kind, float log_eps,
    flags: 0, or DRT_BWD_REUSE_FORWARD when the workspace still holds what
    the last drt_forward on this same scene (same device inputs, same
    workspace, nothing changed since) recorded; the adjoint then starts from
-   the recorded contributions.  With any other history the flag gives wrong
-   gradients: pass 0. */
+   the recorded contributions and the wall records the forward prepared.
+   With any other history the flag gives wrong gradients: pass 0. */
 #define DRT_BWD_REUSE_FORWARD 1
 int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t flags,
                  float* grad_tx_dev, float* grad_walls_dev, float* grad_rx_dev,

@@ -406,13 +406,18 @@ int drt_backward(const drt_scene* scene, const float* grad_power_dev, int32_t fl
   if ((rc = check_ws(p, ws_dev, ws_bytes))) return rc;
   const drt::TraceArgs A = make_args(scene, p, ws_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  char* w = static_cast<char*>(ws_dev);
-  hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls, A.cull_c,
-                                        reinterpret_cast<drt::WallRec*>(w + p.off_walls),
-                                        reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
-  if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
-  return enqueue_backward(scene, p, A, grad_power_dev, grad_tx_dev, grad_walls_dev, grad_rx_dev,
-                          (flags & DRT_BWD_REUSE_FORWARD) ? 1 : 0, ws_dev, st);
+  const bool reuse = (flags & DRT_BWD_REUSE_FORWARD) != 0;
+  if (!reuse) {
+    // (with the flag, the wall records and culling boxes the forward wrote
+    // into this workspace are still those of this scene)
+    char* w = static_cast<char*>(ws_dev);
+    hipError_t e = drt::launch_prep_walls(scene->walls_dev, scene->n_walls, A.cull_c,
+                                          reinterpret_cast<drt::WallRec*>(w + p.off_walls),
+                                          reinterpret_cast<drt::WallBox*>(w + p.off_boxes), st);
+    if (e != hipSuccess) return hip_fail(e, "prep_walls launch");
+  }
+  return enqueue_backward(scene, p, A, grad_power_dev, grad_tx_dev, grad_walls_dev, grad_rx_dev, reuse ? 1 : 0,
+                          ws_dev, st);
 }
 
 int drt_forward_backward(const drt_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,

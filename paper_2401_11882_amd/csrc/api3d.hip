@@ -267,9 +267,12 @@ int drt3_backward(const drt3_scene* scene, const float* grad_power_dev, int32_t 
   if ((rc = check_ws3(p, ws_dev, ws_bytes))) return rc;
   const drt::Trace3Args A = make_args3(scene, p, ws_dev);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if ((rc = prep3(scene, p, ws_dev, st))) return rc;
-  return enqueue_backward3(scene, p, A, grad_power_dev, grad_tx_dev, grad_panels_dev, grad_rx_dev,
-                           (flags & DRT_BWD_REUSE_FORWARD) ? 1 : 0, ws_dev, st);
+  const bool reuse = (flags & DRT_BWD_REUSE_FORWARD) != 0;
+  // (with the flag, the panel records the forward wrote into this workspace
+  // are still those of this scene)
+  if (!reuse && (rc = prep3(scene, p, ws_dev, st))) return rc;
+  return enqueue_backward3(scene, p, A, grad_power_dev, grad_tx_dev, grad_panels_dev, grad_rx_dev, reuse ? 1 : 0,
+                           ws_dev, st);
 }
 
 int drt3_forward_backward(const drt3_scene* scene, int32_t loss_kind, float log_eps, float* power_dev,
