@@ -49,7 +49,10 @@ __device__ __forceinline__ int batch_rx_of_lane(int tile, int lane, int nx, int 
   return tile * kWave + lane;
 }
 
-template <int NW, int MODE>
+// MAXK: the highest order of the batch's candidates (2 covers orders 0..2;
+// the code of higher orders is left out, which keeps register pressure at
+// that order's).
+template <int NW, int MODE, int MAXK>
 __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_batched(BatchArgs B) {
   extern __shared__ float smem[];
   __shared__ int item_sh;
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
     // this wavefront's running sum (see k_forward)
     float cut_base = 0.0f, own1 = 0.0f;
     auto visit = [&](int c, const Cand& cd, const float* Ix, const float* Iy, int j) {
-      const float v = candidate_power_img<MODE>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
+      const float v = candidate_power_img<MODE, MAXK>(S, cd, Ix, Iy, txx, txy, rxx, rxy, live, boxes, j,
                                                 cutf * (cut_base + (sum - comp) - own1));
       kahan_add(sum, comp, v);
       if (cache_c && B.loss_kind != 0 && ballot(v != 0.0f) != 0) {
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
         if (ballot(Wl != 0.0f) == 0) continue;
         const Cand cd = decode_candidate(c, W);
         const float* gbox = boxes ? B.cache_box + ((size_t)slot * B.cache_cap + p) * B.box_stride : nullptr;
-        candidate_adjoint_known<MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
+        candidate_adjoint_known<MODE, MAXK>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
       }
     } else {
       // re-evaluation of this wavefront's share as the forward split it, the
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(5, 8
           for (int c = c0; c < c1; ++c) {
             const Cand cd = decode_candidate(c, W);
             kahan_add(rs, rc,
-                      candidate_adjoint<MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, cutf * (rs - rc)));
+                      candidate_adjoint<MODE, MAXK>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, cutf * (rs - rc)));
           }
         }
       }
@@ -262,15 +265,20 @@ size_t batched_lds_bytes(int nw, int max_walls, int max_order) {
          (batched_box_lds(nw, max_walls, max_order) ? sizeof(float) * (size_t)nw * 6 * (max_order + 1) * kWave : 0);
 }
 
+template <int NW, int MAXK>
+static hipError_t batched_nw_k(const BatchArgs& B, int n_blocks, hipStream_t st) {
+  if (B.mode)
+    hipLaunchKernelGGL((k_batched<NW, 1, MAXK>), dim3(n_blocks), dim3(NW * kWave),
+                       batched_lds_bytes(NW, B.max_walls, B.max_order), st, B);
+  else
+    hipLaunchKernelGGL((k_batched<NW, 0, MAXK>), dim3(n_blocks), dim3(NW * kWave),
+                       batched_lds_bytes(NW, B.max_walls, B.max_order), st, B);
+  return hipGetLastError();
+}
+
 template <int NW>
 static hipError_t batched_nw(const BatchArgs& B, int n_blocks, hipStream_t st) {
-  if (B.mode)
-    hipLaunchKernelGGL((k_batched<NW, 1>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls, B.max_order),
-                       st, B);
-  else
-    hipLaunchKernelGGL((k_batched<NW, 0>), dim3(n_blocks), dim3(NW * kWave), batched_lds_bytes(NW, B.max_walls, B.max_order),
-                       st, B);
-  return hipGetLastError();
+  return B.max_order <= 2 ? batched_nw_k<NW, 2>(B, n_blocks, st) : batched_nw_k<NW, 3>(B, n_blocks, st);
 }
 
 hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float* walls_raw, const float* alpha,
@@ -296,18 +304,24 @@ hipError_t launch_batched(const BatchArgs& B, int nw, int n_blocks, const float*
 
 // Resident workgroups per CU for a launch shape (the smaller of the two
 // smoothing modes, so the persistent grid fits either).
+template <int MAXK>
+static void batched_fns(int nw, const void* (&fns)[2]) {
+  if (nw == 4) {
+    fns[0] = reinterpret_cast<const void*>(k_batched<4, 0, MAXK>);
+    fns[1] = reinterpret_cast<const void*>(k_batched<4, 1, MAXK>);
+  } else if (nw == 8) {
+    fns[0] = reinterpret_cast<const void*>(k_batched<8, 0, MAXK>);
+    fns[1] = reinterpret_cast<const void*>(k_batched<8, 1, MAXK>);
+  } else {
+    fns[0] = reinterpret_cast<const void*>(k_batched<16, 0, MAXK>);
+    fns[1] = reinterpret_cast<const void*>(k_batched<16, 1, MAXK>);
+  }
+}
+
 int batched_max_blocks_per_cu(int nw, int max_walls, int max_order) {
   const void* fns[2];
-  if (nw == 4) {
-    fns[0] = reinterpret_cast<const void*>(k_batched<4, 0>);
-    fns[1] = reinterpret_cast<const void*>(k_batched<4, 1>);
-  } else if (nw == 8) {
-    fns[0] = reinterpret_cast<const void*>(k_batched<8, 0>);
-    fns[1] = reinterpret_cast<const void*>(k_batched<8, 1>);
-  } else {
-    fns[0] = reinterpret_cast<const void*>(k_batched<16, 0>);
-    fns[1] = reinterpret_cast<const void*>(k_batched<16, 1>);
-  }
+  if (max_order <= 2) batched_fns<2>(nw, fns);
+  else batched_fns<3>(nw, fns);
   int best = 1 << 30;
   for (const void* fn : fns) {
     int nb = 0;

@@ -745,28 +745,36 @@ __device__ __forceinline__ float candidate_power_img(const SceneView& S, const C
   }
 }
 
-template <int MODE>
+// MAXK as in candidate_power_img: the highest order the caller's candidates
+// can have.
+template <int MODE, int MAXK = 3>
 __device__ __forceinline__ float candidate_adjoint(const SceneView& S, const Cand& cd, float txx, float txy,
                                                    float rxx, float rxy, bool live, float g, float* acc,
                                                    int lane, LaneGrad& G, float scut) {
+  static_assert(MAXK >= 2 && MAXK <= 3, "orders 2..3");
   switch (cd.k) {
     case 0: return path_adjoint<0, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
     case 1: return path_adjoint<1, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
     case 2: return path_adjoint<2, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
-    default: return path_adjoint<3, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
+    default:
+      if constexpr (MAXK >= 3) return path_adjoint<3, MODE>(S, cd, txx, txy, rxx, rxy, live, g, acc, lane, G, scut);
+      else return 0.0f;
   }
 }
 
-template <int MODE>
+template <int MODE, int MAXK = 3>
 __device__ __forceinline__ void candidate_adjoint_known(const SceneView& S, const Cand& cd, float txx,
                                                         float txy, float rxx, float rxy, bool live,
                                                         float Wl, float* acc, int lane, LaneGrad& G,
                                                         const float* gbox = nullptr) {
+  static_assert(MAXK >= 2 && MAXK <= 3, "orders 2..3");
   switch (cd.k) {
     case 0: path_adjoint_known<0, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
     case 1: path_adjoint_known<1, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
     case 2: path_adjoint_known<2, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
-    default: path_adjoint_known<3, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox); break;
+    default:
+      if constexpr (MAXK >= 3) path_adjoint_known<3, MODE>(S, cd, txx, txy, rxx, rxy, live, Wl, acc, lane, G, gbox);
+      break;
   }
 }
 
