@@ -127,6 +127,19 @@ class _Sc:  # minimal scene record for BatchPlan
         self.walls, self.tx, self.rx, self.alpha, self.grid_n = walls, tx, rx, alpha, 0
 
 
+def z_order(p: np.ndarray, bits: int = 16) -> np.ndarray:
+    """Morton code of points in [0,1]^2 (last axis x, y), `bits` bits per axis."""
+    q = np.clip((p * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+
+    def spread(u):
+        u = (u | (u << 8)) & 0x00FF00FF
+        u = (u | (u << 4)) & 0x0F0F0F0F
+        u = (u | (u << 2)) & 0x33333333
+        return (u | (u << 1)) & 0x55555555
+
+    return spread(q[..., 0]) | (spread(q[..., 1]) << 1)
+
+
 def generate_data(walls: np.ndarray, n_tx: int, n_rx: int, alpha: float, max_order: int, seed: int = 0,
                   eps: float = 1e-6):
     """(v [n_tx*n_rx, 4], y [n_tx*n_rx]) on the device: tx ~ U[0,1]^2 and, per tx,
@@ -134,12 +147,20 @@ def generate_data(walls: np.ndarray, n_tx: int, n_rx: int, alpha: float, max_ord
     rng = WL.rng_for(5, 4000 + seed)
     txs = rng.uniform(0.0, 1.0, (n_tx, 2)).astype(np.float32)
     rxs = rng.uniform(0.0, 1.0, (n_tx, n_rx, 2)).astype(np.float32)
-    scenes = [_Sc(walls, txs[i], rxs[i], alpha) for i in range(n_tx)]
+    # each transmitter's receivers traced in Z-order, so that a tile of
+    # consecutive receivers is a compact patch the candidate screen can prune;
+    # the powers go back to the drawn order
+    order = np.argsort(z_order(rxs), axis=1, kind="stable")
+    rxs_sorted = np.take_along_axis(rxs, order[..., None], axis=1)
+    scenes = [_Sc(walls, txs[i], rxs_sorted[i], alpha) for i in range(n_tx)]
     plan = B.BatchPlan(scenes, max_order)
-    P = plan.run(loss="none")[0]
+    P_sorted = plan.run(loss="none")[0]
+    dst = torch.tensor((order + n_rx * np.arange(n_tx)[:, None]).ravel(), device=plan.device, dtype=torch.long)
+    P = torch.empty_like(P_sorted)
+    P[dst] = P_sorted
     y = log_targets(P, eps)
     v = torch.cat([torch.tensor(np.repeat(txs, n_rx, axis=0), device=plan.device),
-                   plan.rx], dim=1).contiguous()
+                   torch.tensor(rxs.reshape(-1, 2), device=plan.device)], dim=1).contiguous()
     torch.cuda.synchronize()
     plan.close()
     return v, y, txs
