@@ -127,9 +127,9 @@ class _Sc:  # minimal scene record for BatchPlan
         self.walls, self.tx, self.rx, self.alpha, self.grid_n = walls, tx, rx, alpha, 0
 
 
-def z_order(p: np.ndarray, bits: int = 16) -> np.ndarray:
-    """Morton code of points in [0,1]^2 (last axis x, y), `bits` bits per axis."""
-    q = np.clip((p * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+def z_order_dev(p: torch.Tensor, bits: int = 16) -> torch.Tensor:
+    """Morton codes of points in [0,1]^2 (last axis x, y), `bits` bits per axis."""
+    q = (p * float(1 << bits)).to(torch.int64).clamp_(0, (1 << bits) - 1)
 
     def spread(u):
         u = (u | (u << 8)) & 0x00FF00FF
@@ -150,12 +150,15 @@ def generate_data(walls: np.ndarray, n_tx: int, n_rx: int, alpha: float, max_ord
     # each transmitter's receivers traced in Z-order, so that a tile of
     # consecutive receivers is a compact patch the candidate screen can prune;
     # the powers go back to the drawn order
-    order = np.argsort(z_order(rxs), axis=1, kind="stable")
-    rxs_sorted = np.take_along_axis(rxs, order[..., None], axis=1)
+    # (codes and the stable sort on the device: 0.6 s on the host for 1e7 points)
+    dev = torch.device("cuda")
+    r = torch.tensor(rxs, device=dev)
+    order = torch.argsort(z_order_dev(r), dim=1, stable=True)
+    rxs_sorted = torch.gather(r, 1, order[..., None].expand(-1, -1, 2)).cpu().numpy()
     scenes = [_Sc(walls, txs[i], rxs_sorted[i], alpha) for i in range(n_tx)]
     plan = B.BatchPlan(scenes, max_order)
     P_sorted = plan.run(loss="none")[0]
-    dst = torch.tensor((order + n_rx * np.arange(n_tx)[:, None]).ravel(), device=plan.device, dtype=torch.long)
+    dst = (order + n_rx * torch.arange(n_tx, device=order.device)[:, None]).reshape(-1).to(plan.device)
     P = torch.empty_like(P_sorted)
     P[dst] = P_sorted
     y = log_targets(P, eps)
