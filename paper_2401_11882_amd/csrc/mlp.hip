@@ -51,6 +51,13 @@ __device__ __forceinline__ size_t frag_off(int c, int k, int K) {
          (k & 7);
 }
 
+// ReLU on the bit pattern: a float with its sign bit set (a negative value or
+// -0) becomes +0 and any other is kept, as fmaxf(x, 0) gives for every non-NaN
+// x, in one integer max (fmaxf first quietens its operand: a second instruction)
+__device__ __forceinline__ float relu(float x) {
+  return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
+}
+
 // Workgroup barrier that orders LDS only, so that global loads stay in
 // flight across it (used where no wavefront reads global memory that
 // another wavefront of the workgroup writes in the same launch).
@@ -175,15 +182,16 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
     const float* bias = a.p + a.L.b_off[l];
     const int nks = K / 32;
     // the accumulators start at the bias of their 4 columns (weights as the
-    // first MFMA operand: a lane holds 4 consecutive output columns of one row)
-    floatx4 acc[kRT][4];
+    // first MFMA operand: a lane holds 4 consecutive output columns of one
+    // row): the first step's multiplications take it as their addend, so no
+    // copy of it into the accumulators is made
+    floatx4 bq[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int col = c0 + 16 * j + 4 * (lane >> 4);
-      const floatx4 b = (floatx4){bias[col], bias[col + 1], bias[col + 2], bias[col + 3]};
-#pragma unroll
-      for (int i = 0; i < kRT; ++i) acc[i][j] = b;
+      bq[j] = (floatx4){bias[col], bias[col + 1], bias[col + 2], bias[col + 3]};
     }
+    floatx4 acc[kRT][4];
     // weight fragments in two register sets, named apart (the loop body is
     // written out twice): the next k-step's fragments load into one while the
     // multiplications use the other.  nks (4 or 8) is even; the last request
@@ -203,10 +211,23 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], af, acc[i][j], 0, 0, 0);
       }
     };
+    auto wmul0 = [&](const bf16x8 (&w)[4]) {  // step 0: the bias as the addend
+#pragma unroll
+      for (int i = 0; i < kRT; ++i) {
+        const bf16x8 af = *reinterpret_cast<const bf16x8*>(&act[(16 * i + (lane & 15)) * ALD + kq]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], af, bq[j], 0, 0, 0);
+      }
+    };
     bf16x8 wa[4], wb[4];
     wload(wa, 0);
+    // nks (4 or 8) is even; the first pair of steps is written out
+    wload(wb, 1);
+    wmul0(wa);
+    wload(wa, 2 < nks ? 2 : 1);
+    wmul(wb, 1);
 #pragma unroll 1
-    for (int ks = 0; ks < nks; ks += 2) {
+    for (int ks = 2; ks < nks; ks += 2) {
       wload(wb, ks + 1);
       wmul(wa, ks);
       wload(wa, ks + 2 < nks ? ks + 2 : ks + 1);
@@ -221,7 +242,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
       for (int i = 0; i < kRT; ++i) {
         bf16x4 v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (bf16)fmaxf(acc[i][j][q], 0.0f);
+        for (int q = 0; q < 4; ++q) v[q] = (bf16)relu(acc[i][j][q]);
         *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
       }
     }
@@ -387,7 +408,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_train(TrainArgs a) 
           uint32_t m = 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            v[q] = (bf16)fmaxf(acc[i][j][q] + bq[q], 0.0f);
+            v[q] = (bf16)relu(acc[i][j][q] + bq[q]);
             m |= ((float)v[q] > 0.0f ? 1u : 0u) << q;
           }
           if (p < kMlpHidden - 1) mnib[p][16 * i + (lane & 15)][col / 4] = (uint8_t)m;
