@@ -32,8 +32,9 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 // tiles x 4 column tiles), k in increasing steps of 32, FP32 accumulation.
 // After a layer every wavefront has finished reading its inputs (barrier),
 // and the new activations (bias, ReLU, bf16) overwrite them in place.  The
-// head is a per-row dot product in FP32 (4 columns per lane, then the wave
-// sum), the same as in the training pass.
+// head is a per-row dot product in FP32 over the last layer's registers
+// (4 columns per lane, then a pairwise tree over the 64 column groups), with
+// the same sums in the same order as the training pass's wave sum.
 // ---------------------------------------------------------------------------
 constexpr int kFusedWaves = 4;
 constexpr int kFusedRows = 128;
@@ -56,6 +57,39 @@ __device__ __forceinline__ size_t frag_off(int c, int k, int K) {
 // x, in one integer max (fmaxf first quietens its operand: a second instruction)
 __device__ __forceinline__ float relu(float x) {
   return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
+}
+
+// Two floats rounded to BF16 (nearest even) in one register, x in the low
+// half: the packed conversion the compiler emits for a pair, written out
+// because it does not pair conversions whose result is then bit-cast.
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float x, float y) {
+  uint32_t r;
+  asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
+
+// ReLU of four values rounded to BF16: rounding keeps the sign, so the
+// patterns with the sign bit set (negative values, -0, negative NaN) become
+// +0 by an integer max on each 16-bit half, as rounding relu(x) gives for
+// every x; two packed maxima where the float form takes four.
+__device__ __forceinline__ bf16x4 relu_bf16x4(const floatx4& x) {
+  typedef __attribute__((__vector_size__(2 * sizeof(short)))) short shortx2;
+  const shortx2 lo = __builtin_bit_cast(shortx2, cvt_pk_bf16(x[0], x[1]));
+  const shortx2 hi = __builtin_bit_cast(shortx2, cvt_pk_bf16(x[2], x[3]));
+  const uint2 u = {__builtin_bit_cast(uint32_t, __builtin_elementwise_max(lo, (shortx2){0, 0})),
+                   __builtin_bit_cast(uint32_t, __builtin_elementwise_max(hi, (shortx2){0, 0}))};
+  return __builtin_bit_cast(bf16x4, u);
+}
+
+// x plus x of the lane 16 apart (lanes 0..15 pair with 16..31, 32..47 with
+// 48..63), and x plus x of the lane 32 apart: each lane gets the pair's sum.
+__device__ __forceinline__ float pair_sum16(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum32(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Workgroup barrier that orders LDS only, so that global loads stay in
@@ -157,18 +191,26 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
   const long long tile0 = (long long)blockIdx.x * ROWS;
 
   // head parameters now, so their loads are long done when the head runs
-  const float* hw = a.p + a.L.head_w;
-  float wv[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) wv[q] = hw[lane * 4 + q];
+  static_assert(kFusedWaves * 64 == kMlpWidth, "one head weight per thread");
+  __shared__ __attribute__((aligned(16))) float hws[kMlpWidth];
+  hws[tid] = a.p[a.L.head_w + tid];
   const float hb = a.p[a.L.head_b];
   __shared__ float xin[ROWS][4], bfs[kMlpFreq][4];
   if (a.v) {
     tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) { return a.v[4 * row + e]; });
   } else {
+    // row g pairs transmitter g / R with receiver g % R: the tile's first row
+    // is divided once and its other rows step on from there (R >= 1, so at
+    // most ROWS steps, none where R is a multiple of ROWS)
+    const long long g0 = a.row0 + tile0;
+    const long long q0 = g0 / a.R, r0 = g0 % a.R;
     tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) {
-      const long long g = a.row0 + row;
-      return e < 2 ? a.tx[2 * (g / a.R) + e] : a.rx[2 * (g % a.R) + e - 2];
+      long long q = q0, rr = r0 + (row - tile0);
+      while (rr >= a.R) {
+        rr -= a.R;
+        ++q;
+      }
+      return e < 2 ? a.tx[2 * q + e] : a.rx[2 * rr + e - 2];
     });
   }
   __syncthreads();
@@ -233,40 +275,68 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
       wload(wa, ks + 2 < nks ? ks + 2 : ks + 1);
       wmul(wb, ks + 1);
     }
+    if (l + 1 == kMlpHidden) {
+      // The head's dot product of each row from the registers, summed as one
+      // balanced tree of pairs over the 64 four-column groups (group G holds
+      // columns 4 G .. 4 G + 3, a chain of fused multiply-adds from zero;
+      // here G = 16 wave + 4 j + lane / 16): its lowest level pairs lanes 16
+      // apart, the next lanes 32 apart, the next two this lane's column
+      // tiles j, the last two the wavefronts (below, through LDS).
+      float4 hw4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) hw4[j] = *reinterpret_cast<const float4*>(&hws[c0 + 16 * j + 4 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < kRT; ++i) {
+        float t[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const bf16x4 h = relu_bf16x4(acc[i][j]);
+          float p = 0.0f;
+          p = fmaf((float)h[0], hw4[j].x, p);
+          p = fmaf((float)h[1], hw4[j].y, p);
+          p = fmaf((float)h[2], hw4[j].z, p);
+          p = fmaf((float)h[3], hw4[j].w, p);
+          t[j] = pair_sum32(pair_sum16(p));
+        }
+        if (lane < 16) xin[16 * i + lane][wave] = (t[0] + t[1]) + (t[2] + t[3]);
+      }
+      break;
+    }
     __syncthreads();  // every wavefront is past its last read of this layer's inputs
     // ReLU, BF16, 4 columns of one row per lane written as 8 bytes
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int col = c0 + 16 * j + 4 * (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < kRT; ++i) {
-        bf16x4 v;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (bf16)relu(acc[i][j][q]);
-        *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = v;
-      }
+      for (int i = 0; i < kRT; ++i)
+        *reinterpret_cast<bf16x4*>(&act[(16 * i + (lane & 15)) * ALD + col]) = relu_bf16x4(acc[i][j]);
     }
     __syncthreads();
   }
-  // head: rows of this wavefront, one wave sum per row
-  constexpr int kRowsPerWave = ROWS / kFusedWaves;
-  double wsum = 0.0;  // lane 0: this wavefront's rows, in order
-#pragma unroll 1
-  for (int i = 0; i < kRowsPerWave; ++i) {
-    const int r = wave * kRowsPerWave + i;
-    float part = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) part = fmaf((float)act[r * ALD + lane * 4 + q], wv[q], part);
-    const float yh = wave_sum(part) + hb;
-    if (lane == 0 && tile0 + r < a.n) {
-      if (a.yhat) a.yhat[tile0 + r] = yh;
-      wsum += (double)yh;
-    }
+  // xin[r][w] now holds wavefront w's sum for row r (the inputs were last
+  // read before the first layer): the tree's last two levels and the bias
+  __syncthreads();
+  float* yhs = &bfs[0][0];  // ROWS values (the features' B is no longer read)
+  static_assert(ROWS <= kMlpFreq * 4, "yhat of the tile fits in the features' B");
+  if (tid < ROWS) {
+    const float yh = ((xin[tid][0] + xin[tid][1]) + (xin[tid][2] + xin[tid][3])) + hb;
+    yhs[tid] = yh;
+    if (a.yhat && tile0 + tid < a.n) a.yhat[tile0 + tid] = yh;
   }
   if (a.tile_sum) {
-    // the tile's sum of yhat, wavefronts in order (for per-transmitter means)
+    // the tile's sum of yhat: each wavefront's quarter of the rows in order,
+    // then the wavefronts in order (for per-transmitter means)
+    constexpr int kRowsPerWave = ROWS / kFusedWaves;
     __shared__ double ws[kFusedWaves];
-    if (lane == 0) ws[wave] = wsum;
+    __syncthreads();
+    if (lane == 0) {
+      double wsum = 0.0;
+      for (int i = 0; i < kRowsPerWave; ++i) {
+        const int r = wave * kRowsPerWave + i;
+        if (tile0 + r < a.n) wsum += (double)yhs[r];
+      }
+      ws[wave] = wsum;
+    }
     __syncthreads();
     if (tid == 0) {
       double t = 0.0;

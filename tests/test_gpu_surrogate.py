@@ -112,17 +112,21 @@ def test_train_step_on_row_indices_equals_gathered_rows():
     b.close()
 
 
-def test_scan_is_mean_of_forward():
+@pytest.mark.parametrize("n_rx", [1024, 300, 100, 1])
+def test_scan_is_mean_of_forward(n_rx):
+    # 1024: whole 128-row tiles per transmitter (per-tile sums); 300, 100, 1:
+    # tiles that span 2, 3 or 128 transmitters (per-row outputs, then means)
     S, net = _net(max_batch=8192)
+    rx_np = WL.rx_grid(32)[:n_rx]
     tx = torch.tensor(WL.rx_grid(4)).cuda()          # 16 transmitters
-    rx = torch.tensor(WL.rx_grid(32)).cuda()         # 1024 receivers
+    rx = torch.tensor(rx_np).cuda()
     F = net.scan(tx, rx).cpu().numpy()
     pairs = torch.cat([tx.repeat_interleave(rx.shape[0], 0), rx.repeat(tx.shape[0], 1)], 1).contiguous()
-    yh = net.forward(pairs).cpu().numpy().reshape(16, 1024)
+    yh = net.forward(pairs).cpu().numpy().reshape(16, n_rx)
     np.testing.assert_allclose(F, yh.astype(np.float64).mean(1), rtol=1e-5, atol=1e-6)
     # and against the reference for two transmitters
     for t in (0, 9):
-        v = np.concatenate([np.repeat(WL.rx_grid(4)[t:t + 1], 1024, 0), WL.rx_grid(32)], 1)
+        v = np.concatenate([np.repeat(WL.rx_grid(4)[t:t + 1], n_rx, 0), rx_np], 1)
         yo, _ = M.forward(v, WL.fourier_matrix(0), S.init_params(0), round_bf16=True)
         assert F[t] == pytest.approx(yo.mean(), abs=1e-3 * (1 + abs(yo.mean())))
     net.close()
