@@ -166,19 +166,24 @@ __device__ __forceinline__ void tile_features(bf16* act, float (*xin)[4], float 
   }
   bfs[tid >> 2][tid & 3] = bv;
   __syncthreads();
-  for (int i = tid; i < ROWS * 64; i += kFusedWaves * 64) {
-    const int r = i >> 6, f = i & 63;
-    float sn = 0.0f, cs = 0.0f;
-    if (tile0 + r < n) {
-      const float tt = bfs[f][0] * xin[r][0] + bfs[f][1] * xin[r][1] + bfs[f][2] * xin[r][2] + bfs[f][3] * xin[r][3];
-      // sin / cos of 2 pi tt by the hardware's revolution-scaled sine and
-      // cosine on the fractional part (exact), as BF16 features
-      const float fr = __builtin_amdgcn_fractf(tt);
-      sn = __builtin_amdgcn_sinf(fr);
-      cs = __builtin_amdgcn_cosf(fr);
-    }
-    act[r * ALD + f] = (bf16)sn;
-    act[r * ALD + 64 + f] = (bf16)cs;
+  // thread (wavefront w, lane f) makes feature f of rows w, w + kFusedWaves,
+  // ...: row f of B is read once, the rows' inputs are wave-uniform reads, and
+  // the row limit is wave-uniform
+  const int f = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const float b0 = bfs[f][0], b1 = bfs[f][1], b2 = bfs[f][2], b3 = bfs[f][3];
+  const int rows_in = (int)(n - tile0 < ROWS ? n - tile0 : ROWS);  // rows r < rows_in exist
+#pragma unroll 4
+  for (int u = 0; u < ROWS / kFusedWaves; ++u) {
+    const int r = w + kFusedWaves * u;
+    // every row is evaluated (rows past n hold zero inputs) so that the
+    // unrolled rows' input reads are in flight together; those rows store 0
+    const float tt = b0 * xin[r][0] + b1 * xin[r][1] + b2 * xin[r][2] + b3 * xin[r][3];
+    // sin / cos of 2 pi tt by the hardware's revolution-scaled sine and
+    // cosine on the fractional part (exact), as BF16 features
+    const float fr = __builtin_amdgcn_fractf(tt);
+    const bool in = r < rows_in;
+    act[r * ALD + f] = (bf16)(in ? __builtin_amdgcn_sinf(fr) : 0.0f);
+    act[r * ALD + 64 + f] = (bf16)(in ? __builtin_amdgcn_cosf(fr) : 0.0f);
   }
 }
 
