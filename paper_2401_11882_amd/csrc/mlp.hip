@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
   } else {
     // row g pairs transmitter g / R with receiver g % R: the tile's first row
     // is divided once and its other rows step on from there (R >= 1, so at
-    // most ROWS steps, none where R is a multiple of ROWS)
+    // most ROWS steps; none where R is a multiple of ROWS, as row0 is a
+    // multiple of R)
     const long long g0 = a.row0 + tile0;
     const long long q0 = g0 / a.R, r0 = g0 % a.R;
     tile_features<ROWS>(act, xin, bfs, a.Bf, tile0, a.n, [&](long long row, int e) {
