@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
       for (int j = 0; j < 4; ++j) hw4[j] = *reinterpret_cast<const float4*>(&hws[c0 + 16 * j + 4 * (lane >> 4)]);
 #pragma unroll
       for (int i = 0; i < kRT; ++i) {
-        float t[4];
+        uint32_t t[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const bf16x4 h = relu_bf16x4(acc[i][j]);
@@ -302,9 +302,19 @@ __global__ __launch_bounds__(kFusedWaves * 64, 2) void k_mlp_fused(FusedArgs a) 
           p = fmaf((float)h[1], hw4[j].y, p);
           p = fmaf((float)h[2], hw4[j].z, p);
           p = fmaf((float)h[3], hw4[j].w, p);
-          t[j] = pair_sum32(pair_sum16(p));
+          t[j] = __float_as_uint(p);
         }
-        if (lane < 16) xin[16 * i + lane][wave] = (t[0] + t[1]) + (t[2] + t[3]);
+        // lanes 16 apart: swapping rows between tiles 0 and 1 (2 and 3)
+        // leaves tile 0's (2's) pair sums in rows 0 and 2, tile 1's (3's) in
+        // rows 1 and 3; lanes 32 apart: then row k holds tile k's sum
+        const auto a01 = __builtin_amdgcn_permlane16_swap(t[0], t[1], false, false);
+        const auto a23 = __builtin_amdgcn_permlane16_swap(t[2], t[3], false, false);
+        const float s01 = __uint_as_float(a01[0]) + __uint_as_float(a01[1]);
+        const float s23 = __uint_as_float(a23[0]) + __uint_as_float(a23[1]);
+        const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s01), __float_as_uint(s23), false, false);
+        // tiles (0, 1) and (2, 3), then the two pairs
+        const float v = pair_sum32(pair_sum16(__uint_as_float(b[0]) + __uint_as_float(b[1])));
+        if (lane < 16) xin[16 * i + lane][wave] = v;
       }
       break;
     }
